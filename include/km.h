@@ -1,0 +1,161 @@
+/*
+ * km.h -- C ABI of libkmaa: Anderson-accelerated Lloyd K-Means on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Zhang, Yao, Peng, Yu, Deng, "Fast K-Means Clustering with Anderson
+ * Acceleration" (arXiv 1805.10638).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments named X, C, C0, C_out, rho, rho_prev, rho_out are
+ *    DEVICE pointers (memory from hipMalloc or a framework allocator on the
+ *    context's device), row-major and contiguous.  The caller owns them; the
+ *    library never frees or retains them after the call returns.
+ *  - Scalar outputs (E, iters) and statistics structs are HOST pointers.
+ *  - X is N x d, stored as float32 (KM_X_F32) or as bfloat16 bit patterns
+ *    (KM_X_BF16, uint16 per element).  C, C0 and C_out are K x d float32.
+ *    Labels are int32 in [0, K).
+ *  - Limits: 1 <= K <= N, 1 <= d <= 256, K <= 4096, N < 2^31.  Violations
+ *    return KM_EINVAL (bad value) or KM_EUNSUPPORTED (beyond a limit).
+ *  - Every call is stream-ordered on the context's HIP stream and returns
+ *    after the results are complete (it synchronises that stream).
+ *  - Errors are reported by status code only; km_last_error() gives a
+ *    message for the last failing call on that context.  On error, outputs
+ *    are unspecified.  A context is not thread-safe.
+ */
+#ifndef KM_H
+#define KM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KM_OK = 0,               /* converged (exactly, or by the energy tolerance) */
+  KM_NOT_CONVERGED = 1,    /* max_iter reached; outputs hold the last accepted iterate */
+  KM_EINVAL = -1,          /* invalid argument */
+  KM_ENOMEM = -2,          /* device allocation failed */
+  KM_EDEVICE = -3,         /* HIP runtime error */
+  KM_EUNSUPPORTED = -4,    /* argument beyond a documented limit */
+  KM_ENONFINITE = -5       /* an energy evaluated to Inf/NaN */
+} km_status;
+
+typedef enum { KM_X_F32 = 0, KM_X_BF16 = 1 } km_xtype;
+
+/* Precision of the distance GEMM inside the assignment step.  Labels are the
+ * exact float64 argmin either way: rows whose best/second-best gap is within
+ * a rigorous rounding bound of the GEMM are re-checked with float64 direct
+ * differences. */
+typedef enum { KM_GEMM_F32 = 0, KM_GEMM_BF16 = 1 } km_prec;
+
+/* Solver flags (km_opts.flags). */
+#define KM_FLAG_FIXED_M        1u  /* keep m at m_init (classical fixed-m Anderson, Sec. 2.2) */
+#define KM_FLAG_LITERAL_RETURN 2u  /* return as soon as an assignment repeats, even for an
+                                      accelerated iterate (Algorithm 1 read literally) */
+
+#define KM_M_MAX_LIMIT 64          /* largest supported m_max */
+#define KM_TRACE_REC 80            /* doubles per trace record (see km_opts) */
+
+typedef struct km_ctx km_ctx;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL selects the device's null stream).  The context owns
+ * a workspace that grows on demand and is freed by km_destroy. */
+km_status km_create(int device, void *hip_stream, km_ctx **out);
+void km_destroy(km_ctx *ctx);
+
+/* Change the stream of an existing context. */
+km_status km_set_stream(km_ctx *ctx, void *hip_stream);
+
+/* Static string for a status code. */
+const char *km_status_str(int status);
+
+/* Message describing the last failure on `ctx` ("" if none). */
+const char *km_last_error(const km_ctx *ctx);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int km_version(void);
+
+/* Record HIP events around every assignment-kernel launch of kmeans_solve
+ * (1) or not (0, default).  Results appear in km_solve_stats.assign_ms. */
+km_status km_set_timing(km_ctx *ctx, int enable);
+
+typedef struct {
+  int64_t changed;         /* rows whose label differs from rho_prev (0 if rho_prev NULL) */
+  int64_t flagged_rows;    /* rows re-checked with float64 differences */
+  int32_t empty_clusters;  /* clusters with no sample (centroid kept, reading R9) */
+} km_g_stats;
+
+/*
+ * kmeans_g -- one application of the fixed-point map G of Sec. 2.1, Eq. (6).
+ *   rho   = Assignment-Step(X, C)            (Sec. 1, Eq. (3); lowest index on ties)
+ *   C_out = Update-Step(X, rho)              (Sec. 1, Eq. (4)); an empty cluster keeps C_j
+ *   *E    = sum_i ||x_i - c_{rho_i}||^2      (Sec. 1, Eq. (1)), energy of the INPUT C
+ * Arguments:
+ *   X [N x d] (xt), C [K x d] float32, rho_prev [N] int32 or NULL (only used
+ *   to count changed labels), rho [N] int32 out, C_out [K x d] float32 out
+ *   (must not alias C or X), E host double out, st host stats out or NULL.
+ */
+km_status kmeans_g(km_ctx *ctx, const void *X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                   const float *C, km_prec prec, const int32_t *rho_prev,
+                   int32_t *rho, float *C_out, double *E, km_g_stats *st);
+
+typedef struct {
+  double eps1;          /* dynamic-m shrink threshold (Sec. 3 default 0.02) */
+  double eps2;          /* dynamic-m grow threshold (Sec. 3 default 0.5) */
+  double ridge;         /* Tikhonov term of the normalised normal equations (1e-10) */
+  int32_t m_init;       /* initial m, clipped to m_max (Sec. 3 default 2) */
+  int32_t max_iter;     /* iteration cap (default 500) */
+  km_prec prec;         /* distance-GEMM precision (default KM_GEMM_F32) */
+  uint32_t flags;       /* KM_FLAG_* */
+  /* Optional step-by-step trace, device pointers, both may be NULL:
+   *   trace_C   [(max_iter + 1) x K x d] float32: candidate C^t at slot t.
+   *   trace_rec [(max_iter + 1) x KM_TRACE_REC] double, slot t holds
+   *     0 t, 1 E(candidate), 2 changed labels of candidate, 3 m after the
+   *     m-rule, 4 decision (0 Lloyd candidate kept, 1 accelerated kept,
+   *     2 rejected, 3 converged, 4 stopped by tol, 5 max_iter),
+   *     5 E(fall-back), 6 changed labels of fall-back, 7 accepted energy,
+   *     8 m_t, 9 columns used, 10 flagged rows, 16.. theta_1..theta_{m_t}. */
+  float *trace_C;
+  double *trace_rec;
+} km_opts;
+
+/* Fill `opt` with the defaults listed above. */
+void km_opts_default(km_opts *opt);
+
+typedef struct {
+  int32_t iters;           /* value of t at return */
+  int32_t accepted;        /* iterations that kept an accelerated candidate */
+  int32_t rejected;        /* iterations that fell back to the Lloyd iterate */
+  int32_t assign_passes;   /* assignment passes incl. the one of G(C0) */
+  int32_t m_final;         /* m at return */
+  int32_t assign_launches; /* timed candidate assignment launches (timing on) */
+  int64_t flagged_rows;    /* rows re-checked in float64, summed over passes */
+  double device_ms;        /* wall time of the call measured with HIP events */
+  double assign_ms;        /* summed duration of the timed assignment launches */
+} km_solve_stats;
+
+/*
+ * kmeans_solve -- Anderson-accelerated Lloyd iteration with dynamic m and
+ * the energy-decrease safeguard (Sec. 2.1, Sec. 2.2, Algorithm 1).
+ *   Starts from C0 [K x d] float32.  m_max (0..KM_M_MAX_LIMIT) bounds the
+ *   number of previous iterates; m_max = 0 is plain Lloyd.  tol >= 0 stops
+ *   when the accepted energy's relative decrease is at most tol (0 = run to
+ *   an exact fixed point).  opt may be NULL (defaults).
+ * Outputs: C_out [K x d] float32 (may alias C0), rho_out [N] int32, *E the
+ *   energy of C_out, *iters, *st (host, may be NULL).
+ * Returns KM_OK on convergence, KM_NOT_CONVERGED after max_iter iterations
+ * (outputs hold the last accepted iterate), or an error.
+ */
+km_status kmeans_solve(km_ctx *ctx, const void *X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                       const float *C0, int32_t m_max, double tol, const km_opts *opt,
+                       float *C_out, int32_t *rho_out, double *E, int32_t *iters,
+                       km_solve_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KM_H */

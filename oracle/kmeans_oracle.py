@@ -278,12 +278,15 @@ class SolveResult:
 def solve(X, C0, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
           eps1: float = EPS1, eps2: float = EPS2, m_init: int = M_INIT,
           fixed_m: bool = False, literal_return: bool = False,
-          replay=None, lam: float = RIDGE) -> SolveResult:
+          replay=None, stored=None, lam: float = RIDGE) -> SolveResult:
     """Anderson-accelerated Lloyd iteration with dynamic m (Algorithm 1).
 
     ``replay(t)`` may return a centroid array that replaces the candidate
     C^t at the start of iteration t (used to follow another implementation's
     iterates step by step); returning None keeps the oracle's own candidate.
+    ``stored(C)`` maps the fall-back iterate to the values another
+    implementation stores for it (e.g. float32 rounding) when replaying;
+    by default the fall-back is the float64 G^{t-1} itself.
     """
     X = _f64(X)
     C0 = _f64(C0)
@@ -336,7 +339,7 @@ def solve(X, C0, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
 
         if not C_is_lloyd and (same or E >= E1):
             # Revert to the Lloyd iterate (Sec. 2.1 safeguard; R2, R6)
-            C = G_prev.copy()
+            C = G_prev.copy() if stored is None else _f64(stored(G_prev)).reshape(k, d)
             a = assign(X, C)
             passes += 1
             P = a.rho
@@ -368,7 +371,8 @@ def solve(X, C0, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
         hist.push(G, F)
         mt = min(m, t)
         x_next, theta, used = hist.accelerate(mt, lam)
-        rec.update(mt=mt, used=used, theta=theta.tolist(), G=G.copy())
+        rec.update(mt=mt, used=used, theta=theta.tolist(), G=G.copy(),
+                   C_next=x_next.reshape(k, d).copy())
         trace.append(rec)
 
         E2, E1 = E1, E

@@ -6,15 +6,17 @@ the package does not load the library; the first call does, and fails loudly
 if the library has not been built.
 """
 
+import importlib
+
 __all__ = ["kmeans_g", "kmeans_solve", "Context", "KMError", "synth"]
+
+_LIB_NAMES = ("kmeans_g", "kmeans_solve", "Context", "KMError", "SolveStats", "GStats",
+              "load_library")
 
 
 def __getattr__(name):
-    if name in ("kmeans_g", "kmeans_solve", "Context", "KMError", "SolveStats",
-                "GStats", "kmeans_solve_batched", "load_library"):
-        from . import _lib
-        return getattr(_lib, name)
-    if name == "synth":
-        from . import synth
-        return synth
+    if name in _LIB_NAMES:
+        return getattr(importlib.import_module("._lib", __name__), name)
+    if name in ("synth", "build", "_lib"):
+        return importlib.import_module("." + name, __name__)
     raise AttributeError(name)

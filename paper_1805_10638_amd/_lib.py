@@ -1,0 +1,267 @@
+"""ctypes binding of libkmaa (include/km.h).
+
+Argument marshalling only: tensors are checked for device, dtype and layout,
+their data pointers and the current HIP stream are handed to the C ABI, and
+status codes become exceptions.  All arithmetic runs in the library's HIP
+kernels.  There is no fallback: if the library is missing or cannot be
+loaded, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmaa.so")
+
+KM_OK, KM_NOT_CONVERGED = 0, 1
+KM_EINVAL, KM_ENOMEM, KM_EDEVICE, KM_EUNSUPPORTED, KM_ENONFINITE = -1, -2, -3, -4, -5
+KM_X_F32, KM_X_BF16 = 0, 1
+KM_GEMM_F32, KM_GEMM_BF16 = 0, 1
+KM_FLAG_FIXED_M, KM_FLAG_LITERAL_RETURN = 1, 2
+KM_TRACE_REC = 80
+
+
+class KMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class _GStats(ct.Structure):
+    _fields_ = [("changed", ct.c_int64), ("flagged_rows", ct.c_int64),
+                ("empty_clusters", ct.c_int32)]
+
+
+class _Opts(ct.Structure):
+    _fields_ = [("eps1", ct.c_double), ("eps2", ct.c_double), ("ridge", ct.c_double),
+                ("m_init", ct.c_int32), ("max_iter", ct.c_int32), ("prec", ct.c_int),
+                ("flags", ct.c_uint32), ("trace_C", ct.c_void_p), ("trace_rec", ct.c_void_p)]
+
+
+class _SolveStats(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("accepted", ct.c_int32), ("rejected", ct.c_int32),
+                ("assign_passes", ct.c_int32), ("m_final", ct.c_int32),
+                ("assign_launches", ct.c_int32), ("flagged_rows", ct.c_int64),
+                ("device_ms", ct.c_double), ("assign_ms", ct.c_double)]
+
+
+@dataclass
+class GStats:
+    changed: int
+    flagged_rows: int
+    empty_clusters: int
+
+
+@dataclass
+class SolveStats:
+    iters: int
+    accepted: int
+    rejected: int
+    assign_passes: int
+    m_final: int
+    flagged_rows: int
+    device_ms: float
+    assign_ms: float
+    assign_launches: int
+    status: int
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libkmaa.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libkmaa.so not found at {path}; build it with "
+                           "`python -m paper_1805_10638_amd.build`")
+    lib = ct.CDLL(path)
+    vp, i32, i64, dbl = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_double
+    lib.km_create.argtypes = [ct.c_int, vp, ct.POINTER(vp)]
+    lib.km_create.restype = ct.c_int
+    lib.km_destroy.argtypes = [vp]
+    lib.km_destroy.restype = None
+    lib.km_set_stream.argtypes = [vp, vp]
+    lib.km_set_stream.restype = ct.c_int
+    lib.km_set_timing.argtypes = [vp, ct.c_int]
+    lib.km_set_timing.restype = ct.c_int
+    lib.km_status_str.argtypes = [ct.c_int]
+    lib.km_status_str.restype = ct.c_char_p
+    lib.km_last_error.argtypes = [vp]
+    lib.km_last_error.restype = ct.c_char_p
+    lib.km_version.argtypes = []
+    lib.km_version.restype = ct.c_int
+    lib.km_opts_default.argtypes = [ct.POINTER(_Opts)]
+    lib.km_opts_default.restype = None
+    lib.kmeans_g.argtypes = [vp, vp, ct.c_int, i64, i32, i32, vp, ct.c_int, vp, vp, vp,
+                             ct.POINTER(dbl), ct.POINTER(_GStats)]
+    lib.kmeans_g.restype = ct.c_int
+    lib.kmeans_solve.argtypes = [vp, vp, ct.c_int, i64, i32, i32, vp, i32, dbl,
+                                 ct.POINTER(_Opts), vp, vp, ct.POINTER(dbl), ct.POINTER(i32),
+                                 ct.POINTER(_SolveStats)]
+    lib.kmeans_solve.restype = ct.c_int
+    _lib = lib
+    return lib
+
+
+class Context:
+    """A libkmaa context bound to one device (workspace + stream)."""
+
+    def __init__(self, device: int | None = None):
+        self.lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ct.c_void_p()
+        st = self.lib.km_create(self.device, None, ct.byref(h))
+        if st != KM_OK:
+            raise KMError(st, "km_create failed: " + self.lib.km_status_str(st).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.km_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.km_set_stream(self.h, ct.c_void_p(s))
+
+    def set_timing(self, on: bool):
+        self.lib.km_set_timing(self.h, 1 if on else 0)
+
+    def _check(self, st: int, what: str, allow=(KM_OK,)):
+        if st in allow:
+            return
+        msg = self.lib.km_last_error(self.h).decode() or self.lib.km_status_str(st).decode()
+        raise KMError(st, f"{what}: {msg}")
+
+
+_ctx: dict[int, Context] = {}
+
+
+def _context(device: int) -> Context:
+    c = _ctx.get(device)
+    if c is None:
+        c = Context(device)
+        _ctx[device] = c
+    return c
+
+
+def _xtype(X: torch.Tensor) -> int:
+    if X.dtype == torch.float32:
+        return KM_X_F32
+    if X.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return KM_X_BF16
+    raise TypeError(f"X must be float32 or bfloat16 (got {X.dtype})")
+
+
+def _prec(p) -> int:
+    if p in ("f32", "fp32", KM_GEMM_F32, None):
+        return KM_GEMM_F32
+    if p in ("bf16", KM_GEMM_BF16):
+        return KM_GEMM_BF16
+    raise ValueError(f"unknown precision {p!r}")
+
+
+def _check_dev(t: torch.Tensor, name: str, device: int):
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def kmeans_g(X: torch.Tensor, C: torch.Tensor, prec="f32", rho_prev: torch.Tensor | None = None,
+             ctx: Context | None = None):
+    """One application of G (assignment then update).
+
+    Returns (rho int32 [N], C_out float32 [K,d], E float (energy of C), GStats)."""
+    dev = X.device.index
+    ctx = ctx or _context(dev)
+    _check_dev(X, "X", dev)
+    _check_dev(C, "C", dev)
+    if C.dtype != torch.float32:
+        raise TypeError("C must be float32")
+    N, d = X.shape
+    K = C.shape[0]
+    if C.shape[1] != d:
+        raise ValueError("C must be K x d")
+    rho = torch.empty(N, dtype=torch.int32, device=X.device)
+    C_out = torch.empty_like(C)
+    E = ct.c_double()
+    gs = _GStats()
+    if rho_prev is not None:
+        _check_dev(rho_prev, "rho_prev", dev)
+        if rho_prev.dtype != torch.int32:
+            raise TypeError("rho_prev must be int32")
+    ctx._bind_stream()
+    st = ctx.lib.kmeans_g(ctx.h, ct.c_void_p(X.data_ptr()), _xtype(X), N, d, K,
+                          ct.c_void_p(C.data_ptr()), _prec(prec),
+                          ct.c_void_p(rho_prev.data_ptr()) if rho_prev is not None else None,
+                          ct.c_void_p(rho.data_ptr()), ct.c_void_p(C_out.data_ptr()),
+                          ct.byref(E), ct.byref(gs))
+    ctx._check(st, "kmeans_g")
+    return rho, C_out, E.value, GStats(gs.changed, gs.flagged_rows, gs.empty_clusters)
+
+
+def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float = 1e-6,
+                 max_iter: int = 500, eps1: float = 0.02, eps2: float = 0.5, m_init: int = 2,
+                 prec="f32", fixed_m: bool = False, literal_return: bool = False,
+                 ridge: float = 1e-10, trace: bool = False, ctx: Context | None = None,
+                 out: tuple | None = None):
+    """Anderson-accelerated Lloyd K-Means (Algorithm 1).
+
+    Returns (C float32 [K,d], rho int32 [N], E, iters, SolveStats) and, with
+    ``trace=True``, a dict with the per-iteration candidates and records."""
+    dev = X.device.index
+    ctx = ctx or _context(dev)
+    _check_dev(X, "X", dev)
+    _check_dev(C0, "C0", dev)
+    if C0.dtype != torch.float32:
+        raise TypeError("C0 must be float32")
+    N, d = X.shape
+    K = C0.shape[0]
+    if out is None:
+        C = torch.empty_like(C0)
+        rho = torch.empty(N, dtype=torch.int32, device=X.device)
+    else:
+        C, rho = out
+    o = _Opts()
+    ctx.lib.km_opts_default(ct.byref(o))
+    o.eps1, o.eps2, o.ridge = eps1, eps2, ridge
+    o.m_init, o.max_iter, o.prec = m_init, max_iter, _prec(prec)
+    o.flags = (KM_FLAG_FIXED_M if fixed_m else 0) | (KM_FLAG_LITERAL_RETURN if literal_return else 0)
+    tr = None
+    if trace:
+        tr = {"C": torch.zeros((max_iter + 1, K, d), dtype=torch.float32, device=X.device),
+              "rec": torch.zeros((max_iter + 1, KM_TRACE_REC), dtype=torch.float64, device=X.device)}
+        o.trace_C = tr["C"].data_ptr()
+        o.trace_rec = tr["rec"].data_ptr()
+    E = ct.c_double()
+    it = ct.c_int32()
+    ss = _SolveStats()
+    ctx._bind_stream()
+    st = ctx.lib.kmeans_solve(ctx.h, ct.c_void_p(X.data_ptr()), _xtype(X), N, d, K,
+                              ct.c_void_p(C0.data_ptr()), m_max, tol, ct.byref(o),
+                              ct.c_void_p(C.data_ptr()), ct.c_void_p(rho.data_ptr()),
+                              ct.byref(E), ct.byref(it), ct.byref(ss))
+    ctx._check(st, "kmeans_solve", allow=(KM_OK, KM_NOT_CONVERGED))
+    stats = SolveStats(ss.iters, ss.accepted, ss.rejected, ss.assign_passes, ss.m_final,
+                       ss.flagged_rows, ss.device_ms, ss.assign_ms, ss.assign_launches, st)
+    if trace:
+        return C, rho, E.value, it.value, stats, tr
+    return C, rho, E.value, it.value, stats

@@ -1,0 +1,554 @@
+// C ABI of libkmaa (declared in include/km.h): argument checking, the
+// context and its workspace, and the launch sequence of the solver.
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/km.h"
+#include "km_launch.h"
+
+using namespace km;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Sizes that determine the workspace layout.
+struct Shape {
+  int64_t N = 0;
+  int d = 0, K = 0, cap = 0, bf = 0;
+  bool fits(const Shape& o) const {
+    return N >= o.N && d >= o.d && K >= o.K && cap >= o.cap && bf >= o.bf &&
+           (int64_t)K * d >= (int64_t)o.K * o.d;
+  }
+};
+
+}  // namespace
+
+struct km_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool timing = false;
+
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  Shape shape;
+
+  Ctl* ctl = nullptr;           // device
+  Ctl* ctl_host = nullptr;      // pinned host mirror
+  int* done_host = nullptr;     // pinned poll slots
+  double* scal_host = nullptr;  // pinned scalars
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::vector<hipEvent_t> tev;  // assignment timing pairs
+
+  // workspace carve-up
+  int* labels = nullptr;        // 3 x N
+  int* lrank = nullptr;         // N
+  int* perm = nullptr;          // N
+  int* blockcount = nullptr;    // nblk x K
+  int* counts = nullptr;        // K
+  int* seg_start = nullptr;     // K + 1
+  int* item_start = nullptr;    // K + 1
+  int* item_cluster = nullptr;  // max_items
+  double* e_part = nullptr;     // 2 x grid
+  double* partial = nullptr;    // max_items x d
+  double* G_last = nullptr;     // K x d
+  double* F_last = nullptr;     // K x d
+  double* ring_dF = nullptr;    // cap x K x d
+  double* ring_dG = nullptr;    // cap x K x d
+  double* gram = nullptr;       // cap x cap
+  double* dots = nullptr;       // fin_grid x 2 cap
+  double* e_out = nullptr;      // 1
+  float* C_cand = nullptr;      // K x d
+  float* C_fb = nullptr;        // K x d
+  float* C_tmp = nullptr;       // K x d (kmeans_g / prologue input copy)
+  float* nc_cand = nullptr;
+  float* nc_fb = nullptr;
+  float* nc_tmp = nullptr;
+  uint16_t* Cb_cand = nullptr;  // bf16 shadows (bf16 GEMM only)
+  uint16_t* Cb_fb = nullptr;
+  uint16_t* Cb_tmp = nullptr;
+  float* del_cand = nullptr;
+  float* del_fb = nullptr;
+  float* del_tmp = nullptr;
+  int grid_assign = 0, max_items = 0, nblk = 0, fin_grid = 0;
+};
+
+static km_status fail(km_ctx* c, km_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+static km_status hip_fail(km_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? KM_ENOMEM : KM_EDEVICE, m);
+}
+
+#define HIP_TRY(c, expr, where)                       \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return hip_fail(c, _e, where); \
+  } while (0)
+
+static bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+static km_status ensure_ws(km_ctx* c, const Shape& want) {
+  if (c->arena && c->shape.fits(want)) return KM_OK;
+  Shape s = want;
+  if (c->arena) {  // grow monotonically
+    s.N = s.N > c->shape.N ? s.N : c->shape.N;
+    s.d = s.d > c->shape.d ? s.d : c->shape.d;
+    s.K = s.K > c->shape.K ? s.K : c->shape.K;
+    s.cap = s.cap > c->shape.cap ? s.cap : c->shape.cap;
+    s.bf = s.bf > c->shape.bf ? s.bf : c->shape.bf;
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    HIP_TRY(c, hipFree(c->arena), "hipFree");
+    c->arena = nullptr;
+  }
+  const int64_t N = s.N;
+  const int64_t KD = (int64_t)s.K * s.d;
+  const int grid = assign_grid(N, 1, 0) > assign_grid(N, s.d, 0) ? assign_grid(N, 1, 0)
+                                                                  : assign_grid(N, s.d, 0);
+  const int max_items = update_max_items(N, s.K);
+  const int nblk = update_rank_blocks(N);
+  const int fin_grid = finalize_grid(s.K);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += up(bytes); return o; };
+  const size_t o_ctl = take(sizeof(Ctl));
+  const size_t o_lab = take(3 * N * 4);
+  const size_t o_lr = take(N * 4);
+  const size_t o_perm = take(N * 4);
+  const size_t o_bc = take((size_t)nblk * s.K * 4);
+  const size_t o_cnt = take((size_t)s.K * 4);
+  const size_t o_ss = take((size_t)(s.K + 1) * 4);
+  const size_t o_is = take((size_t)(s.K + 1) * 4);
+  const size_t o_ic = take((size_t)max_items * 4);
+  const size_t o_ep = take((size_t)2 * grid * 8);
+  const size_t o_pa = take((size_t)max_items * s.d * 8);
+  const size_t o_gl = take(KD * 8);
+  const size_t o_fl = take(KD * 8);
+  const size_t o_rf = take((size_t)s.cap * KD * 8);
+  const size_t o_rg = take((size_t)s.cap * KD * 8);
+  const size_t o_gr = take((size_t)s.cap * s.cap * 8 + 8);
+  const size_t o_dt = take((size_t)fin_grid * 2 * s.cap * 8 + 8);
+  const size_t o_eo = take(8);
+  const size_t o_cc = take(KD * 4);
+  const size_t o_cf = take(KD * 4);
+  const size_t o_ct = take(KD * 4);
+  const size_t o_nc = take((size_t)s.K * 4);
+  const size_t o_nf = take((size_t)s.K * 4);
+  const size_t o_nt = take((size_t)s.K * 4);
+  const size_t o_bcand = take(s.bf ? KD * 2 : 0);
+  const size_t o_bfb = take(s.bf ? KD * 2 : 0);
+  const size_t o_btmp = take(s.bf ? KD * 2 : 0);
+  const size_t o_dc = take(s.bf ? s.K * 4 : 0);
+  const size_t o_df = take(s.bf ? s.K * 4 : 0);
+  const size_t o_dtmp = take(s.bf ? s.K * 4 : 0);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, off);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->shape = Shape();
+    c->arena_bytes = 0;
+    return fail(c, KM_ENOMEM, "workspace allocation of " + std::to_string(off) + " bytes failed");
+  }
+  HIP_TRY(c, hipMemsetAsync(p, 0, off, c->stream), "hipMemsetAsync");
+  char* b = (char*)p;
+  c->arena = p;
+  c->arena_bytes = off;
+  c->shape = s;
+  c->ctl = (Ctl*)(b + o_ctl);
+  c->labels = (int*)(b + o_lab);
+  c->lrank = (int*)(b + o_lr);
+  c->perm = (int*)(b + o_perm);
+  c->blockcount = (int*)(b + o_bc);
+  c->counts = (int*)(b + o_cnt);
+  c->seg_start = (int*)(b + o_ss);
+  c->item_start = (int*)(b + o_is);
+  c->item_cluster = (int*)(b + o_ic);
+  c->e_part = (double*)(b + o_ep);
+  c->partial = (double*)(b + o_pa);
+  c->G_last = (double*)(b + o_gl);
+  c->F_last = (double*)(b + o_fl);
+  c->ring_dF = (double*)(b + o_rf);
+  c->ring_dG = (double*)(b + o_rg);
+  c->gram = (double*)(b + o_gr);
+  c->dots = (double*)(b + o_dt);
+  c->e_out = (double*)(b + o_eo);
+  c->C_cand = (float*)(b + o_cc);
+  c->C_fb = (float*)(b + o_cf);
+  c->C_tmp = (float*)(b + o_ct);
+  c->nc_cand = (float*)(b + o_nc);
+  c->nc_fb = (float*)(b + o_nf);
+  c->nc_tmp = (float*)(b + o_nt);
+  c->Cb_cand = s.bf ? (uint16_t*)(b + o_bcand) : nullptr;
+  c->Cb_fb = s.bf ? (uint16_t*)(b + o_bfb) : nullptr;
+  c->Cb_tmp = s.bf ? (uint16_t*)(b + o_btmp) : nullptr;
+  c->del_cand = s.bf ? (float*)(b + o_dc) : nullptr;
+  c->del_fb = s.bf ? (float*)(b + o_df) : nullptr;
+  c->del_tmp = s.bf ? (float*)(b + o_dtmp) : nullptr;
+  c->grid_assign = grid;
+  c->max_items = max_items;
+  c->nblk = nblk;
+  c->fin_grid = fin_grid;
+  return KM_OK;
+}
+
+static km_status check_common(km_ctx* c, const void* X, int xt, int64_t N, int32_t d, int32_t K,
+                              int prec) {
+  if (!c) return KM_EINVAL;
+  c->err.clear();
+  if (N < 1 || d < 1 || K < 1) return fail(c, KM_EINVAL, "N, d and K must be positive");
+  if (K > N) return fail(c, KM_EINVAL, "K must not exceed N");
+  if (xt != KM_X_F32 && xt != KM_X_BF16) return fail(c, KM_EINVAL, "unknown X type");
+  if (prec != KM_GEMM_F32 && prec != KM_GEMM_BF16) return fail(c, KM_EINVAL, "unknown precision");
+  if (d > kMaxD) return fail(c, KM_EUNSUPPORTED, "d > 256 is not supported");
+  if (K > kMaxK) return fail(c, KM_EUNSUPPORTED, "K > 4096 is not supported");
+  if (N >= ((int64_t)1 << 31)) return fail(c, KM_EUNSUPPORTED, "N >= 2^31 is not supported");
+  if (!is_device_ptr(X)) return fail(c, KM_EINVAL, "X is not a device pointer");
+  return KM_OK;
+}
+
+extern "C" {
+
+int km_version(void) { return 10000; }
+
+const char* km_status_str(int s) {
+  switch (s) {
+    case KM_OK: return "ok";
+    case KM_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case KM_EINVAL: return "invalid argument";
+    case KM_ENOMEM: return "out of device memory";
+    case KM_EDEVICE: return "HIP runtime error";
+    case KM_EUNSUPPORTED: return "unsupported argument";
+    case KM_ENONFINITE: return "non-finite energy";
+  }
+  return "unknown status";
+}
+
+const char* km_last_error(const km_ctx* c) { return c ? c->err.c_str() : ""; }
+
+km_status km_create(int device, void* stream, km_ctx** out) {
+  if (!out) return KM_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return KM_EINVAL;
+  }
+  if (hipSetDevice(device) != hipSuccess) return KM_EDEVICE;
+  km_ctx* c = new km_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  bool ok = hipHostMalloc((void**)&c->ctl_host, sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&c->done_host, 2 * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&c->scal_host, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+            hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->poll_ev[1], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess;
+  if (!ok) {
+    km_destroy(c);
+    return KM_EDEVICE;
+  }
+  *out = c;
+  return KM_OK;
+}
+
+void km_destroy(km_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->arena) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->arena);
+  }
+  if (c->ctl_host) (void)hipHostFree(c->ctl_host);
+  if (c->done_host) (void)hipHostFree(c->done_host);
+  if (c->scal_host) (void)hipHostFree(c->scal_host);
+  for (hipEvent_t e : c->poll_ev) if (e) (void)hipEventDestroy(e);
+  if (c->t0) (void)hipEventDestroy(c->t0);
+  if (c->t1) (void)hipEventDestroy(c->t1);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+km_status km_set_stream(km_ctx* c, void* stream) {
+  if (!c) return KM_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return KM_OK;
+}
+
+km_status km_set_timing(km_ctx* c, int enable) {
+  if (!c) return KM_EINVAL;
+  c->timing = enable != 0;
+  return KM_OK;
+}
+
+void km_opts_default(km_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->eps1 = 0.02;
+  o->eps2 = 0.5;
+  o->ridge = 1e-10;
+  o->m_init = 2;
+  o->max_iter = 500;
+  o->prec = KM_GEMM_F32;
+  o->flags = 0;
+  o->trace_C = nullptr;
+  o->trace_rec = nullptr;
+}
+
+km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                   const float* C, km_prec prec, const int32_t* rho_prev, int32_t* rho, float* C_out,
+                   double* E, km_g_stats* st) {
+  km_status s = check_common(c, X, xt, N, d, K, prec);
+  if (s != KM_OK) return s;
+  if (!E) return fail(c, KM_EINVAL, "E must be a host pointer");
+  if (!is_device_ptr(C) || !is_device_ptr(rho) || !is_device_ptr(C_out))
+    return fail(c, KM_EINVAL, "C, rho and C_out must be device pointers");
+  if (rho_prev && !is_device_ptr(rho_prev)) return fail(c, KM_EINVAL, "rho_prev must be a device pointer");
+  const size_t xbytes = (size_t)N * d * (xt == KM_X_BF16 ? 2 : 4);
+  const size_t cbytes = (size_t)K * d * 4;
+  if (overlap(C_out, cbytes, C, cbytes) || overlap(C_out, cbytes, X, xbytes) ||
+      overlap(rho, (size_t)N * 4, X, xbytes) || overlap(rho, (size_t)N * 4, C_out, cbytes))
+    return fail(c, KM_EINVAL, "outputs must not alias the inputs");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  Shape want;
+  want.N = N; want.d = d; want.K = K; want.cap = 0; want.bf = prec == KM_GEMM_BF16;
+  s = ensure_ws(c, want);
+  if (s != KM_OK) return s;
+  hipStream_t st_ = c->stream;
+  const bool gbf = prec == KM_GEMM_BF16;
+
+  HIP_TRY(c, hipMemsetAsync(c->ctl, 0, sizeof(Ctl), st_), "hipMemsetAsync");
+  HIP_TRY(c, launch_prep(C, K, d, c->nc_tmp, gbf ? c->Cb_tmp : nullptr, gbf ? c->del_tmp : nullptr, st_),
+          "prep");
+  AssignArgs a{};
+  a.X = X; a.N = N; a.d = d; a.K = K; a.C = C; a.nc = c->nc_tmp;
+  a.Cb = gbf ? c->Cb_tmp : nullptr; a.delta = gbf ? c->del_tmp : nullptr;
+  a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->e_part; a.ctl = c->ctl;
+  a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
+  HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
+  const int grid = assign_grid(N, d, gbf);
+  HIP_TRY(c, launch_reduce_energy(c->e_part, grid, c->e_out, st_), "energy");
+  UpdateArgs u{};
+  u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
+  u.lab = rho; u.lab_from_ctl = 0; u.lrank = c->lrank; u.blockcount = c->blockcount;
+  u.counts = c->counts; u.seg_start = c->seg_start; u.item_start = c->item_start;
+  u.item_cluster = c->item_cluster; u.perm = c->perm; u.partial = c->partial;
+  u.max_items = update_max_items(N, K); u.ctl = c->ctl; u.gated = 0;
+  HIP_TRY(c, launch_update_sums(u, st_), "update");
+  FinalizeArgs f{};
+  f.d = d; f.K = K; f.cap = 0; f.partial = c->partial; f.item_start = c->item_start;
+  f.counts = c->counts; f.C_in = C; f.C_out = C_out; f.ctl = c->ctl; f.mode = kFinG;
+  HIP_TRY(c, launch_finalize(f, st_), "finalize");
+  HIP_TRY(c, hipMemcpyAsync(c->scal_host, c->e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
+  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
+  HIP_TRY(c, hipStreamSynchronize(st_), "hipStreamSynchronize");
+  *E = c->scal_host[0];
+  if (st) {
+    st->changed = rho_prev ? (int64_t)c->ctl_host->cnt_changed[0] : 0;
+    st->flagged_rows = (int64_t)c->ctl_host->cnt_flagged[0];
+    st->empty_clusters = c->ctl_host->empty;
+  }
+  if (!isfinite(*E)) return fail(c, KM_ENONFINITE, "energy is not finite");
+  return KM_OK;
+}
+
+km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                       const float* C0, int32_t m_max, double tol, const km_opts* opt_in,
+                       float* C_out, int32_t* rho_out, double* E, int32_t* iters,
+                       km_solve_stats* st) {
+  km_opts opt;
+  if (opt_in) opt = *opt_in; else km_opts_default(&opt);
+  km_status s = check_common(c, X, xt, N, d, K, opt.prec);
+  if (s != KM_OK) return s;
+  if (m_max < 0 || m_max > KM_M_MAX_LIMIT) return fail(c, KM_EINVAL, "m_max must be in [0, 64]");
+  if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
+  if (opt.max_iter < 1) return fail(c, KM_EINVAL, "max_iter must be >= 1");
+  if (opt.m_init < 0) return fail(c, KM_EINVAL, "m_init must be >= 0");
+  if (!(opt.ridge >= 0.0) || !isfinite(opt.eps1) || !isfinite(opt.eps2))
+    return fail(c, KM_EINVAL, "eps1, eps2 and ridge must be finite (ridge >= 0)");
+  if (!E || !iters) return fail(c, KM_EINVAL, "E and iters must be host pointers");
+  if (!is_device_ptr(C0) || !is_device_ptr(C_out) || !is_device_ptr(rho_out))
+    return fail(c, KM_EINVAL, "C0, C_out and rho_out must be device pointers");
+  if (opt.trace_C && !is_device_ptr(opt.trace_C)) return fail(c, KM_EINVAL, "trace_C must be a device pointer");
+  if (opt.trace_rec && !is_device_ptr(opt.trace_rec))
+    return fail(c, KM_EINVAL, "trace_rec must be a device pointer");
+  const size_t xbytes = (size_t)N * d * (xt == KM_X_BF16 ? 2 : 4);
+  const size_t cbytes = (size_t)K * d * 4;
+  if (overlap(C_out, cbytes, X, xbytes) || overlap(rho_out, (size_t)N * 4, X, xbytes) ||
+      overlap(rho_out, (size_t)N * 4, C_out, cbytes) || overlap(rho_out, (size_t)N * 4, C0, cbytes))
+    return fail(c, KM_EINVAL, "outputs must not alias X or each other");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  const bool gbf = opt.prec == KM_GEMM_BF16;
+  Shape want;
+  want.N = N; want.d = d; want.K = K; want.cap = m_max; want.bf = gbf;
+  s = ensure_ws(c, want);
+  if (s != KM_OK) return s;
+  hipStream_t q = c->stream;
+  const bool xbf = xt == KM_X_BF16;
+  const int cap = m_max;
+
+  // controller state
+  Ctl h;
+  memset(&h, 0, sizeof(h));
+  h.m = opt.m_init < m_max ? opt.m_init : m_max;
+  h.cand_is_lloyd = 1;
+  h.lab_prev = 0; h.lab_cand = 1; h.lab_fb = 2;
+  h.max_iter = opt.max_iter;
+  h.m_max = m_max;
+  h.flags = (int32_t)opt.flags;
+  h.eps1 = opt.eps1; h.eps2 = opt.eps2; h.tol = tol; h.ridge = opt.ridge;
+  h.E1 = HUGE_VAL; h.E2 = HUGE_VAL;
+  h.assign_passes = 1;
+  *c->ctl_host = h;
+  HIP_TRY(c, hipEventRecord(c->t0, q), "hipEventRecord");
+  HIP_TRY(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
+
+  // prologue: P^0 = Assign(C^0), G^0 = Update(P^0), F^0 = G^0 - C^0, C^1 = G^0
+  HIP_TRY(c, hipMemcpyAsync(c->C_tmp, C0, cbytes, hipMemcpyDeviceToDevice, q), "copy C0");
+  HIP_TRY(c, launch_prep(c->C_tmp, K, d, c->nc_tmp, gbf ? c->Cb_tmp : nullptr,
+                         gbf ? c->del_tmp : nullptr, q), "prep");
+  AssignArgs a{};
+  a.X = X; a.N = N; a.d = d; a.K = K; a.C = c->C_tmp; a.nc = c->nc_tmp;
+  a.Cb = gbf ? c->Cb_tmp : nullptr; a.delta = gbf ? c->del_tmp : nullptr;
+  a.lab = c->labels; a.lab_prev = nullptr; a.e_part = c->e_part; a.ctl = c->ctl;
+  a.xbf16 = xbf; a.gemm_bf16 = gbf;
+  HIP_TRY(c, launch_assign(a, kRolePlain, q), "assignment");
+  UpdateArgs u{};
+  u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xbf;
+  u.lab = c->labels; u.lab_from_ctl = 1; u.lrank = c->lrank; u.blockcount = c->blockcount;
+  u.counts = c->counts; u.seg_start = c->seg_start; u.item_start = c->item_start;
+  u.item_cluster = c->item_cluster; u.perm = c->perm; u.partial = c->partial;
+  u.max_items = update_max_items(N, K); u.ctl = c->ctl; u.gated = 1;
+  HIP_TRY(c, launch_update_sums(u, q), "update");
+  FinalizeArgs f{};
+  f.d = d; f.K = K; f.cap = cap; f.partial = c->partial; f.item_start = c->item_start;
+  f.counts = c->counts; f.C_in = c->C_tmp; f.C_out = nullptr;
+  f.C_cand = c->C_cand; f.C_cand_w = c->C_cand; f.nc_cand = c->nc_cand;
+  f.C_fb = c->C_fb; f.nc_fb = c->nc_fb;
+  f.Cb_cand = gbf ? c->Cb_cand : nullptr; f.delta_cand = gbf ? c->del_cand : nullptr;
+  f.Cb_fb = gbf ? c->Cb_fb : nullptr; f.delta_fb = gbf ? c->del_fb : nullptr;
+  f.G_last = c->G_last; f.F_last = c->F_last; f.ring_dF = c->ring_dF; f.ring_dG = c->ring_dG;
+  f.dots = c->dots; f.ctl = c->ctl; f.mode = kFinInit;
+  HIP_TRY(c, launch_finalize(f, q), "finalize");
+  // counters of the first candidate pass start at zero
+  HIP_TRY(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
+
+  // per-iteration launch sequence
+  const int grid = assign_grid(N, d, gbf);
+  AssignArgs ac = a;
+  ac.C = c->C_cand; ac.nc = c->nc_cand; ac.Cb = gbf ? c->Cb_cand : nullptr;
+  ac.delta = gbf ? c->del_cand : nullptr; ac.e_part = c->e_part;
+  AssignArgs af = a;
+  af.C = c->C_fb; af.nc = c->nc_fb; af.Cb = gbf ? c->Cb_fb : nullptr;
+  af.delta = gbf ? c->del_fb : nullptr; af.e_part = c->e_part + grid;
+  CtlArgs k1{};
+  k1.ctl = c->ctl; k1.e_part = c->e_part; k1.n_part = grid; k1.stage = 1; k1.C_cand = c->C_cand;
+  k1.K = K; k1.d = d; k1.trace_C = opt.trace_C; k1.trace_rec = opt.trace_rec;
+  CtlArgs k2 = k1;
+  k2.e_part = c->e_part + grid; k2.stage = 2; k2.trace_C = nullptr;
+  FinalizeArgs fi = f;
+  fi.mode = kFinIter; fi.C_in = nullptr; fi.C_cand_w = nullptr;
+  SolveArgs sa{};
+  sa.ctl = c->ctl; sa.dots = c->dots; sa.n_dots = c->fin_grid > 0 ? finalize_grid(K) : 0;
+  sa.gram = c->gram; sa.cap = cap; sa.trace_rec = opt.trace_rec;
+  CombineArgs cb{};
+  cb.ctl = c->ctl; cb.G_last = c->G_last; cb.ring_dG = c->ring_dG; cb.K = K; cb.d = d; cb.cap = cap;
+  cb.C_cand = c->C_cand; cb.nc_cand = c->nc_cand; cb.Cb_cand = gbf ? c->Cb_cand : nullptr;
+  cb.delta_cand = gbf ? c->del_cand : nullptr;
+
+  if (c->timing && (int)c->tev.size() < 2 * opt.max_iter) {
+    while ((int)c->tev.size() < 2 * opt.max_iter) {
+      hipEvent_t e;
+      HIP_TRY(c, hipEventCreate(&e), "hipEventCreate");
+      c->tev.push_back(e);
+    }
+  }
+
+  int launched = 0;
+  bool finished = false;
+  while (launched < opt.max_iter && !finished) {
+    const int it = launched;
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->tev[2 * it], q), "hipEventRecord");
+    HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->tev[2 * it + 1], q), "hipEventRecord");
+    HIP_TRY(c, launch_controller(k1, q), "controller");
+    HIP_TRY(c, launch_assign(af, kRoleFallback, q), "assignment");
+    HIP_TRY(c, launch_controller(k2, q), "controller");
+    HIP_TRY(c, launch_update_sums(u, q), "update");
+    HIP_TRY(c, launch_finalize(fi, q), "finalize");
+    HIP_TRY(c, launch_ls_solve(sa, q), "least squares");
+    HIP_TRY(c, launch_combine(cb, q), "combine");
+    HIP_TRY(c, hipMemcpyAsync(&c->done_host[it & 1], &c->ctl->done, sizeof(int),
+                              hipMemcpyDeviceToHost, q), "poll copy");
+    HIP_TRY(c, hipEventRecord(c->poll_ev[it & 1], q), "hipEventRecord");
+    if (it >= 1) {
+      HIP_TRY(c, hipEventSynchronize(c->poll_ev[(it - 1) & 1]), "hipEventSynchronize");
+      if (c->done_host[(it - 1) & 1]) finished = true;
+    }
+    ++launched;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, q), "copy ctl");
+  HIP_TRY(c, hipStreamSynchronize(q), "hipStreamSynchronize");
+  Ctl r = *c->ctl_host;
+  if (!r.done) return fail(c, KM_EDEVICE, "solver did not reach a final state");
+  const float* Cres = r.acc_src == 1 ? c->C_fb : c->C_cand;
+  HIP_TRY(c, hipMemcpyAsync(C_out, Cres, cbytes, hipMemcpyDeviceToDevice, q), "copy C");
+  HIP_TRY(c, hipMemcpyAsync(rho_out, c->labels + (size_t)r.lab_prev * N, (size_t)N * 4,
+                            hipMemcpyDeviceToDevice, q), "copy rho");
+  HIP_TRY(c, hipEventRecord(c->t1, q), "hipEventRecord");
+  HIP_TRY(c, hipStreamSynchronize(q), "hipStreamSynchronize");
+  *E = r.E_acc;
+  *iters = r.t;
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->iters = r.t;
+    st->accepted = r.accepted;
+    st->rejected = r.rejected;
+    st->assign_passes = r.assign_passes;
+    st->m_final = r.m;
+    st->flagged_rows = (int64_t)r.flagged_total;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->t0, c->t1) == hipSuccess) st->device_ms = ms;
+    if (c->timing) {
+      double sum = 0.0;
+      int n = 0;
+      for (int it = 0; it < r.t && it < launched; ++it) {
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, c->tev[2 * it], c->tev[2 * it + 1]) == hipSuccess) {
+          sum += e;
+          ++n;
+        }
+      }
+      st->assign_ms = sum;
+      st->assign_launches = n;
+    }
+  }
+  if (r.status == KM_ENONFINITE) return fail(c, KM_ENONFINITE, "energy is not finite");
+  return (km_status)r.status;
+}
+
+}  // extern "C"

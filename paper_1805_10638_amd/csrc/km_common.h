@@ -1,0 +1,78 @@
+// Shared device-side definitions of libkmaa (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace km {
+
+constexpr int kWave = 64;
+constexpr int kMaxK = 4096;          // labels per LDS histogram row in the rank kernel
+constexpr int kMaxD = 256;           // register-resident sample rows in the assignment
+constexpr int kMaxM = 64;            // Anderson history bound
+constexpr int kRankRows = 4096;      // rows per block of the counting sort
+constexpr int kSegRows = 512;        // rows per work item of the segmented sum
+constexpr int kTraceRec = 80;        // doubles per trace record
+
+// Roles of an assignment launch.
+enum Role : int {
+  kRolePlain = 0,      // stand-alone G(C): explicit label pointers, no gating
+  kRoleCand = 1,       // candidate C^t of an iteration
+  kRoleFallback = 2,   // Lloyd fall-back iterate, runs only when ctl->reject
+};
+
+// Decision codes written to trace records.
+enum Decision : int {
+  kDecLloyd = 0, kDecAccepted = 1, kDecRejected = 2, kDecConverged = 3,
+  kDecTol = 4, kDecMaxIter = 5,
+};
+
+// Solver state, resident in device memory for the whole solve.  Written only
+// by the single-workgroup controller kernels (and counters by atomics).
+struct Ctl {
+  int32_t t;               // current iteration (0 during the prologue)
+  int32_t done;            // 1 once the solve has finished
+  int32_t status;          // km_status at finish
+  int32_t m;               // current m of the dynamic rule
+  int32_t cand_is_lloyd;   // candidate C^t equals the Lloyd iterate
+  int32_t reject;          // candidate of this iteration rejected
+  int32_t lab_prev;        // label buffer (0..2) of the accepted P^{t-1}
+  int32_t lab_cand;        // label buffer of the candidate's assignment
+  int32_t lab_fb;          // label buffer of the fall-back assignment
+  int32_t acc_src;         // accepted centroids: 0 candidate buffer, 1 fall-back buffer
+  int32_t hist_len;        // valid history differences
+  int32_t hist_head;       // ring slot of the newest difference
+  int32_t mt;              // m_t used this iteration
+  int32_t used;            // columns that entered the least squares
+  int32_t accepted, rejected, assign_passes, max_iter;
+  int32_t m_max, flags;
+  int32_t total_items;     // work items of the segmented sum
+  int32_t empty;           // empty clusters of the last update
+  double eps1, eps2, tol, ridge;
+  double E1, E2;           // accepted energies E^{t-1}, E^{t-2}
+  double E_cand, E_fb, E_acc;
+  unsigned long long cnt_changed[2];   // [candidate/plain, fall-back]
+  unsigned long long cnt_flagged[2];
+  unsigned long long flagged_total;
+  double theta[kMaxM];
+};
+
+// ---------------------------------------------------------------------------
+// Wave helpers (fixed reduction order, hence deterministic)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ __forceinline__ unsigned popc64(unsigned long long m) { return __popcll(m); }
+
+}  // namespace km

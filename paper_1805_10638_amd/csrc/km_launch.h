@@ -1,0 +1,123 @@
+// Host-side launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "km_common.h"
+
+namespace km {
+
+// ----- assignment (Sec. 1, Eq. (3)) fused with the energy (Eq. (1)) -----
+struct AssignArgs {
+  const void* X;          // N x d rows, float32 or bfloat16 bits
+  int64_t N;
+  int d, K;
+  const float* C;         // K x d float32 centroids
+  const float* nc;        // K squared norms of C (float32)
+  const uint16_t* Cb;     // K x d bfloat16 shadow of C (bf16 GEMM only)
+  const float* delta;     // K norms ||c_j - bf16(c_j)|| (bf16 GEMM only)
+  int* lab;               // label buffers: 3 x N (solver roles) or N (plain role)
+  const int* lab_prev;    // plain role: labels to count changes against, or null
+  double* e_part;         // per-workgroup energy partials
+  Ctl* ctl;
+  int xbf16;              // X stored as bfloat16
+  int gemm_bf16;          // distance GEMM in bfloat16
+};
+int assign_grid(int64_t N, int d, int gemm_bf16);   // workgroups of one launch
+hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s);
+
+// ||c_j||^2 (and the bfloat16 shadow with its error norms when Cb != null).
+hipError_t launch_prep(const float* C, int K, int d, float* nc, uint16_t* Cb, float* delta,
+                       hipStream_t s);
+
+// ----- update step (Sec. 1, Eq. (4)): counting sort + segmented sum -----
+struct UpdateArgs {
+  const void* X;
+  int64_t N;
+  int d, K, xbf16;
+  int* lab;               // label buffers base (3 x N) or the labels themselves
+  int lab_from_ctl;       // 1: labels = lab + ctl->lab_prev * N
+  int* lrank;             // N
+  int* blockcount;        // nblk x K, overwritten with per-block offsets
+  int* counts;            // K
+  int* seg_start;         // K + 1
+  int* item_start;        // K + 1
+  int* item_cluster;      // max_items
+  int* perm;              // N
+  double* partial;        // max_items x d
+  int max_items;
+  Ctl* ctl;
+  int gated;              // 1: skip when ctl->done
+};
+int update_max_items(int64_t N, int K);
+int update_rank_blocks(int64_t N);
+hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s);
+
+// Finalisation of the means and, in the solver, the residual/history push.
+enum FinMode : int { kFinG = 0, kFinInit = 1, kFinIter = 2 };
+struct FinalizeArgs {
+  int d, K, cap;          // cap = m_max (history ring capacity)
+  const double* partial;
+  const int* item_start;
+  const int* counts;
+  const float* C_in;      // kFinG / kFinInit: centroids G was applied to
+  float* C_out;           // kFinG: output means
+  // solver buffers
+  const float* C_cand;
+  float* C_cand_w;        // kFinInit writes C^1 here
+  float* nc_cand;
+  float* C_fb;            // fall-back iterate fl32(G^t), read as C^t when acc_src == 1
+  float* nc_fb;
+  uint16_t* Cb_cand; float* delta_cand;   // bf16 shadows (may be null)
+  uint16_t* Cb_fb; float* delta_fb;
+  double* G_last;         // K x d
+  double* F_last;         // K x d
+  double* ring_dF;        // cap x K x d
+  double* ring_dG;        // cap x K x d
+  double* dots;           // per-workgroup partial inner products (2 x cap each)
+  Ctl* ctl;
+  FinMode mode;
+};
+int finalize_grid(int K);
+hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s);
+
+// ----- controller and Anderson step (Sec. 2.1, Sec. 2.2, Algorithm 1) -----
+struct CtlArgs {
+  Ctl* ctl;
+  const double* e_part;   // partials of the pass being decided
+  int n_part;
+  int stage;              // 1: after the candidate pass, 2: after the fall-back pass
+  const float* C_cand;    // for the trace
+  int K, d;
+  float* trace_C;
+  double* trace_rec;
+};
+hipError_t launch_controller(const CtlArgs& c, hipStream_t s);
+
+struct SolveArgs {
+  Ctl* ctl;
+  const double* dots;
+  int n_dots;             // workgroups of the finalize launch
+  double* gram;           // cap x cap
+  int cap;
+  double* trace_rec;
+};
+hipError_t launch_ls_solve(const SolveArgs& a, hipStream_t s);
+
+struct CombineArgs {
+  Ctl* ctl;
+  const double* G_last;
+  const double* ring_dG;
+  int K, d, cap;
+  float* C_cand;
+  float* nc_cand;
+  uint16_t* Cb_cand;
+  float* delta_cand;
+};
+hipError_t launch_combine(const CombineArgs& a, hipStream_t s);
+
+// Plain energy reduction for stand-alone G(C): sum of partials in fixed order.
+hipError_t launch_reduce_energy(const double* e_part, int n, double* out, hipStream_t s);
+
+}  // namespace km

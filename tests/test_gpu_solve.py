@@ -1,0 +1,188 @@
+"""GPU parity of the full solver (Algorithm 1) against the FP64 oracle.
+
+Three tiers:
+  * step by step: the oracle replays every candidate C^t the GPU evaluated
+    and must take the same decisions, m, m_t and theta, and produce the same
+    next candidate;
+  * end to end from the same C^0 (final energy, centroids, labels, counts);
+  * invariants: m_max = 0 is Lloyd, exact convergence is a fixed point of G,
+    bitwise determinism, max_iter returns the last accepted iterate.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import kmeans_oracle as ko
+from paper_1805_10638_amd import synth
+
+from helpers import centroid_errors, dev, x_tensor, x_values
+
+pytestmark = pytest.mark.gpu
+
+DEC = {"lloyd": 0, "accepted": 1, "rejected": 2, "converged": 3}
+
+
+def _km():
+    import paper_1805_10638_amd as km
+    return km
+
+
+def _labels_match(rho_gpu, X64, C64):
+    a = ko.assign(X64, C64)
+    mism = np.flatnonzero(a.rho != rho_gpu)
+    assert np.all(a.near_tie[mism]), f"{(~a.near_tie[mism]).sum()} label mismatches"
+    return mism.size
+
+
+def lockstep(X, C0, m_max, tol, max_iter=500, **kw):
+    km = _km()
+    C, rho, E, iters, st, tr = km.kmeans_solve(x_tensor(X), dev(C0), m_max=m_max, tol=tol,
+                                               max_iter=max_iter, trace=True, **kw)
+    Ctr = tr["C"].cpu().numpy().astype(np.float64)
+    rec = tr["rec"].cpu().numpy()
+    X64 = x_values(X)
+    oracle_kw = {}
+    if kw.get("fixed_m"):
+        oracle_kw["fixed_m"] = True
+    if "m_init" in kw:
+        oracle_kw["m_init"] = kw["m_init"]
+    res = ko.solve(X64, C0.astype(np.float64), m_max=m_max, tol=tol, max_iter=max_iter,
+                   replay=lambda t: Ctr[t] if t <= iters else None,
+                   stored=lambda G: G.astype(np.float32), **oracle_kw)
+    assert res.iters == iters, (res.iters, iters)
+    near_decisions = 0
+    for r in res.trace:
+        t = r["t"]
+        g = rec[t]
+        assert g[0] == t
+        assert g[1] == pytest.approx(r["E_cand"], rel=1e-9)
+        assert int(g[2]) == r["changed_cand"]
+        if r["decision"] == "converged":
+            assert int(g[4]) == 3
+            continue
+        E1 = rec[t - 1][7] if t > 1 else math.inf
+        if math.isfinite(E1) and abs(r["E_cand"] - E1) < 1e-6 * E1:
+            near_decisions += 1
+        assert int(g[3]) == r["m"], (t, g[3], r["m"])
+        assert int(g[4]) == DEC[r["decision"]], (t, g[4], r["decision"])
+        assert g[7] == pytest.approx(r["E_acc"], rel=1e-9)
+        if "mt" in r:
+            assert int(g[8]) == r["mt"] and int(g[9]) == r["used"]
+            th_o = np.array(r["theta"])
+            th_g = g[16:16 + r["mt"]]
+            # norm-wise relative agreement of the least-squares solution
+            assert np.linalg.norm(th_g - th_o) <= 1e-6 * np.linalg.norm(th_o) + 1e-12, (t, th_g, th_o)
+            if t + 1 <= iters:
+                err = centroid_errors(Ctr[t + 1], r["C_next"], X64)
+                assert err.max() <= 1e-5, (t, err.max())
+    return C.cpu().numpy(), rho.cpu().numpy(), E, iters, st, res, near_decisions
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_lockstep_plain_small(seed):
+    """N=10,000, d=2, K=10, m_max=10, tol=1e-6 (and exact convergence)."""
+    X, _ = synth.plain_small(rep=seed)
+    C0 = synth.init_centroids(X, 10, seed)
+    for tol in (1e-6, 0.0):
+        C, rho, E, iters, st, res, _ = lockstep(X, C0, 10, tol)
+        assert E == pytest.approx(res.E, rel=1e-6)
+        assert st.accepted == res.accepted and st.rejected == res.rejected
+        assert st.assign_passes == res.assign_passes
+
+
+@pytest.mark.parametrize("N,d,K,seed", [(20000, 32, 64, 0), (12345, 16, 100, 1), (6000, 64, 40, 2),
+                                        (9000, 3, 25, 3)])
+def test_lockstep_mixtures(N, d, K, seed):
+    X, _ = synth.plain_large(rep=seed, n=N, d=d, k=K, cfg=60)
+    C0 = synth.init_centroids(X, K, seed)
+    lockstep(X, C0, 10, 1e-6)
+
+
+def test_lockstep_fixed_m_and_literal():
+    X, _ = synth.plain_small(rep=5)
+    C0 = synth.init_centroids(X, 10, 5)
+    lockstep(X, C0, 5, 0.0, fixed_m=True, m_init=5)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_end_to_end_plain_small(seed):
+    km = _km()
+    X, _ = synth.plain_small(rep=seed)
+    C0 = synth.init_centroids(X, 10, seed)
+    C, rho, E, iters, st = km.kmeans_solve(x_tensor(X), dev(C0), m_max=10, tol=1e-6)
+    res = ko.solve(x_values(X), C0.astype(np.float64), m_max=10, tol=1e-6)
+    assert iters == res.iters and st.accepted == res.accepted and st.rejected == res.rejected
+    assert E == pytest.approx(res.E, rel=1e-6)
+    assert centroid_errors(C.cpu().numpy(), res.C, x_values(X)).max() <= 1e-5
+    _labels_match(rho.cpu().numpy(), x_values(X), C.cpu().numpy().astype(np.float64))
+
+
+def test_m0_is_lloyd_on_gpu():
+    km = _km()
+    X, _ = synth.plain_small(rep=7)
+    C0 = synth.init_centroids(X, 10, 7)
+    C, rho, E, iters, st = km.kmeans_solve(x_tensor(X), dev(C0), m_max=0, tol=0.0)
+    res = ko.lloyd(x_values(X), C0.astype(np.float64), tol=0.0)
+    assert iters == res.iters and st.accepted == 0 and st.rejected == 0
+    assert E == pytest.approx(res.E, rel=1e-9)
+    assert centroid_errors(C.cpu().numpy(), res.C, x_values(X)).max() <= 1e-6
+
+
+def test_exact_convergence_is_fixed_point():
+    km = _km()
+    X, _ = synth.plain_large(rep=2, n=30000, d=16, k=50, cfg=61)
+    C0 = synth.init_centroids(X, 50, 2)
+    Xt = x_tensor(X)
+    C, rho, E, iters, st = km.kmeans_solve(Xt, dev(C0), m_max=10, tol=0.0)
+    assert st.status == 0
+    rho2, C2, E2, gs = km.kmeans_g(Xt, C)
+    assert np.array_equal(C2.cpu().numpy().view(np.uint32), C.cpu().numpy().view(np.uint32))
+    assert np.array_equal(rho2.cpu().numpy(), rho.cpu().numpy())
+    assert E2 == E
+
+
+def test_accepted_energies_monotone_and_counts():
+    km = _km()
+    X, _ = synth.plain_large(rep=4, n=20000, d=8, k=30, cfg=62)
+    C0 = synth.init_centroids(X, 30, 4)
+    C, rho, E, iters, st, tr = km.kmeans_solve(x_tensor(X), dev(C0), m_max=10, tol=0.0, trace=True)
+    rec = tr["rec"].cpu().numpy()[1:iters + 1]
+    acc = rec[:, 7]
+    assert np.all(np.diff(acc) <= 1e-12 * acc[:-1])
+    assert st.assign_passes == 1 + iters + st.rejected
+    assert st.accepted == int((rec[:, 4] == 1).sum())
+
+
+def test_max_iter_returns_last_accepted():
+    km = _km()
+    X, _ = synth.plain_small(rep=1)
+    C0 = synth.init_centroids(X, 10, 1)
+    C, rho, E, iters, st = km.kmeans_solve(x_tensor(X), dev(C0), m_max=10, tol=0.0, max_iter=3)
+    res = ko.solve(x_values(X), C0.astype(np.float64), m_max=10, tol=0.0, max_iter=3)
+    if res.status == ko.STATUS_NOT_CONVERGED:
+        assert st.status == 1 and iters == 3
+    assert E == pytest.approx(res.E, rel=1e-6)
+    assert E == pytest.approx(ko.energy(x_values(X), rho.cpu().numpy(), C.cpu().numpy()), rel=1e-9)
+
+
+def test_solver_deterministic():
+    km = _km()
+    X, _ = synth.plain_large(rep=5, n=50000, d=32, k=64, cfg=63)
+    C0 = synth.init_centroids(X, 64, 5)
+    Xt, Ct = x_tensor(X), dev(C0)
+    a = km.kmeans_solve(Xt, Ct, m_max=10, tol=1e-6)
+    b = km.kmeans_solve(Xt, Ct, m_max=10, tol=1e-6)
+    assert a[3] == b[3] and a[2] == b[2]
+    assert np.array_equal(a[0].cpu().numpy().view(np.uint32), b[0].cpu().numpy().view(np.uint32))
+    assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+
+
+def test_k_equals_n_and_k1():
+    km = _km()
+    X = synth.plain_small(rep=0, n=200)[0]
+    C, rho, E, iters, st = km.kmeans_solve(x_tensor(X), dev(X.copy()), m_max=10, tol=0.0)
+    assert E == 0.0 and iters == 1
+    C, rho, E, iters, st = km.kmeans_solve(x_tensor(X), dev(X[:1].copy()), m_max=10, tol=0.0)
+    np.testing.assert_allclose(C.cpu().numpy()[0], X.astype(np.float64).mean(axis=0), rtol=1e-6)
