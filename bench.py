@@ -1,0 +1,180 @@
+"""Benchmark: Anderson-accelerated Lloyd K-Means solves on one MI355X.
+
+One step = one complete solve (Algorithm 1: every assignment, update,
+Anderson and controller step until convergence) of the Gaussian-mixture
+workload N=1,000,000, d=32, K=256 (float32), m_max=10, tol=1e-6, from a
+seeded random-sample initialisation (step s uses init seed s).  X stays
+resident in HBM; the timed region holds K steps between two device
+synchronisations.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD = dict(N=1_000_000, d=32, K=256, m_max=10, tol=1e-6, max_iter=500)
+
+# rocprofv3 counter summaries of the dominant kernel (profiles/) give the
+# HBM traffic per launch; kept here as measured, None until measured for the
+# current kernel.
+TRAFFIC_BYTES_PER_LAUNCH = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU time budget of the oracle baseline sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(X, C0, passes_per_solve, budget_s):
+    """Time the FP64 oracle's G pass on a bounded sample of rows."""
+    from oracle import kmeans_oracle as ko
+    n = X.shape[0]
+    chunk = 32768
+    rows = 0
+    t0 = time.perf_counter()
+    while rows < n and time.perf_counter() - t0 < budget_s:
+        ko.g(X[rows:rows + chunk], C0)
+        rows += min(chunk, n - rows)
+    dt = time.perf_counter() - t0
+    pass_s = dt * n / rows
+    solves_per_s = 1.0 / (pass_s * passes_per_solve)
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        threads = os.cpu_count()
+    return {
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle G pass (float64 direct differences, assignment+update+energy) on the "
+                   f"first {rows} of {n} rows in {dt:.1f} s, scaled to full passes "
+                   f"({pass_s:.2f} s/pass) times {passes_per_solve:.1f} assignment passes per "
+                   f"solve; single-threaded NumPy on a host with {threads} visible cores"),
+        "dist_evals_per_s": rows * C0.shape[0] / dt,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1805_10638_amd as km
+    from paper_1805_10638_amd import synth
+
+    w = WORKLOAD
+    X, _ = synth.plain_large(rep=0, n=w["N"], d=w["d"], k=w["K"])
+    Xd = torch.from_numpy(X).to("cuda")
+    seeds = list(range(args.warmup + args.steps))
+    inits = [torch.from_numpy(synth.init_centroids(X, w["K"], s)).to("cuda") for s in seeds]
+    Cout = torch.empty((w["K"], w["d"]), dtype=torch.float32, device="cuda")
+    rho = torch.empty(w["N"], dtype=torch.int32, device="cuda")
+    ctx = km.Context(0)
+
+    def solve(C0):
+        return km.kmeans_solve(Xd, C0, m_max=w["m_max"], tol=w["tol"], max_iter=w["max_iter"],
+                               ctx=ctx, out=(Cout, rho))
+
+    for s in range(args.warmup):
+        solve(inits[s])
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    lat, iters, passes, acc, rej, flagged, assign_ms, assign_n = [], [], [], [], [], [], 0.0, 0
+    t0 = time.perf_counter()
+    for s in range(args.warmup, args.warmup + args.steps):
+        ts = time.perf_counter()
+        _, _, E, it, st = solve(inits[s])
+        lat.append(time.perf_counter() - ts)
+        iters.append(it)
+        passes.append(st.assign_passes)
+        acc.append(st.accepted)
+        rej.append(st.rejected)
+        flagged.append(st.flagged_rows)
+        assign_ms += st.assign_ms
+        assign_n += st.assign_launches
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+
+    N, d, K = w["N"], w["d"], w["K"]
+    solves_per_s = args.steps / elapsed
+    dist_evals = sum(passes) * N * K
+    avg_assign_s = (assign_ms / 1e3) / max(assign_n, 1)
+    flops = 2.0 * N * K * d
+    achieved = flops / avg_assign_s / 1e12
+    lat_ms = sorted(x * 1e3 for x in lat)
+
+    def pct(p):
+        i = min(len(lat_ms) - 1, max(0, int(round(p / 100.0 * (len(lat_ms) - 1)))))
+        return lat_ms[i]
+
+    out = {
+        "metric": "Lloyd+AA solves/s, p50/p99 latency; dist-evals/s & % roofline vs FP32",
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "gaussian-mixture N=1000000 d=32 K=256 float32, random-sample init "
+                        "(seed = step index), m_max=10 tol=1e-6 max_iter=500",
+            "N": N, "d": d, "K": K, "m_max": w["m_max"], "tol": w["tol"],
+            "gemm": "f32 MFMA", "parallelism": "single GPU",
+        },
+        "p50_ms": pct(50),
+        "p99_ms": pct(99),
+        "dist_evals_per_s": dist_evals / elapsed,
+        "iters_mean": statistics.mean(iters),
+        "assign_passes_mean": statistics.mean(passes),
+        "accepted_mean": statistics.mean(acc),
+        "rejected_mean": statistics.mean(rej),
+        "flagged_rows_per_pass": sum(flagged) / max(sum(passes), 1),
+        "roofline": {
+            "kernel": "assignment (k_assign, candidate role)",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": FP32_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+            "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+            "avg_launch_us": avg_assign_s * 1e6,
+            "launches": assign_n,
+            "flop_per_launch": flops,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(X, synth.init_centroids(X, K, 0),
+                                           statistics.mean(passes), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
