@@ -45,9 +45,15 @@ struct km_ctx {
   Ctl* ctl_host = nullptr;      // pinned host mirror
   int* done_host = nullptr;     // pinned poll slots
   double* scal_host = nullptr;  // pinned scalars
+  hipStream_t q = nullptr;      // internal stream (graph capture needs a non-null stream)
+  hipEvent_t enter = nullptr;   // orders q after the caller's stream
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  std::vector<hipEvent_t> tev;  // assignment timing pairs
+  hipEvent_t ta[2] = {nullptr, nullptr}, tb[2] = {nullptr, nullptr};  // around assignment
+
+  // per-iteration graphs (two, so that one can be inspected while the other runs)
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::string gkey;
 
   // workspace carve-up
   int* labels = nullptr;        // 3 x N
@@ -123,17 +129,21 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
     s.K = s.K > c->shape.K ? s.K : c->shape.K;
     s.cap = s.cap > c->shape.cap ? s.cap : c->shape.cap;
     s.bf = s.bf > c->shape.bf ? s.bf : c->shape.bf;
-    HIP_TRY(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    HIP_TRY(c, hipStreamSynchronize(c->q), "hipStreamSynchronize");
     HIP_TRY(c, hipFree(c->arena), "hipFree");
     c->arena = nullptr;
+    for (hipGraphExec_t& g : c->gexec) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+    c->gkey.clear();
   }
   const int64_t N = s.N;
   const int64_t KD = (int64_t)s.K * s.d;
-  const int grid = assign_grid(N, 1, 0) > assign_grid(N, s.d, 0) ? assign_grid(N, 1, 0)
-                                                                  : assign_grid(N, s.d, 0);
+  const int64_t grid = N / 64 + 1;   // upper bound of the assignment grid
   const int max_items = update_max_items(N, s.K);
   const int nblk = update_rank_blocks(N);
-  const int fin_grid = finalize_grid(s.K);
+  const int fin_grid = finalize_grid((int64_t)s.K * s.d);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += up(bytes); return o; };
   const size_t o_ctl = take(sizeof(Ctl));
@@ -174,7 +184,7 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
     c->arena_bytes = 0;
     return fail(c, KM_ENOMEM, "workspace allocation of " + std::to_string(off) + " bytes failed");
   }
-  HIP_TRY(c, hipMemsetAsync(p, 0, off, c->stream), "hipMemsetAsync");
+  HIP_TRY(c, hipMemsetAsync(p, 0, off, c->q), "hipMemsetAsync");
   char* b = (char*)p;
   c->arena = p;
   c->arena_bytes = off;
@@ -262,7 +272,11 @@ km_status km_create(int device, void* stream, km_ctx** out) {
   km_ctx* c = new km_ctx();
   c->device = device;
   c->stream = (hipStream_t)stream;
-  bool ok = hipHostMalloc((void**)&c->ctl_host, sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
+  bool ok = hipStreamCreateWithFlags(&c->q, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&c->enter, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreate(&c->ta[0]) == hipSuccess && hipEventCreate(&c->ta[1]) == hipSuccess &&
+            hipEventCreate(&c->tb[0]) == hipSuccess && hipEventCreate(&c->tb[1]) == hipSuccess &&
+            hipHostMalloc((void**)&c->ctl_host, sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&c->done_host, 2 * sizeof(int), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&c->scal_host, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
             hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming) == hipSuccess &&
@@ -279,17 +293,19 @@ km_status km_create(int device, void* stream, km_ctx** out) {
 void km_destroy(km_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  if (c->arena) {
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(c->arena);
-  }
+  if (c->q) (void)hipStreamSynchronize(c->q);
+  for (hipGraphExec_t g : c->gexec) if (g) (void)hipGraphExecDestroy(g);
+  if (c->arena) (void)hipFree(c->arena);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
   if (c->done_host) (void)hipHostFree(c->done_host);
   if (c->scal_host) (void)hipHostFree(c->scal_host);
   for (hipEvent_t e : c->poll_ev) if (e) (void)hipEventDestroy(e);
   if (c->t0) (void)hipEventDestroy(c->t0);
   if (c->t1) (void)hipEventDestroy(c->t1);
-  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ta) if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->tb) if (e) (void)hipEventDestroy(e);
+  if (c->enter) (void)hipEventDestroy(c->enter);
+  if (c->q) (void)hipStreamDestroy(c->q);
   delete c;
 }
 
@@ -338,8 +354,10 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   want.N = N; want.d = d; want.K = K; want.cap = 0; want.bf = prec == KM_GEMM_BF16;
   s = ensure_ws(c, want);
   if (s != KM_OK) return s;
-  hipStream_t st_ = c->stream;
+  hipStream_t st_ = c->q;
   const bool gbf = prec == KM_GEMM_BF16;
+  HIP_TRY(c, hipEventRecord(c->enter, c->stream), "hipEventRecord");
+  HIP_TRY(c, hipStreamWaitEvent(st_, c->enter, 0), "hipStreamWaitEvent");
 
   HIP_TRY(c, hipMemsetAsync(c->ctl, 0, sizeof(Ctl), st_), "hipMemsetAsync");
   HIP_TRY(c, launch_prep(C, K, d, c->nc_tmp, gbf ? c->Cb_tmp : nullptr, gbf ? c->del_tmp : nullptr, st_),
@@ -350,7 +368,7 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->e_part; a.ctl = c->ctl;
   a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
   HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
-  const int grid = assign_grid(N, d, gbf);
+  const int grid = assign_grid(a);
   HIP_TRY(c, launch_reduce_energy(c->e_part, grid, c->e_out, st_), "energy");
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
@@ -362,6 +380,8 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = 0; f.partial = c->partial; f.item_start = c->item_start;
   f.counts = c->counts; f.C_in = C; f.C_out = C_out; f.ctl = c->ctl; f.mode = kFinG;
+  f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
+  f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
   HIP_TRY(c, launch_finalize(f, st_), "finalize");
   HIP_TRY(c, hipMemcpyAsync(c->scal_host, c->e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
   HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
@@ -388,7 +408,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
   if (opt.max_iter < 1) return fail(c, KM_EINVAL, "max_iter must be >= 1");
   if (opt.m_init < 0) return fail(c, KM_EINVAL, "m_init must be >= 0");
-  if (!(opt.ridge >= 0.0) || !isfinite(opt.eps1) || !isfinite(opt.eps2))
+  if (!(opt.ridge >= 0.0) || !isfinite(opt.ridge) || !isfinite(opt.eps1) || !isfinite(opt.eps2))
     return fail(c, KM_EINVAL, "eps1, eps2 and ridge must be finite (ridge >= 0)");
   if (!E || !iters) return fail(c, KM_EINVAL, "E and iters must be host pointers");
   if (!is_device_ptr(C0) || !is_device_ptr(C_out) || !is_device_ptr(rho_out))
@@ -407,9 +427,10 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   want.N = N; want.d = d; want.K = K; want.cap = m_max; want.bf = gbf;
   s = ensure_ws(c, want);
   if (s != KM_OK) return s;
-  hipStream_t q = c->stream;
+  hipStream_t q = c->q;
   const bool xbf = xt == KM_X_BF16;
   const int cap = m_max;
+  const int64_t KD = (int64_t)K * d;
 
   // controller state
   Ctl h;
@@ -424,95 +445,147 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   h.E1 = HUGE_VAL; h.E2 = HUGE_VAL;
   h.assign_passes = 1;
   *c->ctl_host = h;
+  HIP_TRY(c, hipEventRecord(c->enter, c->stream), "hipEventRecord");
+  HIP_TRY(c, hipStreamWaitEvent(q, c->enter, 0), "hipStreamWaitEvent");
   HIP_TRY(c, hipEventRecord(c->t0, q), "hipEventRecord");
   HIP_TRY(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
 
-  // prologue: P^0 = Assign(C^0), G^0 = Update(P^0), F^0 = G^0 - C^0, C^1 = G^0
-  HIP_TRY(c, hipMemcpyAsync(c->C_tmp, C0, cbytes, hipMemcpyDeviceToDevice, q), "copy C0");
-  HIP_TRY(c, launch_prep(c->C_tmp, K, d, c->nc_tmp, gbf ? c->Cb_tmp : nullptr,
-                         gbf ? c->del_tmp : nullptr, q), "prep");
+  // ---- kernel arguments ----
   AssignArgs a{};
   a.X = X; a.N = N; a.d = d; a.K = K; a.C = c->C_tmp; a.nc = c->nc_tmp;
   a.Cb = gbf ? c->Cb_tmp : nullptr; a.delta = gbf ? c->del_tmp : nullptr;
   a.lab = c->labels; a.lab_prev = nullptr; a.e_part = c->e_part; a.ctl = c->ctl;
   a.xbf16 = xbf; a.gemm_bf16 = gbf;
-  HIP_TRY(c, launch_assign(a, kRolePlain, q), "assignment");
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xbf;
   u.lab = c->labels; u.lab_from_ctl = 1; u.lrank = c->lrank; u.blockcount = c->blockcount;
   u.counts = c->counts; u.seg_start = c->seg_start; u.item_start = c->item_start;
   u.item_cluster = c->item_cluster; u.perm = c->perm; u.partial = c->partial;
   u.max_items = update_max_items(N, K); u.ctl = c->ctl; u.gated = 1;
-  HIP_TRY(c, launch_update_sums(u, q), "update");
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = cap; f.partial = c->partial; f.item_start = c->item_start;
   f.counts = c->counts; f.C_in = c->C_tmp; f.C_out = nullptr;
-  f.C_cand = c->C_cand; f.C_cand_w = c->C_cand; f.nc_cand = c->nc_cand;
-  f.C_fb = c->C_fb; f.nc_fb = c->nc_fb;
-  f.Cb_cand = gbf ? c->Cb_cand : nullptr; f.delta_cand = gbf ? c->del_cand : nullptr;
-  f.Cb_fb = gbf ? c->Cb_fb : nullptr; f.delta_fb = gbf ? c->del_fb : nullptr;
+  f.C_cand = c->C_cand; f.C_fb = c->C_fb;
   f.G_last = c->G_last; f.F_last = c->F_last; f.ring_dF = c->ring_dF; f.ring_dG = c->ring_dG;
   f.dots = c->dots; f.ctl = c->ctl; f.mode = kFinInit;
+  CombineArgs cb{};
+  cb.ctl = c->ctl; cb.gated = 0; cb.G_last = c->G_last; cb.ring_dG = c->ring_dG;
+  cb.K = K; cb.d = d; cb.cap = cap;
+  cb.C_cand = c->C_cand; cb.nc_cand = c->nc_cand; cb.Cb_cand = gbf ? c->Cb_cand : nullptr;
+  cb.delta_cand = gbf ? c->del_cand : nullptr;
+  cb.C_fb = c->C_fb; cb.nc_fb = c->nc_fb; cb.Cb_fb = gbf ? c->Cb_fb : nullptr;
+  cb.delta_fb = gbf ? c->del_fb : nullptr;
+
+  // ---- prologue: P^0 = Assign(C^0), G^0 = Update(P^0), F^0 = G^0 - C^0, C^1 = G^0 ----
+  HIP_TRY(c, hipMemcpyAsync(c->C_tmp, C0, cbytes, hipMemcpyDeviceToDevice, q), "copy C0");
+  HIP_TRY(c, launch_prep(c->C_tmp, K, d, c->nc_tmp, gbf ? c->Cb_tmp : nullptr,
+                         gbf ? c->del_tmp : nullptr, q), "prep");
+  HIP_TRY(c, launch_assign(a, kRolePlain, q), "assignment");
+  HIP_TRY(c, launch_update_sums(u, q), "update");
   HIP_TRY(c, launch_finalize(f, q), "finalize");
-  // counters of the first candidate pass start at zero
+  HIP_TRY(c, launch_combine(cb, q), "combine");
+  // counters of the first candidate pass start from zero
   HIP_TRY(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
 
-  // per-iteration launch sequence
-  const int grid = assign_grid(N, d, gbf);
+  // ---- per-iteration launch sequence, captured once into two graphs ----
+  const int grid = assign_grid(a);
+  if (grid <= 0) return fail(c, KM_EUNSUPPORTED, "no assignment kernel for this shape");
   AssignArgs ac = a;
   ac.C = c->C_cand; ac.nc = c->nc_cand; ac.Cb = gbf ? c->Cb_cand : nullptr;
   ac.delta = gbf ? c->del_cand : nullptr; ac.e_part = c->e_part;
   AssignArgs af = a;
   af.C = c->C_fb; af.nc = c->nc_fb; af.Cb = gbf ? c->Cb_fb : nullptr;
   af.delta = gbf ? c->del_fb : nullptr; af.e_part = c->e_part + grid;
-  CtlArgs k1{};
-  k1.ctl = c->ctl; k1.e_part = c->e_part; k1.n_part = grid; k1.stage = 1; k1.C_cand = c->C_cand;
-  k1.K = K; k1.d = d; k1.trace_C = opt.trace_C; k1.trace_rec = opt.trace_rec;
-  CtlArgs k2 = k1;
-  k2.e_part = c->e_part + grid; k2.stage = 2; k2.trace_C = nullptr;
   FinalizeArgs fi = f;
-  fi.mode = kFinIter; fi.C_in = nullptr; fi.C_cand_w = nullptr;
+  fi.mode = kFinIter; fi.C_in = nullptr;
   SolveArgs sa{};
-  sa.ctl = c->ctl; sa.dots = c->dots; sa.n_dots = c->fin_grid > 0 ? finalize_grid(K) : 0;
+  sa.ctl = c->ctl; sa.dots = c->dots; sa.n_dots = finalize_grid(KD);
   sa.gram = c->gram; sa.cap = cap; sa.trace_rec = opt.trace_rec;
-  CombineArgs cb{};
-  cb.ctl = c->ctl; cb.G_last = c->G_last; cb.ring_dG = c->ring_dG; cb.K = K; cb.d = d; cb.cap = cap;
-  cb.C_cand = c->C_cand; cb.nc_cand = c->nc_cand; cb.Cb_cand = gbf ? c->Cb_cand : nullptr;
-  cb.delta_cand = gbf ? c->del_cand : nullptr;
+  CombineArgs ci = cb;
+  ci.gated = 1;
 
-  if (c->timing && (int)c->tev.size() < 2 * opt.max_iter) {
-    while ((int)c->tev.size() < 2 * opt.max_iter) {
-      hipEvent_t e;
-      HIP_TRY(c, hipEventCreate(&e), "hipEventCreate");
-      c->tev.push_back(e);
-    }
-  }
+  // The candidate assignment is launched directly (between two HIP events
+  // when timing is on); the rest of the iteration is replayed from a graph.
+  CtlArgs k1{};
+  k1.ctl = c->ctl; k1.e_part = c->e_part; k1.n_part = grid; k1.stage = 1;
+  k1.tr.trace_C = opt.trace_C; k1.tr.trace_rec = opt.trace_rec; k1.tr.C_cand = c->C_cand;
+  k1.tr.K = K; k1.tr.d = d;
+  CtlArgs k2 = k1;
+  k2.e_part = c->e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
 
-  int launched = 0;
-  bool finished = false;
-  while (launched < opt.max_iter && !finished) {
-    const int it = launched;
-    if (c->timing) HIP_TRY(c, hipEventRecord(c->tev[2 * it], q), "hipEventRecord");
-    HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
-    if (c->timing) HIP_TRY(c, hipEventRecord(c->tev[2 * it + 1], q), "hipEventRecord");
+  auto enqueue_rest = [&](int p) -> km_status {
     HIP_TRY(c, launch_controller(k1, q), "controller");
     HIP_TRY(c, launch_assign(af, kRoleFallback, q), "assignment");
     HIP_TRY(c, launch_controller(k2, q), "controller");
     HIP_TRY(c, launch_update_sums(u, q), "update");
     HIP_TRY(c, launch_finalize(fi, q), "finalize");
     HIP_TRY(c, launch_ls_solve(sa, q), "least squares");
-    HIP_TRY(c, launch_combine(cb, q), "combine");
-    HIP_TRY(c, hipMemcpyAsync(&c->done_host[it & 1], &c->ctl->done, sizeof(int),
-                              hipMemcpyDeviceToHost, q), "poll copy");
-    HIP_TRY(c, hipEventRecord(c->poll_ev[it & 1], q), "hipEventRecord");
+    HIP_TRY(c, launch_combine(ci, q), "combine");
+    HIP_TRY(c, hipMemcpyAsync(&c->done_host[p], &c->ctl->done, sizeof(int), hipMemcpyDeviceToHost, q),
+            "poll copy");
+    return KM_OK;
+  };
+
+  char keybuf[512];
+  snprintf(keybuf, sizeof keybuf, "%p|%d|%lld|%d|%d|%d|%d|%p|%p|%p", X, (int)xt, (long long)N, d, K,
+           cap, (int)gbf, (void*)opt.trace_C, (void*)opt.trace_rec, c->arena);
+  if (c->gkey != keybuf) {
+    for (hipGraphExec_t& g : c->gexec) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+    c->gkey.clear();
+    for (int p = 0; p < 2; ++p) {
+      hipGraph_t graph = nullptr;
+      HIP_TRY(c, hipStreamBeginCapture(q, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+      km_status es = enqueue_rest(p);
+      hipError_t ee = hipStreamEndCapture(q, &graph);
+      if (es != KM_OK) return es;
+      if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
+      ee = hipGraphInstantiate(&c->gexec[p], graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ee != hipSuccess) return hip_fail(c, ee, "hipGraphInstantiate");
+    }
+    c->gkey = keybuf;
+  }
+
+  std::vector<float> it_ms;
+  it_ms.reserve(64);
+  int launched = 0;
+  bool finished = false;
+  while (launched < opt.max_iter && !finished) {
+    const int it = launched;
+    const int p = it & 1;
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[p], q), "hipEventRecord");
+    HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[p], q), "hipEventRecord");
+    HIP_TRY(c, hipGraphLaunch(c->gexec[p], q), "hipGraphLaunch");
+    HIP_TRY(c, hipEventRecord(c->poll_ev[p], q), "hipEventRecord");
     if (it >= 1) {
-      HIP_TRY(c, hipEventSynchronize(c->poll_ev[(it - 1) & 1]), "hipEventSynchronize");
-      if (c->done_host[(it - 1) & 1]) finished = true;
+      const int pp = (it - 1) & 1;
+      HIP_TRY(c, hipEventSynchronize(c->poll_ev[pp]), "hipEventSynchronize");
+      if (c->timing) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ta[pp], c->tb[pp]) != hipSuccess) {
+          clear_pending_error();
+          ms = -1.f;
+        }
+        it_ms.push_back(ms);
+      }
+      if (c->done_host[pp]) finished = true;
     }
     ++launched;
   }
   HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, q), "copy ctl");
   HIP_TRY(c, hipStreamSynchronize(q), "hipStreamSynchronize");
+  if (c->timing && !finished) {  // the last launched iteration was not inspected in the loop
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ta[(launched - 1) & 1], c->tb[(launched - 1) & 1]) != hipSuccess) {
+      clear_pending_error();
+      ms = -1.f;
+    }
+    it_ms.push_back(ms);
+  }
   Ctl r = *c->ctl_host;
   if (!r.done) return fail(c, KM_EDEVICE, "solver did not reach a final state");
   const float* Cres = r.acc_src == 1 ? c->C_fb : c->C_cand;
@@ -533,13 +606,13 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     st->flagged_rows = (int64_t)r.flagged_total;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->t0, c->t1) == hipSuccess) st->device_ms = ms;
+    else clear_pending_error();
     if (c->timing) {
       double sum = 0.0;
       int n = 0;
-      for (int it = 0; it < r.t && it < launched; ++it) {
-        float e = 0.f;
-        if (hipEventElapsedTime(&e, c->tev[2 * it], c->tev[2 * it + 1]) == hipSuccess) {
-          sum += e;
+      for (int it = 0; it < r.t && it < (int)it_ms.size(); ++it) {
+        if (it_ms[it] >= 0.f) {
+          sum += it_ms[it];
           ++n;
         }
       }

@@ -2,16 +2,21 @@
 //
 // The squared distance ||x - c_j||^2 = ||x||^2 - 2 (x.c_j - ||c_j||^2 / 2), so
 // the argmin over j is the argmax of s_j = x.c_j - ||c_j||^2 / 2.  The s_j
-// of a 16-centroid x 16-sample tile come out of MFMA (v_mfma_f32_16x16x4f32)
-// with the accumulator pre-loaded with -||c_j||^2 / 2; the running best and
-// second-best s_j of each sample stay in registers across the whole K loop.
+// of a 16-centroid x 16-sample tile come out of MFMA (v_mfma_f32_16x16x4f32,
+// or v_mfma_f32_16x16x32_bf16) with the accumulator pre-loaded with
+// -||c_j||^2 / 2; the running best and second-best s_j of each sample stay in
+// registers across the whole K loop.
 //
-// Operand layout of the 16x16x4 MFMA: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; it receives D[4*(l/16)+r][l%16], r = 0..3.  A is a tile of
-// 16 centroids, B a tile of 16 samples, so each lane accumulates 4 centroids
-// of one sample.  The reduction index k is permuted so that lane group
-// g = l/16 owns the contiguous dimensions [g*KS, g*KS+KS): sample rows are
-// read with wide contiguous loads and kept in registers for the whole K loop.
+// Operand layout of the 16x16 MFMAs: lane l supplies row l%16 of A and
+// column l%16 of B for the k-slice owned by lane group g = l/16, and
+// receives D[4g+r][l%16], r = 0..3.  A is a tile of 16 centroids, B a tile of
+// 16 samples, so each lane accumulates 4 centroids of one sample.  The
+// reduction index is permuted so that lane group g owns the contiguous
+// dimensions [g*KS, g*KS+KS): sample rows are read with wide contiguous loads
+// and kept in registers for the whole K loop.
+//
+// Workgroups are persistent: each stages the centroids into LDS once (when
+// they fit) and then walks row groups gridDim.x apart.
 //
 // Exactness.  With u = 2^-24 and dp the padded dimension, every computed s_j
 // is within gamma/2 * (||x|| + max_j ||c_j||)^2 of its exact value, gamma =
@@ -26,6 +31,8 @@
 // extra error of at most ||x|| * delta_j with delta_j = ||c_j - Cb_j||, which
 // is added to the bound.  X stored as bfloat16 is exact in both modes.
 
+#include <stdlib.h>
+
 #include "km_launch.h"
 
 namespace km {
@@ -34,8 +41,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short i16x8 __attribute__((ext_vector_type(8)));
 
+constexpr int kAssignLdsBudget = 60 * 1024;   // bytes of LDS for the centroid tile
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
   return __uint_as_float(((uint32_t)b) << 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
 
 __device__ __forceinline__ float ld_x(const void* X, int64_t idx, bool bf) {
@@ -82,20 +97,7 @@ __device__ __forceinline__ void load_chunk(const void* X, int64_t i, int d, int 
 // Exact re-check of one flagged sample by the whole wave: float64 direct
 // differences to all K centroids, lowest index on ties.  Returns the label
 // (or -1 if every distance is NaN) and its distance in *dist.
-template <bool XBF>
-__device__ __forceinline__ int exact_argmin(const void* X, int64_t i, int d, const float* C, int K,
-                                            int lane, double* dist) {
-  double bd = __builtin_inf();
-  int bj = -1;
-  for (int j = lane; j < K; j += kWave) {
-    const float* cr = C + (int64_t)j * d;
-    double s = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double df = (double)ld_x(X, i * d + k, XBF) - (double)cr[k];
-      s = fma(df, df, s);
-    }
-    if (s < bd) { bd = s; bj = j; }
-  }
+__device__ __forceinline__ int wave_argmin(double bd, int bj, double* dist) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const double ob = __shfl_xor(bd, off, kWave);
@@ -108,35 +110,133 @@ __device__ __forceinline__ int exact_argmin(const void* X, int64_t i, int d, con
   return bj;
 }
 
-// One 16x16 tile: s = nc4 + C_tile . x_tile over the padded dimension.
-template <int KS, bool GBF>
-__device__ __forceinline__ f32x4 tile_dot(const float (&av)[KS], const float (&xv)[KS],
-                                          const i16x8 (&ab)[KS / 8 > 0 ? KS / 8 : 1],
-                                          const i16x8 (&xbv)[KS / 8 > 0 ? KS / 8 : 1], f32x4 acc) {
-  if constexpr (GBF) {
-#pragma unroll
-    for (int q = 0; q < KS / 8; ++q)
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ab[q]),
-                                                    __builtin_bit_cast(bf16x8, xbv[q]), acc, 0, 0, 0);
-  } else {
-#pragma unroll
-    for (int q = 0; q < KS; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], xv[q], acc, 0, 0, 0);
+// Centroids and the sample from global memory (any layout case).
+template <bool XBF>
+__device__ __noinline__ int exact_argmin(const void* X, int64_t i, int d, const float* C, int K,
+                                         int lane, double* dist) {
+  double bd = __builtin_inf();
+  int bj = -1;
+  for (int j = lane; j < K; j += kWave) {
+    const float* cr = C + (int64_t)j * d;
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double df = (double)ld_x(X, i * d + k, XBF) - (double)cr[k];
+      s = fma(df, df, s);
+    }
+    if (s < bd) { bd = s; bj = j; }
   }
-  return acc;
+  return wave_argmin(bd, bj, dist);
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// Centroids resident in LDS (row stride ld, zero-padded to DP) and the
+// sample staged in LDS (xrow, zero-padded to DP).
+template <int DP>
+__device__ __noinline__ int exact_argmin_lds(const float* xrow, const float* Cs, int ld, int K, int lane,
+                                             double* dist) {
+  double bd = __builtin_inf();
+  int bj = -1;
+  for (int j = lane; j < K; j += kWave) {
+    const float* cr = Cs + j * ld;
+    double s = 0.0;
+    if constexpr (DP % 4 == 0) {
+#pragma unroll 4
+      for (int k = 0; k < DP; k += 4) {
+        const float4 x4 = *(const float4*)(xrow + k);
+        const float4 c4 = *(const float4*)(cr + k);
+        double df = (double)x4.x - (double)c4.x; s = fma(df, df, s);
+        df = (double)x4.y - (double)c4.y; s = fma(df, df, s);
+        df = (double)x4.z - (double)c4.z; s = fma(df, df, s);
+        df = (double)x4.w - (double)c4.w; s = fma(df, df, s);
+      }
+    } else {
+      for (int k = 0; k < DP; ++k) {
+        const double df = (double)xrow[k] - (double)cr[k];
+        s = fma(df, df, s);
+      }
+    }
+    if (s < bd) { bd = s; bj = j; }
+  }
+  return wave_argmin(bd, bj, dist);
 }
 
-// KS: padded dims per lane group (dp = 4*KS for f32 MFMA; for the bf16 MFMA
-// the per-lane chunk is KS dims with KS a multiple of 8 and dp = 4*KS).
-// SB: 16-sample blocks per wave.
-template <int KS, int SB, int ROLE, bool XBF, bool GBF>
-__global__ __launch_bounds__(256) void k_assign(AssignArgs a) {
+template <int KS, bool GBF>
+struct Tile {
+  static constexpr int DP = 4 * KS;                    // padded dimension
+  static constexpr int NB = GBF ? KS / 8 : 1;          // bf16 MFMAs per tile
+  static constexpr int LD = DP + 4;                    // f32 LDS row stride (floats)
+  static constexpr int LDB = DP + 8;                   // bf16 LDS row stride (elements)
+  static constexpr int ROW_BYTES = GBF ? LDB * 2 : LD * 4;
+  // centroid rows per LDS chunk (multiple of 16) for a given K
+  static __host__ __device__ int chunk_rows(int K) {
+    const int kpad = (K + 15) & ~15;
+    int c = ((kAssignLdsBudget - 16 * DP * 4) / (ROW_BYTES + 4)) & ~15;
+    return c < kpad ? c : kpad;
+  }
+  static __host__ __device__ size_t lds_bytes(int K) {
+    const int c = chunk_rows(K);
+    return (size_t)c * ROW_BYTES + (size_t)c * 4 + 32 * 4 + 16 * 8 + (size_t)16 * DP * 4;
+  }
+};
+
+// Plain v_max_f32: the IEEE-mode lowering of fmaxf would first quiet both
+// operands (two extra instructions per compare on this hot path).  NaN
+// inputs only arise from non-finite data, which the energy reports anyway.
+__device__ __forceinline__ float vmax(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// MFMAs of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk) against
+// the SB sample blocks of this wave; accumulators start at -||c||^2/2.
+template <int KS, int SB, bool GBF>
+__device__ __forceinline__ void tile_mfma(const float* Cs, const uint16_t* Cbs, const float* ncs,
+                                          int tt, int g, int r16, const float (&xv)[SB][KS],
+                                          const i16x8 (&xbv)[SB][Tile<KS, GBF>::NB], f32x4 (&acc)[SB]) {
+  using T = Tile<KS, GBF>;
+  const f32x4 n4 = *(const f32x4*)(ncs + tt + 4 * g);
+#pragma unroll
+  for (int s = 0; s < SB; ++s) acc[s] = n4;
+  if constexpr (GBF) {
+    i16x8 ab[T::NB];
+    const i16x8* cr = (const i16x8*)(Cbs + (tt + r16) * T::LDB + g * KS);
+#pragma unroll
+    for (int q = 0; q < T::NB; ++q) ab[q] = cr[q];
+#pragma unroll
+    for (int q = 0; q < T::NB; ++q)
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf16x8, ab[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+  } else {
+    float av[KS];
+    const float* cr = Cs + (tt + r16) * T::LD + g * KS;
+    if constexpr (KS % 4 == 0) {
+#pragma unroll
+      for (int q = 0; q < KS; q += 4) {
+        const float4 v = *(const float4*)(cr + q);
+        av[q] = v.x; av[q + 1] = v.y; av[q + 2] = v.z; av[q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KS; ++q) av[q] = cr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < KS; ++q)
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], xv[s][q], acc[s], 0, 0, 0);
+  }
+}
+
+// KS: padded dims per lane group; SB: 16-sample blocks per wave; W: waves
+// per workgroup (they share one LDS copy of the centroids).
+template <int KS, int SB, int W, int ROLE, bool XBF, bool GBF>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((GBF || KS > 32) ? 1 : 4))) void k_assign(AssignArgs a) {
+  constexpr int NT = 64 * W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  using T = Tile<KS, GBF>;
+  constexpr int DP = T::DP, LD = T::LD, LDB = T::LDB, NB = T::NB;
   Ctl* ctl = a.ctl;
   if (ROLE != kRolePlain) {
     if (ctl->done) return;
@@ -156,211 +256,244 @@ __global__ __launch_bounds__(256) void k_assign(AssignArgs a) {
   }
   const int slot = (ROLE == kRoleFallback) ? 1 : 0;
 
-  constexpr int DP = 4 * KS;        // padded dimension
-  constexpr int LD = DP + 4;        // LDS row stride (floats) of the f32 tile
-  constexpr int LDB = DP + 8;       // LDS row stride (bf16) of the bf16 tile
-  constexpr int NB = KS / 8 > 0 ? KS / 8 : 1;
   const int d = a.d, K = a.K;
   const int Kpad = (K + 15) & ~15;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r16 = lane & 15;
 
   // LDS: centroid tile, -||c||^2/2 per row, small reduction scratch.
-  const int chunk = GBF ? (int)(65536 / (LDB * 2 + 4)) & ~15 : (int)(65536 / (LD * 4 + 4)) & ~15;
-  const int kchunk = chunk < Kpad ? chunk : Kpad;
+  const int kchunk = T::chunk_rows(K);
+  const bool resident = kchunk >= Kpad;
   float* Cs = (float*)smem_raw;                                  // kchunk x LD (f32 path)
   uint16_t* Cbs = (uint16_t*)smem_raw;                           // kchunk x LDB (bf16 path)
-  float* ncs = (float*)(smem_raw + (GBF ? (size_t)kchunk * LDB * 2 : (size_t)kchunk * LD * 4));
-  float* fred = ncs + kchunk;          // 8 floats
-  double* dred = (double*)(fred + 8);  // 4 doubles
+  float* ncs = (float*)(smem_raw + (size_t)kchunk * T::ROW_BYTES);
+  float* fred = ncs + kchunk;          // 2 W floats (W <= 16)
+  double* dred = (double*)(fred + 32); // W doubles
 
   // max_j ||c_j||^2 and max_j delta_j over the real centroids
   float mx = 0.f, mdel = 0.f;
-  for (int j = tid; j < K; j += 256) {
+  for (int j = tid; j < K; j += NT) {
     mx = fmaxf(mx, a.nc[j]);
     if (GBF) mdel = fmaxf(mdel, a.delta[j]);
   }
   mx = wave_max(mx);
   mdel = wave_max(mdel);
-  if (lane == 0) { fred[wave] = mx; fred[4 + wave] = mdel; }
+  if (lane == 0) { fred[wave] = mx; fred[16 + wave] = mdel; }
   __syncthreads();
-  const float cmax = sqrtf(fmaxf(fmaxf(fred[0], fred[1]), fmaxf(fred[2], fred[3]))) * 1.0001f;
-  const float dmax = GBF ? fmaxf(fmaxf(fred[4], fred[5]), fmaxf(fred[6], fred[7])) * 1.0001f : 0.f;
+  float cm2 = 0.f, dm = 0.f;
+#pragma unroll
+  for (int w = 0; w < W; ++w) { cm2 = fmaxf(cm2, fred[w]); dm = fmaxf(dm, fred[16 + w]); }
+  const float cmax = sqrtf(cm2) * 1.0001f;
+  const float dmax = GBF ? dm * 1.0001f : 0.f;
+  const float u = 5.9604644775390625e-8f;  // 2^-24
+  const float gam = 2.0f * ((float)(DP + 3) * u) / (1.0f - (float)(DP + 3) * u) * 1.001f;
 
-  // Sample rows of this wave, kept in registers.
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * SB);
-  const bool vec = (d == DP);
-  float xv[SB][KS];
-  i16x8 xbv[SB][NB];
-  float xerr[SB];  // ||x - bf16(x)||^2 partial when float32 X feeds the bf16 GEMM
-#pragma unroll
-  for (int s = 0; s < SB; ++s) {
-    xerr[s] = 0.f;
-    const int64_t i = row0 + 16 * s + r16;
-    if (i < a.N) {
-      load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xv[s]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < KS; ++q) xv[s][q] = 0.f;
-    }
+  // Stage centroid rows [c0, c0 + rows) into LDS (zero padding beyond d and K).
+  auto stage = [&](int c0, int rows) {
     if constexpr (GBF) {
-      // X values are exact in bfloat16 when stored so; otherwise this rounds.
+      const bool v8 = (d % 8) == 0;
+      for (int e = tid; e < rows * (DP / 8); e += NT) {
+        const int rr = e / (DP / 8), c8 = (e - rr * (DP / 8)) * 8, j = c0 + rr;
+        i16x8 v;
+        if (v8 && j < K && c8 < d) {
+          v = *(const i16x8*)(a.Cb + (int64_t)j * d + c8);
+        } else {
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint16_t hb = f32_to_bf16_rne(xv[s][8 * q + e]);
-          xbv[s][q][e] = (short)hb;
-          if (!XBF) {
-            const float df = xv[s][8 * q + e] - bf16_to_f32(hb);
-            xerr[s] = fmaf(df, df, xerr[s]);
-          }
+          for (int q = 0; q < 8; ++q)
+            v[q] = (j < K && c8 + q < d) ? (short)a.Cb[(int64_t)j * d + c8 + q] : (short)0;
         }
-    }
-  }
-
-  float best[SB], sec[SB];
-  int bidx[SB];
-#pragma unroll
-  for (int s = 0; s < SB; ++s) { best[s] = -__builtin_inff(); sec[s] = -__builtin_inff(); bidx[s] = 0; }
-
-  for (int c0 = 0; c0 < Kpad; c0 += kchunk) {
-    const int rows = (Kpad - c0) < kchunk ? (Kpad - c0) : kchunk;
-    __syncthreads();
-    if constexpr (GBF) {
-      for (int e = tid; e < rows * DP; e += 256) {
-        const int rr = e / DP, col = e - rr * DP, j = c0 + rr;
-        Cbs[rr * LDB + col] = (j < K && col < d) ? a.Cb[(int64_t)j * d + col] : (uint16_t)0;
+        *(i16x8*)(Cbs + rr * LDB + c8) = v;
       }
     } else {
-      for (int e = tid; e < rows * DP; e += 256) {
-        const int rr = e / DP, col = e - rr * DP, j = c0 + rr;
-        Cs[rr * LD + col] = (j < K && col < d) ? a.C[(int64_t)j * d + col] : 0.f;
+      const bool v4 = (d % 4) == 0;
+      for (int e = tid; e < rows * (DP / 4); e += NT) {
+        const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
+        float4 v;
+        if (v4 && j < K && c4 < d) {
+          v = *(const float4*)(a.C + (int64_t)j * d + c4);
+        } else {
+          v.x = (j < K && c4 + 0 < d) ? a.C[(int64_t)j * d + c4 + 0] : 0.f;
+          v.y = (j < K && c4 + 1 < d) ? a.C[(int64_t)j * d + c4 + 1] : 0.f;
+          v.z = (j < K && c4 + 2 < d) ? a.C[(int64_t)j * d + c4 + 2] : 0.f;
+          v.w = (j < K && c4 + 3 < d) ? a.C[(int64_t)j * d + c4 + 3] : 0.f;
+        }
+        *(float4*)(Cs + rr * LD + c4) = v;
       }
     }
-    for (int rr = tid; rr < rows; rr += 256) {
+    for (int rr = tid; rr < rows; rr += NT) {
       const int j = c0 + rr;
       ncs[rr] = (j < K) ? -0.5f * a.nc[j] : -__builtin_inff();
     }
+  };
+  if (resident) {
+    stage(0, Kpad);
     __syncthreads();
-
-    for (int tt = 0; tt < rows; tt += 16) {
-      float av[KS];
-      i16x8 ab[NB];
-      if constexpr (GBF) {
-        const i16x8* cr = (const i16x8*)(Cbs + (tt + r16) * LDB + g * KS);
-#pragma unroll
-        for (int q = 0; q < NB; ++q) ab[q] = cr[q];
-      } else {
-        const float* cr = Cs + (tt + r16) * LD + g * KS;
-        if constexpr (KS % 4 == 0) {
-#pragma unroll
-          for (int q = 0; q < KS; q += 4) {
-            const float4 v = *(const float4*)(cr + q);
-            av[q] = v.x; av[q + 1] = v.y; av[q + 2] = v.z; av[q + 3] = v.w;
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < KS; ++q) av[q] = cr[q];
-        }
-      }
-      const f32x4 n4 = *(const f32x4*)(ncs + tt + 4 * g);
-      const int jb = c0 + tt;
-#pragma unroll
-      for (int s = 0; s < SB; ++s) {
-        const f32x4 acc = tile_dot<KS, GBF>(av, xv[s], ab, xbv[s], n4);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float v = acc[r];
-          const bool gt = v > best[s];
-          sec[s] = fmaxf(sec[s], fminf(v, best[s]));
-          best[s] = fmaxf(best[s], v);
-          bidx[s] = gt ? (jb + r) : bidx[s];
-        }
-      }
-    }
   }
+  float* xrow = fred + 32 + 2 * 16 + wave * DP;   // per-wave row of a flagged sample
 
-  // Epilogue: combine the 4 lane groups, flag near ties, exact energy terms.
-  const float u = 5.9604644775390625e-8f;  // 2^-24
-  const float gam = 2.0f * ((float)(DP + 3) * u) / (1.0f - (float)(DP + 3) * u) * 1.001f;
+  const int64_t group_rows = 16 * SB * W;
+  const int64_t groups = (a.N + group_rows - 1) / group_rows;
+  const bool vec = (d == DP);
   double e_wave = 0.0;
   unsigned n_changed = 0, n_flag = 0;
-#pragma unroll
-  for (int s = 0; s < SB; ++s) {
-    const int64_t i = row0 + 16 * s + r16;
-    const bool valid = i < a.N;
-    float b = best[s], sc = sec[s];
-    int bi = bidx[s] + 4 * g;
-#pragma unroll
-    for (int off = 16; off <= 32; off <<= 1) {
-      const float ob = __shfl_xor(b, off, kWave);
-      const int oi = __shfl_xor(bi, off, kWave);
-      const float os = __shfl_xor(sc, off, kWave);
-      const float ns = fmaxf(fmaxf(sc, os), fminf(b, ob));
-      const bool take = (ob > b) || (ob == b && oi < bi);
-      b = take ? ob : b;
-      bi = take ? oi : bi;
-      sc = ns;
-    }
-    if (bi < 0 || bi >= K) bi = 0;
-    float xs = 0.f;
-#pragma unroll
-    for (int q = 0; q < KS; ++q) xs = fmaf(xv[s][q], xv[s][q], xs);
-    xs += __shfl_xor(xs, 16, kWave);
-    xs += __shfl_xor(xs, 32, kWave);
-    const float nx = sqrtf(xs) * 1.0001f;
-    float bound;
-    if (GBF) {
-      // s_j is computed from bf16(x) . bf16(c_j): |x.c - x^.c^| <= ex ||c|| + ||x^|| delta_j
-      float ex = 0.f;
-      if (!XBF) {
-        float e2 = xerr[s];
-        e2 += __shfl_xor(e2, 16, kWave);
-        e2 += __shfl_xor(e2, 32, kWave);
-        ex = sqrtf(e2) * 1.0001f;
-      }
-      const float cb = cmax + dmax;
-      bound = gam * (nx + ex + cb) * (nx + ex + cb) + 4.0f * (ex * cb + (nx + ex) * dmax);
-    } else {
-      bound = gam * (nx + cmax) * (nx + cmax);
-    }
-    const bool flag = valid && !((b - sc) > bound);
 
-    // exact energy term of the provisional label
-    double term;
-    {
-      const float* cr = a.C + (int64_t)bi * d + g * KS;
-      double p = 0.0;
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    // Sample rows of this wave, kept in registers.
+    const int64_t row0 = grp * group_rows + (int64_t)wave * (16 * SB);
+    float xv[SB][KS];
+    i16x8 xbv[SB][NB];
+    float xerr[SB];  // ||x - bf16(x)||^2 partial when float32 X feeds the bf16 GEMM
 #pragma unroll
-      for (int q = 0; q < KS; ++q) {
-        if (g * KS + q < d) {
-          const double df = (double)xv[s][q] - (double)cr[q];
-          p = fma(df, df, p);
+    for (int s = 0; s < SB; ++s) {
+      xerr[s] = 0.f;
+      const int64_t i = row0 + 16 * s + r16;
+      if (i < a.N) {
+        load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xv[s]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < KS; ++q) xv[s][q] = 0.f;
+      }
+      if constexpr (GBF) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint16_t hb = f32_to_bf16_rne(xv[s][8 * q + e]);
+            xbv[s][q][e] = (short)hb;
+            if (!XBF) {
+              const float df = xv[s][8 * q + e] - bf16_to_f32(hb);
+              xerr[s] = fmaf(df, df, xerr[s]);
+            }
+          }
+      }
+    }
+
+    float best[SB], sec[SB];
+    int bidx[SB];
+#pragma unroll
+    for (int s = 0; s < SB; ++s) { best[s] = -__builtin_inff(); sec[s] = -__builtin_inff(); bidx[s] = 0; }
+
+    for (int c0 = 0; c0 < Kpad; c0 += kchunk) {
+      const int rows = (Kpad - c0) < kchunk ? (Kpad - c0) : kchunk;
+      if (!resident) {
+        __syncthreads();
+        stage(c0, rows);
+        __syncthreads();
+      }
+      for (int tt = 0; tt < rows; tt += 16) {
+        f32x4 acc[SB];
+        tile_mfma<KS, SB, GBF>(Cs, Cbs, ncs, tt, g, r16, xv, xbv, acc);
+        const int jb = c0 + tt;
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float v = acc[s][r];
+            const bool gt = v > best[s];
+            // second best = median of (v, best, second) since second <= best
+            sec[s] = __builtin_amdgcn_fmed3f(v, best[s], sec[s]);
+            best[s] = vmax(v, best[s]);
+            bidx[s] = gt ? (jb + r) : bidx[s];
+          }
         }
       }
-      p += __shfl_xor(p, 16, kWave);
-      p += __shfl_xor(p, 32, kWave);
-      term = p;
     }
 
-    unsigned long long fm = __ballot(flag) & 0xFFFFull;
-    n_flag += (unsigned)__popcll(fm);
-    while (fm) {
-      const int f = __ffsll((long long)fm) - 1;
-      fm &= fm - 1;
-      double dist;
-      const int j = exact_argmin<XBF>(a.X, row0 + 16 * s + f, d, a.C, K, lane, &dist);
-      if (j >= 0 && r16 == f) { bi = j; term = dist; }
-    }
+    // Epilogue: combine the 4 lane groups, flag near ties, exact energy terms.
+    double e_lane = 0.0;
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int64_t i = row0 + 16 * s + r16;
+      const bool valid = i < a.N;
+      float b = best[s], sc = sec[s];
+      int bi = bidx[s] + 4 * g;
+#pragma unroll
+      for (int off = 16; off <= 32; off <<= 1) {
+        const float ob = __shfl_xor(b, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        const float os = __shfl_xor(sc, off, kWave);
+        const float ns = fmaxf(fmaxf(sc, os), fminf(b, ob));
+        const bool take = (ob > b) || (ob == b && oi < bi);
+        b = take ? ob : b;
+        bi = take ? oi : bi;
+        sc = ns;
+      }
+      if (bi < 0 || bi >= K) bi = 0;
+      float xs = 0.f;
+#pragma unroll
+      for (int q = 0; q < KS; ++q) xs = fmaf(xv[s][q], xv[s][q], xs);
+      xs += __shfl_xor(xs, 16, kWave);
+      xs += __shfl_xor(xs, 32, kWave);
+      const float nx = sqrtf(xs) * 1.0001f;
+      float bound;
+      if (GBF) {
+        // s_j is computed from bf16(x) . bf16(c_j): |x.c - x^.c^| <= ex ||c|| + ||x^|| delta_j
+        float ex = 0.f;
+        if (!XBF) {
+          float e2 = xerr[s];
+          e2 += __shfl_xor(e2, 16, kWave);
+          e2 += __shfl_xor(e2, 32, kWave);
+          ex = sqrtf(e2) * 1.0001f;
+        }
+        const float cb = cmax + dmax;
+        bound = gam * (nx + ex + cb) * (nx + ex + cb) + 4.0f * (ex * cb + (nx + ex) * dmax);
+      } else {
+        bound = gam * (nx + cmax) * (nx + cmax);
+      }
+      const bool flag = valid && !((b - sc) > bound);
 
-    bool ch = false;
-    if (valid && g == 0) {
-      rho[i] = bi;
-      ch = (prev != nullptr) && (prev[i] != bi);
+      // exact energy term of the provisional label
+      double term;
+      {
+        const float* cr = (resident && !GBF) ? Cs + bi * LD + g * KS : a.C + (int64_t)bi * d + g * KS;
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+          if (g * KS + q < d) {
+            const double df = (double)xv[s][q] - (double)cr[q];
+            p = fma(df, df, p);
+          }
+        }
+        p += __shfl_xor(p, 16, kWave);
+        p += __shfl_xor(p, 32, kWave);
+        term = p;
+      }
+
+      unsigned long long fm = __ballot(flag) & 0xFFFFull;
+      n_flag += (unsigned)__popcll(fm);
+      while (fm) {
+        const int f = __ffsll((long long)fm) - 1;
+        fm &= fm - 1;
+        double dist;
+        int j;
+        if (resident && !GBF) {
+          // the flagged row is spread over lanes r16 == f of the 4 lane groups
+          if (r16 == f) {
+#pragma unroll
+            for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xv[s][q];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+          j = exact_argmin<XBF>(a.X, row0 + 16 * s + f, d, a.C, K, lane, &dist);
+        }
+        if (j >= 0 && r16 == f) { bi = j; term = dist; }
+      }
+
+      bool ch = false;
+      if (valid && g == 0) {
+        rho[i] = bi;
+        ch = (prev != nullptr) && (prev[i] != bi);
+      }
+      n_changed += (unsigned)__popcll(__ballot(ch));
+      e_lane += (valid && g == 0) ? term : 0.0;
     }
-    n_changed += (unsigned)__popcll(__ballot(ch));
-    e_wave += wave_sum((valid && g == 0) ? term : 0.0);
+    e_wave += wave_sum(e_lane);
   }
 
   if (lane == 0) {
@@ -369,7 +502,12 @@ __global__ __launch_bounds__(256) void k_assign(AssignArgs a) {
     if (n_flag) atomicAdd(&ctl->cnt_flagged[slot], (unsigned long long)n_flag);
   }
   __syncthreads();
-  if (tid == 0) a.e_part[blockIdx.x] = ((dred[0] + dred[1]) + dred[2]) + dred[3];
+  if (tid == 0) {
+    double e = dred[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) e += dred[w];
+    a.e_part[blockIdx.x] = e;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -388,86 +526,133 @@ static int pick_ks(int d, int gemm_bf16) {
   return -1;
 }
 
-static int pick_sb(int ks) { return ks <= 16 ? 4 : (ks <= 32 ? 2 : 1); }
+struct KernelPick {
+  const void* fn = nullptr;
+  int rows = 0;        // samples per row group (16 * SB * W)
+  int threads = 0;     // 64 * W
+  size_t lds = 0;
+};
 
-int assign_grid(int64_t N, int d, int gemm_bf16) {
-  const int ks = pick_ks(d, gemm_bf16);
-  if (ks < 0) return -1;
-  const int64_t rows = 64 * pick_sb(ks);
-  return (int)((N + rows - 1) / rows);
+// Tile shapes (SB sample blocks per wave, W waves per workgroup) per KS.
+// The default comes from measurements on MI355X; KM_ASSIGN_SHAPE=<n>
+// selects an alternative for tuning runs.
+template <int KS, int ROLE, bool XBF, bool GBF, int SB, int W>
+static KernelPick make_pick(int K) {
+  KernelPick p;
+  p.fn = (const void*)&k_assign<KS, SB, W, ROLE, XBF, GBF>;
+  p.rows = 16 * SB * W;
+  p.threads = 64 * W;
+  p.lds = Tile<KS, GBF>::lds_bytes(K);
+  return p;
 }
 
-static size_t assign_lds(int ks, int K, int gbf) {
-  const int DP = 4 * ks;
-  const int Kpad = (K + 15) & ~15;
-  if (gbf) {
-    const int LDB = DP + 8;
-    int chunk = (65536 / (LDB * 2 + 4)) & ~15;
-    if (chunk > Kpad) chunk = Kpad;
-    return (size_t)chunk * LDB * 2 + (size_t)chunk * 4 + 8 * 4 + 4 * 8;
+static int shape_override() {
+  static int v = -2;
+  if (v == -2) {
+    const char* e = getenv("KM_ASSIGN_SHAPE");
+    v = e ? atoi(e) : -1;
   }
-  const int LD = DP + 4;
-  int chunk = (65536 / (LD * 4 + 4)) & ~15;
-  if (chunk > Kpad) chunk = Kpad;
-  return (size_t)chunk * LD * 4 + (size_t)chunk * 4 + 8 * 4 + 4 * 8;
+  return v;
 }
 
 template <int KS, int ROLE, bool XBF, bool GBF>
-static hipError_t go(const AssignArgs& a, hipStream_t s) {
-  constexpr int SB = KS <= 16 ? 4 : (KS <= 32 ? 2 : 1);
-  const int64_t rows = 64 * SB;
-  const int grid = (int)((a.N + rows - 1) / rows);
-  const size_t lds = assign_lds(KS, a.K, GBF);
-  hipLaunchKernelGGL((k_assign<KS, SB, ROLE, XBF, GBF>), dim3(grid), dim3(256), lds, s, a);
-  return hipGetLastError();
+static KernelPick pick_one(int K) {
+  constexpr int SB0 = KS <= 16 ? 4 : (KS <= 32 ? 2 : 1);
+  // alternative shapes are only built for the benchmark widths (d = 32 in
+  // float32, d = 128 in bfloat16) and the candidate role
+  if constexpr (ROLE == kRoleCand && ((KS == 8 && !GBF) || (KS == 32 && GBF))) {
+    switch (shape_override()) {
+      case 1: return make_pick<KS, ROLE, XBF, GBF, (SB0 > 1 ? SB0 / 2 : 1), 8>(K);
+      case 2: return make_pick<KS, ROLE, XBF, GBF, (SB0 > 1 ? SB0 / 2 : 1), 4>(K);
+      case 3: return make_pick<KS, ROLE, XBF, GBF, SB0, 8>(K);
+      default: break;
+    }
+  }
+  return make_pick<KS, ROLE, XBF, GBF, SB0, 4>(K);
 }
 
 template <int ROLE, bool XBF, bool GBF>
-static hipError_t dispatch_ks(const AssignArgs& a, hipStream_t s) {
-  const int ks = pick_ks(a.d, GBF);
+static KernelPick pick_ks_role(int d, int K) {
+  const int ks = pick_ks(d, GBF);
   if constexpr (GBF) {
     switch (ks) {
-      case 8: return go<8, ROLE, XBF, GBF>(a, s);
-      case 16: return go<16, ROLE, XBF, GBF>(a, s);
-      case 24: return go<24, ROLE, XBF, GBF>(a, s);
-      case 32: return go<32, ROLE, XBF, GBF>(a, s);
-      case 48: return go<48, ROLE, XBF, GBF>(a, s);
-      case 64: return go<64, ROLE, XBF, GBF>(a, s);
-      default: return hipErrorInvalidValue;
+      case 8: return pick_one<8, ROLE, XBF, GBF>(K);
+      case 16: return pick_one<16, ROLE, XBF, GBF>(K);
+      case 24: return pick_one<24, ROLE, XBF, GBF>(K);
+      case 32: return pick_one<32, ROLE, XBF, GBF>(K);
+      case 48: return pick_one<48, ROLE, XBF, GBF>(K);
+      case 64: return pick_one<64, ROLE, XBF, GBF>(K);
     }
   } else {
     switch (ks) {
-      case 1: return go<1, ROLE, XBF, GBF>(a, s);
-      case 2: return go<2, ROLE, XBF, GBF>(a, s);
-      case 4: return go<4, ROLE, XBF, GBF>(a, s);
-      case 8: return go<8, ROLE, XBF, GBF>(a, s);
-      case 12: return go<12, ROLE, XBF, GBF>(a, s);
-      case 16: return go<16, ROLE, XBF, GBF>(a, s);
-      case 24: return go<24, ROLE, XBF, GBF>(a, s);
-      case 32: return go<32, ROLE, XBF, GBF>(a, s);
-      case 48: return go<48, ROLE, XBF, GBF>(a, s);
-      case 64: return go<64, ROLE, XBF, GBF>(a, s);
-      default: return hipErrorInvalidValue;
+      case 1: return pick_one<1, ROLE, XBF, GBF>(K);
+      case 2: return pick_one<2, ROLE, XBF, GBF>(K);
+      case 4: return pick_one<4, ROLE, XBF, GBF>(K);
+      case 8: return pick_one<8, ROLE, XBF, GBF>(K);
+      case 12: return pick_one<12, ROLE, XBF, GBF>(K);
+      case 16: return pick_one<16, ROLE, XBF, GBF>(K);
+      case 24: return pick_one<24, ROLE, XBF, GBF>(K);
+      case 32: return pick_one<32, ROLE, XBF, GBF>(K);
+      case 48: return pick_one<48, ROLE, XBF, GBF>(K);
+      case 64: return pick_one<64, ROLE, XBF, GBF>(K);
     }
   }
+  return KernelPick();
 }
 
 template <int ROLE>
-static hipError_t dispatch_types(const AssignArgs& a, hipStream_t s) {
-  if (a.gemm_bf16) {
-    return a.xbf16 ? dispatch_ks<ROLE, true, true>(a, s) : dispatch_ks<ROLE, false, true>(a, s);
+static KernelPick pick_types(const AssignArgs& a) {
+  if (a.gemm_bf16)
+    return a.xbf16 ? pick_ks_role<ROLE, true, true>(a.d, a.K) : pick_ks_role<ROLE, false, true>(a.d, a.K);
+  return a.xbf16 ? pick_ks_role<ROLE, true, false>(a.d, a.K) : pick_ks_role<ROLE, false, false>(a.d, a.K);
+}
+
+static KernelPick pick(const AssignArgs& a, Role role) {
+  switch (role) {
+    case kRolePlain: return pick_types<kRolePlain>(a);
+    case kRoleCand: return pick_types<kRoleCand>(a);
+    case kRoleFallback: return pick_types<kRoleFallback>(a);
   }
-  return a.xbf16 ? dispatch_ks<ROLE, true, false>(a, s) : dispatch_ks<ROLE, false, false>(a, s);
+  return KernelPick();
+}
+
+// Persistent grid: as many workgroups as fit on the device at once (queried
+// once per kernel instance), never more than there are row groups.
+int assign_grid(const AssignArgs& a) {
+  if (a.N <= 0 || a.K <= 0 || a.d <= 0 || a.d > kMaxD || a.K > kMaxK) return -1;
+  const KernelPick p = pick(a, kRoleCand);
+  if (!p.fn) return -1;
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+      clear_pending_error();
+      cus = 256;
+    }
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.fn, p.threads, p.lds) != hipSuccess ||
+      per_cu <= 0) {
+    clear_pending_error();
+    per_cu = 1;
+  }
+  const int64_t groups = (a.N + p.rows - 1) / p.rows;
+  int64_t resident = (int64_t)per_cu * cus;
+  if (const char* e = getenv("KM_ASSIGN_GRID_MULT")) resident *= atoi(e) > 0 ? atoi(e) : 1;
+  return (int)(groups < resident ? groups : resident);
 }
 
 hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s) {
   if (a.N <= 0 || a.K <= 0 || a.d <= 0 || a.d > kMaxD || a.K > kMaxK) return hipErrorInvalidValue;
-  switch (role) {
-    case kRolePlain: return dispatch_types<kRolePlain>(a, s);
-    case kRoleCand: return dispatch_types<kRoleCand>(a, s);
-    case kRoleFallback: return dispatch_types<kRoleFallback>(a, s);
-  }
-  return hipErrorInvalidValue;
+  const KernelPick p = pick(a, role);
+  if (!p.fn) return hipErrorInvalidValue;
+  const int grid = assign_grid(a);
+  if (grid <= 0) return hipErrorInvalidValue;
+  AssignArgs arg = a;
+  void* params[] = {&arg};
+  clear_pending_error();
+  return hipLaunchKernel(p.fn, dim3(grid), dim3(p.threads), params, p.lds, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -501,6 +686,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* C, int K, int d, floa
 
 hipError_t launch_prep(const float* C, int K, int d, float* nc, uint16_t* Cb, float* delta,
                        hipStream_t s) {
+  clear_pending_error();
   hipLaunchKernelGGL(k_prep, dim3((K + 3) / 4), dim3(256), 0, s, C, K, d, nc, Cb, delta);
   return hipGetLastError();
 }
@@ -518,7 +704,22 @@ __global__ __launch_bounds__(256) void k_reduce_energy(const double* e_part, int
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// One workgroup: the controller stage that closes a pass (stage 1 after the
+// candidate, stage 2 after the optional fall-back).
+__global__ __launch_bounds__(256) void k_controller(CtlArgs a) {
+  __shared__ double red[256];
+  if (a.ctl->done) return;
+  controller_stage(a.ctl, a.e_part, a.n_part, a.stage, a.tr, red);
+}
+
+hipError_t launch_controller(const CtlArgs& a, hipStream_t s) {
+  clear_pending_error();
+  hipLaunchKernelGGL(k_controller, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_energy(const double* e_part, int n, double* out, hipStream_t s) {
+  clear_pending_error();
   hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(256), 0, s, e_part, n, out);
   return hipGetLastError();
 }

@@ -73,6 +73,10 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// Drop a pending error of an unrelated earlier runtime call so that the
+// check after a launch reports that launch only.
+inline void clear_pending_error() { (void)hipGetLastError(); }
+
 __device__ __forceinline__ unsigned popc64(unsigned long long m) { return __popcll(m); }
 
 }  // namespace km

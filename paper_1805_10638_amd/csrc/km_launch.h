@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "km_common.h"
+#include "km_ctl.h"
 
 namespace km {
 
@@ -19,12 +20,12 @@ struct AssignArgs {
   const float* delta;     // K norms ||c_j - bf16(c_j)|| (bf16 GEMM only)
   int* lab;               // label buffers: 3 x N (solver roles) or N (plain role)
   const int* lab_prev;    // plain role: labels to count changes against, or null
-  double* e_part;         // per-workgroup energy partials
+  double* e_part;         // per-workgroup energy partials of this pass
   Ctl* ctl;
   int xbf16;              // X stored as bfloat16
   int gemm_bf16;          // distance GEMM in bfloat16
 };
-int assign_grid(int64_t N, int d, int gemm_bf16);   // workgroups of one launch
+int assign_grid(const AssignArgs& a);   // workgroups of one launch (persistent grid)
 hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s);
 
 // ||c_j||^2 (and the bfloat16 shadow with its error norms when Cb != null).
@@ -39,7 +40,7 @@ struct UpdateArgs {
   int* lab;               // label buffers base (3 x N) or the labels themselves
   int lab_from_ctl;       // 1: labels = lab + ctl->lab_prev * N
   int* lrank;             // N
-  int* blockcount;        // nblk x K, overwritten with per-block offsets
+  int* blockcount;        // K x nblk, overwritten with per-block offsets
   int* counts;            // K
   int* seg_start;         // K + 1
   int* item_start;        // K + 1
@@ -63,14 +64,8 @@ struct FinalizeArgs {
   const int* counts;
   const float* C_in;      // kFinG / kFinInit: centroids G was applied to
   float* C_out;           // kFinG: output means
-  // solver buffers
-  const float* C_cand;
-  float* C_cand_w;        // kFinInit writes C^1 here
-  float* nc_cand;
-  float* C_fb;            // fall-back iterate fl32(G^t), read as C^t when acc_src == 1
-  float* nc_fb;
-  uint16_t* Cb_cand; float* delta_cand;   // bf16 shadows (may be null)
-  uint16_t* Cb_fb; float* delta_fb;
+  const float* C_cand;    // candidate C^t
+  const float* C_fb;      // fall-back iterate, C^t when ctl->acc_src == 1
   double* G_last;         // K x d
   double* F_last;         // K x d
   double* ring_dF;        // cap x K x d
@@ -79,22 +74,20 @@ struct FinalizeArgs {
   Ctl* ctl;
   FinMode mode;
 };
-int finalize_grid(int K);
+int finalize_grid(int64_t KD);
 hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s);
 
-// ----- controller and Anderson step (Sec. 2.1, Sec. 2.2, Algorithm 1) -----
+// ----- controller (Algorithm 1) -----
 struct CtlArgs {
   Ctl* ctl;
   const double* e_part;   // partials of the pass being decided
   int n_part;
   int stage;              // 1: after the candidate pass, 2: after the fall-back pass
-  const float* C_cand;    // for the trace
-  int K, d;
-  float* trace_C;
-  double* trace_rec;
+  CtlTrace tr;
 };
-hipError_t launch_controller(const CtlArgs& c, hipStream_t s);
+hipError_t launch_controller(const CtlArgs& a, hipStream_t s);
 
+// ----- Anderson step (Sec. 2.1, Eq. (7)-(8)) -----
 struct SolveArgs {
   Ctl* ctl;
   const double* dots;
@@ -107,13 +100,12 @@ hipError_t launch_ls_solve(const SolveArgs& a, hipStream_t s);
 
 struct CombineArgs {
   Ctl* ctl;
+  int gated;              // 1: solver iteration (uses theta); 0: C^1 = G^0
   const double* G_last;
   const double* ring_dG;
   int K, d, cap;
-  float* C_cand;
-  float* nc_cand;
-  uint16_t* Cb_cand;
-  float* delta_cand;
+  float* C_cand; float* nc_cand; uint16_t* Cb_cand; float* delta_cand;
+  float* C_fb; float* nc_fb; uint16_t* Cb_fb; float* delta_fb;
 };
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s);
 

@@ -1,21 +1,24 @@
 // Update step (Sec. 1, Eq. (4)): c_j = mean of the samples labelled j.
 //
-// Deterministic and atomic-free in floating point:
+// Deterministic and free of floating-point atomics:
 //   1. k_rank     stable within-block ranks of every label (wave match by
-//                 ballots, per-wave LDS counters) and a per-block histogram;
-//   2. k_scan     per-label exclusive prefix of the block histograms;
+//                 ballots, per-wave LDS counters) and each block's histogram,
+//                 stored label-major: blockcount[j][b];
+//   2. k_scan     one workgroup per label: exclusive prefix of its block
+//                 counts (the offset of block b inside segment j) and the
+//                 cluster size N_j;
 //   3. k_offsets  segment starts and the list of work items, each item being
-//                 at most kSegRows consecutive samples of one cluster;
-//   4. k_scatter  perm[segment start + block offset + rank] = i  (a stable
-//                 counting sort by label);
+//                 at most kSegRows consecutive sorted samples of one cluster;
+//   4. k_scatter  perm[start_j + offset_jb + rank] = i: a stable counting sort;
 //   5. k_segsum   one workgroup per item gathers its rows and sums them in
 //                 float64, reducing across row groups through LDS in a fixed
 //                 order;
-//   6. k_finalize sums the items of each cluster in order and divides by the
-//                 count (an empty cluster keeps its centroid).  In the solver
-//                 it also forms the residual F = G - C, pushes the newest
-//                 differences of F and G into the history ring and emits the
-//                 partial inner products of the Anderson Gram matrix.
+//   6. k_finalize one thread per centroid element: sums the items of its
+//                 cluster in order and divides by N_j (an empty cluster keeps
+//                 its centroid).  In the solver it also forms the residual
+//                 F = G - C, pushes the newest differences of F and G into the
+//                 history ring and emits per-workgroup partial inner products
+//                 for the Anderson Gram matrix.
 
 #include "km_launch.h"
 
@@ -33,22 +36,28 @@ __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) {
   __shared__ int cnt[4][kMaxK];
   const int* L = labels_of(u);
   const int K = u.K;
+  const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int kChunks = kRankRows / 256;   // 64-row chunks per wave
+  const int64_t base = (int64_t)blockIdx.x * kRankRows + (int64_t)w * (kChunks * 64);
+  int labs[kChunks], rk[kChunks];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const int64_t i = base + c * 64 + lane;
+    int lab = (i < u.N) ? L[i] : 0;
+    labs[c] = (lab < 0 || lab >= K) ? 0 : lab;
+  }
   for (int j = tid; j < 4 * K; j += 256) cnt[j / K][j % K] = 0;
   __syncthreads();
 
   int nbits = 0;
   while ((1 << nbits) < K) ++nbits;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  constexpr int kChunks = kRankRows / 256;   // 64-row chunks per wave
-  int labs[kChunks], rk[kChunks];
-  const int64_t base = (int64_t)blockIdx.x * kRankRows + (int64_t)w * (kChunks * 64);
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
     const int64_t i = base + c * 64 + lane;
     const bool valid = i < u.N;
-    int lab = valid ? L[i] : 0;
-    if (lab < 0 || lab >= K) lab = 0;
+    const int lab = labs[c];
     unsigned long long m = __ballot(valid);
     for (int b = 0; b < nbits; ++b) {
       const bool bit = (lab >> b) & 1;
@@ -60,7 +69,6 @@ __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) {
     const int tot = __popcll(m);
     const int prior = valid ? cnt[w][lab] : 0;
     rk[c] = prior + before;
-    labs[c] = lab;
     if (valid && before == tot - 1) cnt[w][lab] = prior + tot;
   }
   __syncthreads();
@@ -72,7 +80,7 @@ __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) {
       cnt[ww][j] = s;
       s += v;
     }
-    u.blockcount[(int64_t)blockIdx.x * K + j] = s;
+    u.blockcount[(int64_t)j * nblk + blockIdx.x] = s;
   }
   __syncthreads();
 #pragma unroll
@@ -83,57 +91,58 @@ __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) {
 }
 
 // ---------------------------------------------------------------------------
-// 2. per-label prefix over blocks (64 labels x 4 block ranges per workgroup)
+// Workgroup-wide exclusive scan of one int per thread (256 threads).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scan(UpdateArgs u, int nblk) {
-  if (u.gated && u.ctl->done) return;
-  __shared__ int part[4][64];
-  const int K = u.K;
-  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int p = threadIdx.x >> 6;
-  const int b0 = (int)((int64_t)nblk * p / 4), b1 = (int)((int64_t)nblk * (p + 1) / 4);
-  int s = 0;
-  if (j < K)
-    for (int b = b0; b < b1; ++b) s += u.blockcount[(int64_t)b * K + j];
-  part[p][threadIdx.x & 63] = s;
-  __syncthreads();
-  int run = 0;
-  for (int q = 0; q < p; ++q) run += part[q][threadIdx.x & 63];
-  if (j < K) {
-    for (int b = b0; b < b1; ++b) {
-      const int64_t idx = (int64_t)b * K + j;
-      const int v = u.blockcount[idx];
-      u.blockcount[idx] = run;
-      run += v;
-    }
-    if (p == 3) u.counts[j] = run;
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(v, off, kWave);
+    if (lane >= off) v += o;
   }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// 2. per-label prefix over blocks: one workgroup per label
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan(UpdateArgs u) {
+  if (u.gated && u.ctl->done) return;
+  __shared__ int wsum[4];
+  __shared__ int carry;
+  const int j = blockIdx.x;
+  const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int* row = u.blockcount + (int64_t)j * nblk;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nblk; b0 += 256) {
+    const int b = b0 + tid;
+    const int v = (b < nblk) ? row[b] : 0;
+    const int inc = wave_incl_scan(v, lane);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int before = carry;
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    if (b < nblk) row[b] = before + inc - v;
+    __syncthreads();
+    if (tid == 255) carry = before + inc;
+    __syncthreads();
+  }
+  if (tid == 0) u.counts[j] = carry;
 }
 
 // ---------------------------------------------------------------------------
 // 3. segment starts and work items (one workgroup of 1024 threads)
 // ---------------------------------------------------------------------------
-__device__ int block_exclusive_scan_1024(int v, int* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int add = (t >= off) ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  const int incl = sh[t];
-  __syncthreads();
-  return incl - v;
-}
-
 __global__ __launch_bounds__(1024) void k_offsets(UpdateArgs u) {
   if (u.gated && u.ctl->done) return;
-  __shared__ int sh[1024];
+  __shared__ int wc[16], wi[16];
+  __shared__ int empty_sh;
   const int K = u.K;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int per = (K + 1023) / 1024;
-  const int j0 = threadIdx.x * per;
+  const int j0 = tid * per;
+  if (tid == 0) empty_sh = 0;
   int csum = 0, isum = 0, empty = 0;
   for (int j = j0; j < j0 + per && j < K; ++j) {
     const int c = u.counts[j];
@@ -141,9 +150,13 @@ __global__ __launch_bounds__(1024) void k_offsets(UpdateArgs u) {
     isum += (c + kSegRows - 1) / kSegRows;
     empty += (c == 0);
   }
-  int cbase = block_exclusive_scan_1024(csum, sh);
-  int ibase = block_exclusive_scan_1024(isum, sh);
-  int etot = block_exclusive_scan_1024(empty, sh) + empty;   // inclusive at the last thread
+  const int ci = wave_incl_scan(csum, lane);
+  const int ii = wave_incl_scan(isum, lane);
+  if (lane == 63) { wc[w] = ci; wi[w] = ii; }
+  __syncthreads();
+  if (empty) atomicAdd(&empty_sh, empty);
+  int cbase = ci - csum, ibase = ii - isum;
+  for (int q = 0; q < w; ++q) { cbase += wc[q]; ibase += wi[q]; }
   for (int j = j0; j < j0 + per && j < K; ++j) {
     const int c = u.counts[j];
     const int ni = (c + kSegRows - 1) / kSegRows;
@@ -154,11 +167,12 @@ __global__ __launch_bounds__(1024) void k_offsets(UpdateArgs u) {
     cbase += c;
     ibase += ni;
   }
-  if (threadIdx.x == 1023) {
+  __syncthreads();
+  if (tid == 1023) {
     u.seg_start[K] = cbase;
     u.item_start[K] = ibase;
     u.ctl->total_items = ibase < u.max_items ? ibase : u.max_items;
-    u.ctl->empty = etot;
+    u.ctl->empty = empty_sh;
   }
 }
 
@@ -170,10 +184,11 @@ __global__ __launch_bounds__(256) void k_scatter(UpdateArgs u) {
   const int* L = labels_of(u);
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= u.N) return;
+  const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
   int lab = L[i];
   if (lab < 0 || lab >= u.K) lab = 0;
   const int64_t b = i / kRankRows;
-  const int64_t pos = (int64_t)u.seg_start[lab] + u.blockcount[b * u.K + lab] + u.lrank[i];
+  const int64_t pos = (int64_t)u.seg_start[lab] + u.blockcount[(int64_t)lab * nblk + b] + u.lrank[i];
   if (pos >= 0 && pos < u.N) u.perm[pos] = (int)i;
 }
 
@@ -193,7 +208,7 @@ __global__ __launch_bounds__(256) void k_segsum(UpdateArgs u) {
   const int64_t pend = (int64_t)u.seg_start[j] + u.counts[j];
   const int64_t p1 = (p0 + kSegRows < pend) ? p0 + kSegRows : pend;
 
-  // threads per row: power of two covering ceil(d/4) float4 columns (<= 64)
+  // threads per row: power of two covering ceil(d/4) four-element columns
   int tpr = 1;
   while (tpr * 4 < d) tpr <<= 1;
   const int rpp = 256 / tpr;                 // rows per pass
@@ -248,9 +263,13 @@ int update_max_items(int64_t N, int K) { return (int)((N + kSegRows - 1) / kSegR
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
   if (u.K > kMaxK || u.d > kMaxD) return hipErrorInvalidValue;
   const int nblk = update_rank_blocks(u.N);
+  clear_pending_error();
   hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(256), 0, s, u);
-  hipLaunchKernelGGL(k_scan, dim3((u.K + 63) / 64), dim3(256), 0, s, u, nblk);
+  clear_pending_error();
+  hipLaunchKernelGGL(k_scan, dim3(u.K), dim3(256), 0, s, u);
+  clear_pending_error();
   hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, u);
+  clear_pending_error();
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)((u.N + 255) / 256)), dim3(256), 0, s, u);
   if (u.xbf16)
     hipLaunchKernelGGL(k_segsum<true>, dim3(u.max_items), dim3(256), 0, s, u);
@@ -260,130 +279,100 @@ hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// 6. means, residual, history push and Gram partials (one wave per cluster)
+// 6. means, residual, history push and Gram partials (one thread per element)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t x = __float_as_uint(f);
-  x += 0x7FFFu + ((x >> 16) & 1u);
-  return (uint16_t)(x >> 16);
-}
-
-// Writes fl32(v) into C and returns its float32 value; also the bf16 shadow.
-__device__ __forceinline__ float store_centroid(float* C, uint16_t* Cb, int64_t idx, double v,
-                                                double* err2) {
-  const float f = (float)v;
-  C[idx] = f;
-  if (Cb) {
-    const uint16_t b = f32_to_bf16(f);
-    Cb[idx] = b;
-    const double df = (double)f - (double)__uint_as_float(((uint32_t)b) << 16);
-    *err2 = fma(df, df, *err2);
-  }
-  return f;
-}
+constexpr int kDotGroup = 8;    // history slots reduced per pass over the elements
 
 __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
   Ctl* ctl = f.ctl;
   if (f.mode == kFinIter && ctl->done) return;
-  __shared__ double wsum[4][2 * kMaxM];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int j = blockIdx.x * 4 + w;
+  __shared__ double red[2 * kDotGroup][256];
+  const int tid = threadIdx.x;
   const int d = f.d, cap = f.cap;
-  const bool active = j < f.K;
+  const int64_t KD = (int64_t)f.K * d;
+  const int64_t stride = (int64_t)gridDim.x * 256;
 
-  int s_new = 0, len_new = 0, head = 0;
+  int s_new = 0, len_new = 0;
   if (f.mode == kFinIter && cap > 0) {
-    head = ctl->hist_head;
-    s_new = (ctl->hist_len == 0) ? 0 : (head + 1) % cap;
+    s_new = (ctl->hist_len == 0) ? 0 : (ctl->hist_head + 1) % cap;
     len_new = ctl->hist_len + 1 < cap ? ctl->hist_len + 1 : cap;
   }
   const float* Cacc = (f.mode == kFinIter && ctl->acc_src == 1) ? f.C_fb : f.C_cand;
-  const int64_t KD = (int64_t)f.K * d;
 
-  if (active) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < KD; e += stride) {
+    const int j = (int)(e / d);
     const int n = f.counts[j];
     const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
-    double nsq_fb = 0.0, e_fb = 0.0, nsq_c = 0.0, e_c = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      double sum = 0.0;
-      for (int it = i0; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
-      const int64_t e = (int64_t)j * d + k;
-      if (f.mode == kFinG) {
-        const double gv = n > 0 ? sum / (double)n : (double)f.C_in[e];
-        f.C_out[e] = (float)gv;
-        continue;
-      }
-      const double cin = (f.mode == kFinInit) ? (double)f.C_in[e] : (double)Cacc[e];
-      const double gv = n > 0 ? sum / (double)n : cin;
-      const double fv = gv - cin;
-      if (f.mode == kFinIter && cap > 0) {
-        f.ring_dF[(int64_t)s_new * KD + e] = fv - f.F_last[e];
-        f.ring_dG[(int64_t)s_new * KD + e] = gv - f.G_last[e];
-      }
-      f.G_last[e] = gv;
-      f.F_last[e] = fv;
-      const float gf = store_centroid(f.C_fb, f.Cb_fb, e, gv, &e_fb);
-      nsq_fb = fma((double)gf, (double)gf, nsq_fb);
-      if (f.mode == kFinInit) {
-        const float cf = store_centroid(f.C_cand_w, f.Cb_cand, e, gv, &e_c);
-        nsq_c = fma((double)cf, (double)cf, nsq_c);
-      }
+    const int k = (int)(e - (int64_t)j * d);
+    double sum = 0.0;
+    for (int it = i0; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
+    if (f.mode == kFinG) {
+      f.C_out[e] = (float)(n > 0 ? sum / (double)n : (double)f.C_in[e]);
+      continue;
     }
-    if (f.mode != kFinG) {
-      nsq_fb = wave_sum(nsq_fb);
-      e_fb = wave_sum(e_fb);
-      if (lane == 0) {
-        f.nc_fb[j] = (float)nsq_fb;
-        if (f.Cb_fb) f.delta_fb[j] = (float)sqrt(e_fb);
-      }
-      if (f.mode == kFinInit) {
-        nsq_c = wave_sum(nsq_c);
-        e_c = wave_sum(e_c);
-        if (lane == 0) {
-          f.nc_cand[j] = (float)nsq_c;
-          if (f.Cb_cand) f.delta_cand[j] = (float)sqrt(e_c);
-        }
-      }
+    const double cin = (f.mode == kFinInit) ? (double)f.C_in[e] : (double)Cacc[e];
+    const double gv = n > 0 ? sum / (double)n : cin;
+    const double fv = gv - cin;
+    if (f.mode == kFinIter && cap > 0) {
+      f.ring_dF[(int64_t)s_new * KD + e] = fv - f.F_last[e];
+      f.ring_dG[(int64_t)s_new * KD + e] = gv - f.G_last[e];
     }
+    f.G_last[e] = gv;
+    f.F_last[e] = fv;
   }
   if (f.mode != kFinIter || cap == 0) return;
 
-  // Partial inner products for the Gram matrix: for every valid slot s,
-  // <dF_new, dF_s> (index s) and <dF_s, F^t> (index cap + s).  Each lane
-  // reads back only elements it wrote above.
-  for (int q = 0; q < len_new; ++q) {
-    const int sl = (s_new - q + cap) % cap;
-    double a = 0.0, b = 0.0;
-    if (active) {
-      for (int k = lane; k < d; k += kWave) {
-        const int64_t e = (int64_t)j * d + k;
-        const double dfs = f.ring_dF[(int64_t)sl * KD + e];
-        a = fma(f.ring_dF[(int64_t)s_new * KD + e], dfs, a);
-        b = fma(dfs, f.F_last[e], b);
+  // Gram partials: for each valid slot sl, <dF_new, dF_sl> (index sl) and
+  // <dF_sl, F^t> (index cap + sl).  Each thread reads back only the elements
+  // it wrote above.
+  for (int q0 = 0; q0 < len_new; q0 += kDotGroup) {
+    double pa[kDotGroup], pb[kDotGroup];
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) { pa[g] = 0.0; pb[g] = 0.0; }
+    for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < KD; e += stride) {
+      const double dfn = f.ring_dF[(int64_t)s_new * KD + e];
+      const double fv = f.F_last[e];
+#pragma unroll
+      for (int g = 0; g < kDotGroup; ++g) {
+        if (q0 + g < len_new) {
+          const int sl = (s_new - (q0 + g) + cap) % cap;
+          const double dfs = f.ring_dF[(int64_t)sl * KD + e];
+          pa[g] = fma(dfn, dfs, pa[g]);
+          pb[g] = fma(dfs, fv, pb[g]);
+        }
       }
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) {
-      wsum[w][sl] = a;
-      wsum[w][cap + sl] = b;
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+      red[g][tid] = pa[g];
+      red[kDotGroup + g][tid] = pb[g];
     }
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < len_new; q += 256) {
-    const int sl = (s_new - q + cap) % cap;
-    f.dots[(int64_t)blockIdx.x * 2 * cap + sl] =
-        ((wsum[0][sl] + wsum[1][sl]) + wsum[2][sl]) + wsum[3][sl];
-    f.dots[(int64_t)blockIdx.x * 2 * cap + cap + sl] =
-        ((wsum[0][cap + sl] + wsum[1][cap + sl]) + wsum[2][cap + sl]) + wsum[3][cap + sl];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if (tid < w) {
+#pragma unroll
+        for (int g = 0; g < 2 * kDotGroup; ++g) red[g][tid] += red[g][tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid < kDotGroup && q0 + tid < len_new) {
+      const int sl = (s_new - (q0 + tid) + cap) % cap;
+      f.dots[(int64_t)blockIdx.x * 2 * cap + sl] = red[tid][0];
+      f.dots[(int64_t)blockIdx.x * 2 * cap + cap + sl] = red[kDotGroup + tid][0];
+    }
+    __syncthreads();
   }
 }
 
-int finalize_grid(int K) { return (K + 3) / 4; }
+int finalize_grid(int64_t KD) {
+  const int64_t g = (KD + 255) / 256;
+  return (int)(g < 128 ? (g > 0 ? g : 1) : 128);
+}
 
 hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s) {
   if (f.cap > kMaxM) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_finalize, dim3(finalize_grid(f.K)), dim3(256), 0, s, f);
+  clear_pending_error();
+  hipLaunchKernelGGL(k_finalize, dim3(finalize_grid((int64_t)f.K * f.d)), dim3(256), 0, s, f);
   return hipGetLastError();
 }
 
