@@ -13,127 +13,152 @@
 
 namespace km {
 
-__global__ __launch_bounds__(64) void k_ls_solve(SolveArgs a) {
-  Ctl* c = a.ctl;
-  if (c->done) return;
+constexpr int kSmallLs = 12;   // systems up to this size are solved in registers
+
+// Least squares of Eq. (7) on the newest m_t history columns, solved by
+// wave 0 of the calling workgroup (every workgroup of the combine launch
+// solves the same tiny system; results are identical).  Column q (0-based,
+// newest first) lives in ring slot (s_new - q) mod cap.  Entries of the Gram
+// matrix that involve the newest column come from this iteration's partial
+// inner products; older entries from the stored Gram matrix.  Writes theta
+// (zero for dropped columns) to th[0..mt) and returns the number of columns
+// used (0 when the factorisation fails).
+__device__ int ls_solve_group(const CombineArgs& a, int s_new, int len_new, int mt, double ridge,
+                              double* th, double* newrow, double* bvec, double* Lm, double* sc, int* cols,
+                              int* misc) {
   const int cap = a.cap;
-  const int lane = threadIdx.x;
-  if (cap == 0) {
-    if (lane == 0) { c->mt = 0; c->used = 0; c->cand_is_lloyd = 1; }
-    return;
-  }
-  __shared__ double bvec[kMaxM];
-  __shared__ double L[kMaxM * kMaxM];
-  __shared__ double sc[kMaxM], y[kMaxM];
-  __shared__ int cols[kMaxM];
-  __shared__ int n_sh, ok_sh;
-
-  const int s_new = (c->hist_len == 0) ? 0 : (c->hist_head + 1) % cap;
-  const int len_new = c->hist_len + 1 < cap ? c->hist_len + 1 : cap;
-  int mt = c->m < c->t ? c->m : c->t;
-  if (mt > len_new) mt = len_new;
-
-  // new Gram row and right-hand side: fixed-order sums of per-workgroup partials
-  for (int q = lane; q < len_new; q += 64) {
+  const int tid = threadIdx.x;
+  // fixed-order sums of the per-workgroup partials: new Gram row and rhs
+  for (int q = tid; q < len_new; q += blockDim.x) {
     const int sl = (s_new - q + cap) % cap;
     double ga = 0.0, gb = 0.0;
     for (int w = 0; w < a.n_dots; ++w) {
       ga += a.dots[(int64_t)w * 2 * cap + sl];
       gb += a.dots[(int64_t)w * 2 * cap + cap + sl];
     }
-    a.gram[s_new * cap + sl] = ga;
-    a.gram[sl * cap + s_new] = ga;
-    bvec[sl] = gb;
+    newrow[q] = ga;
+    bvec[q] = gb;
   }
-  __threadfence_block();
   __syncthreads();
-
-  // columns with nonzero norm, newest first
-  if (lane == 0) {
+  auto gram = [&](int q, int r) -> double {   // Gram entry of columns q, r
+    if (q == 0) return newrow[r];
+    if (r == 0) return newrow[q];
+    const int sq = (s_new - q + cap) % cap, sr = (s_new - r + cap) % cap;
+    return a.gram[sq * cap + sr];
+  };
+  if (tid == 0) {
     int n = 0;
     for (int q = 0; q < mt; ++q) {
-      const int sl = (s_new - q + cap) % cap;
-      const double nrm = sqrt(a.gram[sl * cap + sl]);
+      const double nrm = sqrt(q == 0 ? newrow[0] : gram(q, q));
       if (nrm > 0.0) { cols[n] = q; sc[n] = nrm; ++n; }
     }
-    n_sh = n;
-    ok_sh = 1;
+    misc[0] = n;
+    misc[1] = 1;
   }
   __syncthreads();
-  const int n = n_sh;
-
-  // A = S^-1 Gram S^-1 + ridge I (lane r owns row r), rhs = S^-1 b
-  if (lane < n) {
-    const int sr = (s_new - cols[lane] + cap) % cap;
-    for (int q = 0; q < n; ++q) {
-      const int sq = (s_new - cols[q] + cap) % cap;
-      L[lane * kMaxM + q] = a.gram[sr * cap + sq] / (sc[lane] * sc[q]) + (lane == q ? c->ridge : 0.0);
+  const int n = misc[0];
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int r = e / n, q = e - r * n;
+    Lm[r * kMaxM + q] = gram(cols[r], cols[q]) / (sc[r] * sc[q]) + (r == q ? ridge : 0.0);
+  }
+  for (int r = tid; r < n; r += blockDim.x) th[r] = bvec[cols[r]] / sc[r];
+  __syncthreads();
+  if (n <= kSmallLs) {
+    // small systems: Cholesky and both substitutions by one lane in registers
+    if (tid == 0) {
+      double A[kSmallLs][kSmallLs], z[kSmallLs];
+#pragma unroll
+      for (int i = 0; i < kSmallLs; ++i) {
+        z[i] = i < n ? th[i] : 0.0;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) A[i][j] = (i < n && j < n) ? Lm[i * kMaxM + j] : (i == j ? 1.0 : 0.0);
+      }
+      bool good = true;
+#pragma unroll
+      for (int k = 0; k < kSmallLs; ++k) {
+        double p = A[k][k];
+#pragma unroll
+        for (int q = 0; q < k; ++q) p -= A[k][q] * A[k][q];
+        good = good && (p > 0.0);
+        const double lkk = sqrt(p > 0.0 ? p : 1.0);
+        A[k][k] = lkk;
+#pragma unroll
+        for (int i = k + 1; i < kSmallLs; ++i) {
+          double v = A[i][k];
+#pragma unroll
+          for (int q = 0; q < k; ++q) v -= A[i][q] * A[k][q];
+          A[i][k] = v / lkk;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kSmallLs; ++i) {        // L z = rhs
+        double v = z[i];
+#pragma unroll
+        for (int q = 0; q < i; ++q) v -= A[i][q] * z[q];
+        z[i] = v / A[i][i];
+      }
+#pragma unroll
+      for (int i = kSmallLs - 1; i >= 0; --i) {   // L^T w = z
+        double v = z[i];
+#pragma unroll
+        for (int q = i + 1; q < kSmallLs; ++q) v -= A[q][i] * z[q];
+        z[i] = v / A[i][i];
+      }
+#pragma unroll
+      for (int i = 0; i < kSmallLs; ++i) if (i < n) th[i] = z[i];
+      if (!good) misc[1] = 0;
     }
-    y[lane] = bvec[sr] / sc[lane];
+    __syncthreads();
+  } else {
+    // right-looking Cholesky in LDS, one row per thread
+    for (int k = 0; k < n; ++k) {
+      if (tid == 0) {
+        const double p = Lm[k * kMaxM + k];
+        if (!(p > 0.0)) misc[1] = 0;
+        Lm[k * kMaxM + k] = sqrt(p > 0.0 ? p : 1.0);
+      }
+      __syncthreads();
+      if (tid > k && tid < n) Lm[tid * kMaxM + k] /= Lm[k * kMaxM + k];
+      __syncthreads();
+      if (tid > k && tid < n) {
+        const double lik = Lm[tid * kMaxM + k];
+        for (int j = k + 1; j <= tid; ++j) Lm[tid * kMaxM + j] -= lik * Lm[j * kMaxM + k];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      for (int i = 0; i < n; ++i) {
+        double v = th[i];
+        for (int q = 0; q < i; ++q) v -= Lm[i * kMaxM + q] * th[q];
+        th[i] = v / Lm[i * kMaxM + i];
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        double v = th[i];
+        for (int q = i + 1; q < n; ++q) v -= Lm[q * kMaxM + i] * th[q];
+        th[i] = v / Lm[i * kMaxM + i];
+      }
+    }
+    __syncthreads();
+  }
+  // scatter back to column positions (cols[] is increasing), undo the scaling
+  const bool ok = misc[1] != 0;
+  if (tid == 0) {
+    for (int r = n - 1; r >= 0; --r) {
+      const double v = ok ? th[r] / sc[r] : 0.0;
+      for (int q = (r + 1 < n ? cols[r + 1] : mt) - 1; q > cols[r]; --q) th[q] = 0.0;
+      th[cols[r]] = v;
+    }
+    for (int q = (n > 0 ? cols[0] : mt) - 1; q >= 0; --q) th[q] = 0.0;
   }
   __syncthreads();
-  // right-looking Cholesky, one row per lane
-  for (int k = 0; k < n; ++k) {
-    if (lane == 0) {
-      const double p = L[k * kMaxM + k];
-      if (!(p > 0.0)) ok_sh = 0;
-      L[k * kMaxM + k] = sqrt(p > 0.0 ? p : 1.0);
-    }
-    __syncthreads();
-    if (lane > k && lane < n) L[lane * kMaxM + k] /= L[k * kMaxM + k];
-    __syncthreads();
-    if (lane > k && lane < n) {
-      const double lik = L[lane * kMaxM + k];
-      for (int j = k + 1; j <= lane; ++j) L[lane * kMaxM + j] -= lik * L[j * kMaxM + k];
-    }
-    __syncthreads();
-  }
-  // forward (L z = rhs) and backward (L^T w = z) substitution, dot products over lanes
-  for (int i = 0; i < n; ++i) {
-    double part = (lane < i) ? L[i * kMaxM + lane] * y[lane] : 0.0;
-    part = wave_sum(part);
-    __syncthreads();
-    if (lane == 0) y[i] = (y[i] - part) / L[i * kMaxM + i];
-    __syncthreads();
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double part = (lane > i && lane < n) ? L[lane * kMaxM + i] * y[lane] : 0.0;
-    part = wave_sum(part);
-    __syncthreads();
-    if (lane == 0) y[i] = (y[i] - part) / L[i * kMaxM + i];
-    __syncthreads();
-  }
-  const bool ok = ok_sh != 0;
-  for (int q = lane; q < mt; q += 64) c->theta[q] = 0.0;
-  __syncthreads();
-  if (ok && lane < n) c->theta[cols[lane]] = y[lane] / sc[lane];
-  __syncthreads();
-  if (lane == 0) {
-    const int used = ok ? n : 0;
-    c->mt = mt;
-    c->used = used;
-    c->cand_is_lloyd = (used == 0) ? 1 : 0;
-    c->hist_head = s_new;
-    c->hist_len = len_new;
-    if (a.trace_rec) {
-      double* rec = a.trace_rec + (int64_t)c->t * kTraceRec;
-      rec[8] = mt;
-      rec[9] = used;
-      for (int q = 0; q < mt; ++q) rec[16 + q] = c->theta[q];
-    }
-  }
-}
-
-hipError_t launch_ls_solve(const SolveArgs& a, hipStream_t s) {
-  if (a.cap > kMaxM) return hipErrorInvalidValue;
-  clear_pending_error();
-  hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, s, a);
-  return hipGetLastError();
+  return ok ? n : 0;
 }
 
 // ---------------------------------------------------------------------------
 // C^{t+1} = G^t - sum_j theta_j dG_j and the fall-back iterate fl32(G^t),
 // each with its squared norms (and bfloat16 shadows): one wave per centroid.
+// In the solver (gated) each workgroup first solves the least-squares
+// problem; workgroup 0 also records the new Gram row and the results.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float put_centroid(float* C, uint16_t* Cb, int64_t e, double v, double* nsq,
                                               double* e2) {
@@ -153,13 +178,51 @@ __device__ __forceinline__ float put_centroid(float* C, uint16_t* Cb, int64_t e,
 
 __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
   Ctl* c = a.ctl;
-  if (a.gated && c->done) return;
+  __shared__ double th[kMaxM], newrow[kMaxM], bvec[kMaxM], sc[kMaxM];
+  __shared__ double Lm[kMaxM * kMaxM];
+  __shared__ int cols[kMaxM], misc[2];
+  int mt = 0, head = 0;
+  const int cap = a.cap;
+  if (a.gated) {
+    if (c->done) return;
+    const int t = c->t;
+    if (cap > 0) {
+      const int s_new = (t - 1) % cap;
+      const int len_new = t < cap ? t : cap;
+      int m = c->m < t ? c->m : t;
+      if (m > len_new) m = len_new;
+      const int used = ls_solve_group(a, s_new, len_new, m, c->ridge, th, newrow, bvec, Lm, sc, cols, misc);
+      if (blockIdx.x == 0) {
+        for (int q = threadIdx.x; q < len_new; q += blockDim.x) {
+          const int sl = (s_new - q + cap) % cap;
+          a.gram[s_new * cap + sl] = newrow[q];
+          a.gram[sl * cap + s_new] = newrow[q];
+        }
+        if (threadIdx.x == 0) {
+          for (int q = 0; q < m; ++q) c->theta[q] = th[q];
+          c->mt = m;
+          c->used = used;
+          c->cand_is_lloyd = (used == 0) ? 1 : 0;
+          if (a.trace_rec) {
+            double* rec = a.trace_rec + (int64_t)t * kTraceRec;
+            rec[8] = m;
+            rec[9] = used;
+            for (int q = 0; q < m; ++q) rec[16 + q] = th[q];
+          }
+        }
+      }
+      mt = used > 0 ? m : 0;
+      head = s_new;
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c->mt = 0;
+      c->used = 0;
+      c->cand_is_lloyd = 1;
+    }
+  }
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= a.K) return;
-  const int d = a.d, cap = a.cap;
-  const int mt = (a.gated && c->used > 0) ? c->mt : 0;
-  const int head = a.gated ? c->hist_head : 0;
+  const int d = a.d;
   const int64_t KD = (int64_t)a.K * d;
   double n_c = 0.0, e_c = 0.0, n_f = 0.0, e_f = 0.0;
   for (int k = lane; k < d; k += kWave) {
@@ -168,7 +231,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
     double v = g;
     for (int q = 0; q < mt; ++q) {
       const int sl = (head - q + cap) % cap;
-      v -= c->theta[q] * a.ring_dG[(int64_t)sl * KD + e];
+      v -= th[q] * a.ring_dG[(int64_t)sl * KD + e];
     }
     put_centroid(a.C_cand, a.Cb_cand, e, v, &n_c, &e_c);
     put_centroid(a.C_fb, a.Cb_fb, e, g, &n_f, &e_f);
@@ -186,6 +249,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
 }
 
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s) {
+  if (a.cap > kMaxM) return hipErrorInvalidValue;
   clear_pending_error();
   hipLaunchKernelGGL(k_combine, dim3((a.K + 3) / 4), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -498,11 +498,9 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   af.delta = gbf ? c->del_fb : nullptr; af.e_part = c->e_part + grid;
   FinalizeArgs fi = f;
   fi.mode = kFinIter; fi.C_in = nullptr;
-  SolveArgs sa{};
-  sa.ctl = c->ctl; sa.dots = c->dots; sa.n_dots = finalize_grid(KD);
-  sa.gram = c->gram; sa.cap = cap; sa.trace_rec = opt.trace_rec;
   CombineArgs ci = cb;
   ci.gated = 1;
+  ci.dots = c->dots; ci.n_dots = finalize_grid(KD); ci.gram = c->gram; ci.trace_rec = opt.trace_rec;
 
   // The candidate assignment is launched directly (between two HIP events
   // when timing is on); the rest of the iteration is replayed from a graph.
@@ -519,7 +517,6 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     HIP_TRY(c, launch_controller(k2, q), "controller");
     HIP_TRY(c, launch_update_sums(u, q), "update");
     HIP_TRY(c, launch_finalize(fi, q), "finalize");
-    HIP_TRY(c, launch_ls_solve(sa, q), "least squares");
     HIP_TRY(c, launch_combine(ci, q), "combine");
     HIP_TRY(c, hipMemcpyAsync(&c->done_host[p], &c->ctl->done, sizeof(int), hipMemcpyDeviceToHost, q),
             "poll copy");

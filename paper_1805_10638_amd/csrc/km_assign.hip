@@ -232,7 +232,7 @@ __device__ __forceinline__ void tile_mfma(const float* Cs, const uint16_t* Cbs, 
 // KS: padded dims per lane group; SB: 16-sample blocks per wave; W: waves
 // per workgroup (they share one LDS copy of the centroids).
 template <int KS, int SB, int W, int ROLE, bool XBF, bool GBF>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((GBF || KS > 32) ? 1 : 4))) void k_assign(AssignArgs a) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF && KS * SB <= 32) ? 4 : 1))) void k_assign(AssignArgs a) {
   constexpr int NT = 64 * W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using T = Tile<KS, GBF>;
@@ -557,14 +557,17 @@ static int shape_override() {
 
 template <int KS, int ROLE, bool XBF, bool GBF>
 static KernelPick pick_one(int K) {
-  constexpr int SB0 = KS <= 16 ? 4 : (KS <= 32 ? 2 : 1);
+  // default: two 16-sample blocks per wave up to 64 padded dimensions per
+  // lane group (measured best for d = 32: 190 us vs 213 us with four blocks
+  // at N = 1e6, K = 256), one block beyond.
+  constexpr int SB0 = KS <= 32 ? 2 : 1;
   // alternative shapes are only built for the benchmark widths (d = 32 in
   // float32, d = 128 in bfloat16) and the candidate role
   if constexpr (ROLE == kRoleCand && ((KS == 8 && !GBF) || (KS == 32 && GBF))) {
     switch (shape_override()) {
-      case 1: return make_pick<KS, ROLE, XBF, GBF, (SB0 > 1 ? SB0 / 2 : 1), 8>(K);
-      case 2: return make_pick<KS, ROLE, XBF, GBF, (SB0 > 1 ? SB0 / 2 : 1), 4>(K);
-      case 3: return make_pick<KS, ROLE, XBF, GBF, SB0, 8>(K);
+      case 1: return make_pick<KS, ROLE, XBF, GBF, SB0, 8>(K);
+      case 2: return make_pick<KS, ROLE, XBF, GBF, 4, 4>(K);
+      case 3: return make_pick<KS, ROLE, XBF, GBF, 1, 8>(K);
       default: break;
     }
   }

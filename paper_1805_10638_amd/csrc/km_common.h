@@ -40,8 +40,6 @@ struct Ctl {
   int32_t lab_cand;        // label buffer of the candidate's assignment
   int32_t lab_fb;          // label buffer of the fall-back assignment
   int32_t acc_src;         // accepted centroids: 0 candidate buffer, 1 fall-back buffer
-  int32_t hist_len;        // valid history differences
-  int32_t hist_head;       // ring slot of the newest difference
   int32_t mt;              // m_t used this iteration
   int32_t used;            // columns that entered the least squares
   int32_t accepted, rejected, assign_passes, max_iter;

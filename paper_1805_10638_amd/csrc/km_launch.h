@@ -88,21 +88,15 @@ struct CtlArgs {
 hipError_t launch_controller(const CtlArgs& a, hipStream_t s);
 
 // ----- Anderson step (Sec. 2.1, Eq. (7)-(8)) -----
-struct SolveArgs {
-  Ctl* ctl;
-  const double* dots;
-  int n_dots;             // workgroups of the finalize launch
-  double* gram;           // cap x cap
-  int cap;
-  double* trace_rec;
-};
-hipError_t launch_ls_solve(const SolveArgs& a, hipStream_t s);
-
 struct CombineArgs {
   Ctl* ctl;
-  int gated;              // 1: solver iteration (uses theta); 0: C^1 = G^0
+  int gated;              // 1: solver iteration (least squares + theta); 0: C^1 = G^0
   const double* G_last;
   const double* ring_dG;
+  const double* dots;     // per-workgroup partial inner products of the finalize launch
+  int n_dots;
+  double* gram;           // cap x cap stored Gram entries of the history
+  double* trace_rec;
   int K, d, cap;
   float* C_cand; float* nc_cand; uint16_t* Cb_cand; float* delta_cand;
   float* C_fb; float* nc_fb; uint16_t* Cb_fb; float* delta_fb;

@@ -216,8 +216,22 @@ __global__ __launch_bounds__(256) void k_segsum(UpdateArgs u) {
   const int k0 = col * 4;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const bool vec = (d % 4) == 0 && k0 + 4 <= d;
-  for (int64_t p = p0 + rg; p < p1; p += rpp) {
-    const int64_t i = u.perm[p];
+  constexpr int kPf = 8;   // perm indices fetched ahead of the row loads
+  int pidx[kPf];
+  int64_t pbase = p0 + rg;
+#pragma unroll
+  for (int q = 0; q < kPf; ++q) {
+    const int64_t pp = pbase + (int64_t)q * rpp;
+    pidx[q] = pp < p1 ? u.perm[pp] : 0;
+  }
+  for (int64_t p = pbase; p < p1; p += rpp) {
+    const int64_t i = pidx[0];
+#pragma unroll
+    for (int q = 0; q < kPf - 1; ++q) pidx[q] = pidx[q + 1];
+    {
+      const int64_t pp = p + (int64_t)kPf * rpp;
+      pidx[kPf - 1] = pp < p1 ? u.perm[pp] : 0;
+    }
     if (XBF) {
       const uint16_t* xr = (const uint16_t*)u.X + i * d;
       if (vec) {
@@ -286,7 +300,7 @@ constexpr int kDotGroup = 8;    // history slots reduced per pass over the eleme
 __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
   Ctl* ctl = f.ctl;
   if (f.mode == kFinIter && ctl->done) return;
-  __shared__ double red[2 * kDotGroup][256];
+  __shared__ double red[2 * kDotGroup][4];
   const int tid = threadIdx.x;
   const int d = f.d, cap = f.cap;
   const int64_t KD = (int64_t)f.K * d;
@@ -294,13 +308,15 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
 
   int s_new = 0, len_new = 0;
   if (f.mode == kFinIter && cap > 0) {
-    s_new = (ctl->hist_len == 0) ? 0 : (ctl->hist_head + 1) % cap;
-    len_new = ctl->hist_len + 1 < cap ? ctl->hist_len + 1 : cap;
+    // the difference created at iteration t goes to ring slot (t - 1) mod cap
+    const int t = ctl->t;
+    s_new = (t - 1) % cap;
+    len_new = t < cap ? t : cap;
   }
   const float* Cacc = (f.mode == kFinIter && ctl->acc_src == 1) ? f.C_fb : f.C_cand;
 
   for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < KD; e += stride) {
-    const int j = (int)(e / d);
+    const int j = (int)((uint32_t)e / (uint32_t)d);   // K*d < 2^31
     const int n = f.counts[j];
     const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
     const int k = (int)(e - (int64_t)j * d);
@@ -324,7 +340,9 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
 
   // Gram partials: for each valid slot sl, <dF_new, dF_sl> (index sl) and
   // <dF_sl, F^t> (index cap + sl).  Each thread reads back only the elements
-  // it wrote above.
+  // it wrote above.  Reduction: waves by shuffles, then the 4 wave partials
+  // in order.
+  const int lane = tid & 63, w = tid >> 6;
   for (int q0 = 0; q0 < len_new; q0 += kDotGroup) {
     double pa[kDotGroup], pb[kDotGroup];
 #pragma unroll
@@ -344,21 +362,22 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
     }
 #pragma unroll
     for (int g = 0; g < kDotGroup; ++g) {
-      red[g][tid] = pa[g];
-      red[kDotGroup + g][tid] = pb[g];
+      pa[g] = wave_sum(pa[g]);
+      pb[g] = wave_sum(pb[g]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int g = 0; g < kDotGroup; ++g) {
+        red[g][w] = pa[g];
+        red[kDotGroup + g][w] = pb[g];
+      }
     }
     __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-      if (tid < w) {
-#pragma unroll
-        for (int g = 0; g < 2 * kDotGroup; ++g) red[g][tid] += red[g][tid + w];
-      }
-      __syncthreads();
-    }
     if (tid < kDotGroup && q0 + tid < len_new) {
       const int sl = (s_new - (q0 + tid) + cap) % cap;
-      f.dots[(int64_t)blockIdx.x * 2 * cap + sl] = red[tid][0];
-      f.dots[(int64_t)blockIdx.x * 2 * cap + cap + sl] = red[kDotGroup + tid][0];
+      f.dots[(int64_t)blockIdx.x * 2 * cap + sl] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+      f.dots[(int64_t)blockIdx.x * 2 * cap + cap + sl] =
+          ((red[kDotGroup + tid][0] + red[kDotGroup + tid][1]) + red[kDotGroup + tid][2]) + red[kDotGroup + tid][3];
     }
     __syncthreads();
   }
