@@ -26,10 +26,11 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOAD = dict(N=1_000_000, d=32, K=256, m_max=10, tol=1e-6, max_iter=500)
 
-# rocprofv3 counter summaries of the dominant kernel (profiles/) give the
-# HBM traffic per launch; kept here as measured, None until measured for the
-# current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = None
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by its reading for a plain copy of known size
+# (profiles/assign_f32_N1M_d32_K256_traffic.md).  Set to None when the kernel
+# changes until it is measured again.
+TRAFFIC_BYTES_PER_LAUNCH = 136784244
 
 
 def parse():
@@ -40,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time budget of the oracle baseline sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run three device-to-device copies of MIB MiB (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -81,6 +85,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "copies": 3}))
+        return
     import paper_1805_10638_amd as km
     from paper_1805_10638_amd import synth
 

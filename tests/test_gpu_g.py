@@ -7,7 +7,7 @@ import pytest
 from oracle import kmeans_oracle as ko
 from paper_1805_10638_amd import synth
 
-from helpers import check_g, dev, x_tensor, x_values
+from helpers import check_g, dev, x_tensor, x_values  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -147,3 +147,58 @@ def test_invalid_arguments():
     with pytest.raises(km.KMError) as e:
         km.kmeans_g(x_tensor(Xn), C)
     assert e.value.status == -5
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 distance GEMM (precision mode): same exactness contract
+# ---------------------------------------------------------------------------
+
+BF_SHAPES = [(3000, 128, 100), (2049, 32, 64), (1500, 96, 40), (777, 16, 5), (2500, 64, 129),
+             (600, 200, 33), (1000, 3, 10), (4099, 48, 256)]
+
+
+@pytest.mark.parametrize("N,d,K", BF_SHAPES)
+def test_g_parity_bf16_gemm_bf16_x(N, d, K):
+    km = _lib()
+    Xb, _ = synth.precision(rep=2, n=N, d=d, k=max(2, K // 2))
+    C = synth.init_centroids(Xb, K, seed=5) + np.float32(0.125)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(Xb), dev(C), prec="bf16")
+    check_g(Xb, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
+
+
+@pytest.mark.parametrize("N,d,K", [(3000, 128, 100), (1500, 96, 40), (900, 33, 31)])
+def test_g_parity_bf16_gemm_f32_x(N, d, K):
+    km = _lib()
+    X = _mixture(N, d, K, seed=N + 7)
+    C = synth.init_centroids(X, K, seed=K + 1)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C), prec="bf16")
+    check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
+
+
+def test_bf16_and_f32_gemm_agree():
+    """Both precisions return the exact argmin: identical labels except rows
+    that the oracle itself calls near ties."""
+    km = _lib()
+    Xb, _ = synth.precision(rep=3, n=20000, d=128, k=256)
+    C = synth.init_centroids(Xb, 256, seed=9)
+    Xt, Ct = x_tensor(Xb), dev(C)
+    r32 = km.kmeans_g(Xt, Ct, prec="f32")
+    r16 = km.kmeans_g(Xt, Ct, prec="bf16")
+    a = r32[0].cpu().numpy(), r16[0].cpu().numpy()
+    diff = np.flatnonzero(a[0] != a[1])
+    if diff.size:
+        o = ko.assign(x_values(Xb[diff]), C.astype(np.float64))
+        assert o.near_tie.all()
+    assert abs(r32[2] - r16[2]) <= 1e-9 * abs(r32[2])
+
+
+def test_solve_bf16_gemm_matches_f32():
+    km = _lib()
+    Xb, _ = synth.precision(rep=4, n=30000, d=64, k=64)
+    C0 = synth.init_centroids(Xb, 64, seed=4)
+    Xt, Ct = x_tensor(Xb), dev(C0)
+    a = km.kmeans_solve(Xt, Ct, m_max=10, tol=1e-6, prec="f32")
+    b = km.kmeans_solve(Xt, Ct, m_max=10, tol=1e-6, prec="bf16")
+    assert a[3] == b[3]
+    assert b[2] == pytest.approx(a[2], rel=1e-9)
+    assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
