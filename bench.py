@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time budget of the oracle baseline sample")
+    ap.add_argument("--workload", choices=["plain", "precision"], default="plain",
+                    help="plain: N=1e6 d=32 K=256 float32 (default line); precision: "
+                         "N=4e6 d=128 K=1024 bfloat16-stored X, float32 vs bfloat16 GEMM")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -96,6 +99,9 @@ def main():
         return
     import paper_1805_10638_amd as km
     from paper_1805_10638_amd import synth
+    if args.workload == "precision":
+        precision_workload(args, km, synth, torch)
+        return
 
     w = WORKLOAD
     X, _ = synth.plain_large(rep=0, n=w["N"], d=w["d"], k=w["K"])
@@ -187,6 +193,60 @@ def main():
         out["cpu_baseline"] = cpu_baseline(X, synth.init_centroids(X, K, 0),
                                            statistics.mean(passes), args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+BF16_MFMA_PEAK_TFLOPS = 2516.6   # MI355X dense bf16 matrix peak
+
+
+def precision_workload(args, km, synth, torch):
+    """N=4,000,000, d=128, K=1024 with X stored as bfloat16: time to converge
+    with the float32 and the bfloat16 distance GEMM from the same C0, the
+    assignment kernel against its roofline, and the error of each result
+    against the float64 oracle (labels on sampled rows, energy, centroids)."""
+    from oracle import kmeans_oracle as ko
+    N, d, K = 4_000_000, 128, 1024
+    Xb, _ = synth.precision(rep=0, n=N, d=d, k=K)
+    Xd = torch.from_numpy(Xb.view(np.int16)).to("cuda")
+    steps = max(1, min(args.steps, 3))
+    inits = [torch.from_numpy(synth.init_centroids(Xb, K, s)).to("cuda") for s in range(steps + 1)]
+    ctx = km.Context(0)
+    rows = np.random.default_rng(7).choice(N, 4096, replace=False)
+    X64s = synth.bf16_bits_to_f32(Xb[rows]).astype(np.float64)
+    res = {}
+    for prec, peak in (("f32", FP32_MFMA_PEAK_TFLOPS), ("bf16", BF16_MFMA_PEAK_TFLOPS)):
+        km.kmeans_solve(Xd, inits[0], m_max=10, tol=1e-6, prec=prec, ctx=ctx, max_iter=3)  # warm-up
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = []
+        for s in range(1, steps + 1):
+            outs.append(km.kmeans_solve(Xd, inits[s], m_max=10, tol=1e-6, prec=prec, ctx=ctx))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.set_timing(False)
+        C, rho, E, it, st = outs[-1]
+        a_ms = sum(o[4].assign_ms for o in outs) / max(1, sum(o[4].assign_launches for o in outs))
+        ach = 2.0 * N * K * d / (a_ms / 1e3) / 1e12
+        Cn = C.cpu().numpy().astype(np.float64)
+        a = ko.assign(X64s, Cn)
+        lab = rho.cpu().numpy()[rows]
+        mism = int(((a.rho != lab) & ~a.near_tie).sum())
+        e_rows = ko.energy(X64s, lab, Cn)
+        e_gpu_rows = float(((X64s - Cn[lab]) ** 2).sum())
+        res[prec] = {"solves_per_s": steps / el, "time_to_converge_ms": el * 1e3 / steps,
+                     "iters": it, "assign_passes": st.assign_passes, "E": E,
+                     "assign_avg_us": a_ms * 1e3, "assign_tflops": ach, "peak_tflops": peak,
+                     "frac": ach / peak, "flagged_rows_per_pass": st.flagged_rows / st.assign_passes,
+                     "oracle_label_mismatch_sampled": mism, "oracle_near_ties_sampled": int(a.near_tie.sum()),
+                     "sampled_energy_rel_err": abs(e_gpu_rows - e_rows) / e_rows}
+    ef, eb = res["f32"]["E"], res["bf16"]["E"]
+    print(json.dumps({"metric": "precision mode: time to converge, f32 vs bf16 distance GEMM",
+                      "config": {"workload": "gaussian-mixture N=4000000 d=128 K=1024, 5% outliers, "
+                                             "X stored bfloat16, m_max=10 tol=1e-6",
+                                 "N": N, "d": d, "K": K},
+                      "steps": steps, "results": res,
+                      "bf16_speedup": res["bf16"]["solves_per_s"] / res["f32"]["solves_per_s"],
+                      "energy_rel_diff_bf16_vs_f32": abs(eb - ef) / ef}), flush=True)
 
 
 if __name__ == "__main__":

@@ -112,7 +112,7 @@ __device__ __forceinline__ int wave_argmin(double bd, int bj, double* dist) {
 
 // Centroids and the sample from global memory (any layout case).
 template <bool XBF>
-__device__ __noinline__ int exact_argmin(const void* X, int64_t i, int d, const float* C, int K,
+__device__ __forceinline__ int exact_argmin(const void* X, int64_t i, int d, const float* C, int K,
                                          int lane, double* dist) {
   double bd = __builtin_inf();
   int bj = -1;
@@ -131,7 +131,7 @@ __device__ __noinline__ int exact_argmin(const void* X, int64_t i, int d, const 
 // Centroids resident in LDS (row stride ld, zero-padded to DP) and the
 // sample staged in LDS (xrow, zero-padded to DP).
 template <int DP>
-__device__ __noinline__ int exact_argmin_lds(const float* xrow, const float* Cs, int ld, int K, int lane,
+__device__ __forceinline__ int exact_argmin_lds(const float* xrow, const float* Cs, int ld, int K, int lane,
                                              double* dist) {
   double bd = __builtin_inf();
   int bj = -1;
@@ -189,9 +189,9 @@ __device__ __forceinline__ float vmax(float a, float b) {
 
 // MFMAs of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk) against
 // the SB sample blocks of this wave; accumulators start at -||c||^2/2.
-template <int KS, int SB, bool GBF>
+template <int KS, int SB, bool GBF, typename XV>
 __device__ __forceinline__ void tile_mfma(const float* Cs, const uint16_t* Cbs, const float* ncs,
-                                          int tt, int g, int r16, const float (&xv)[SB][KS],
+                                          int tt, int g, int r16, const XV& xv,
                                           const i16x8 (&xbv)[SB][Tile<KS, GBF>::NB], f32x4 (&acc)[SB]) {
   using T = Tile<KS, GBF>;
   const f32x4 n4 = *(const f32x4*)(ncs + tt + 4 * g);
@@ -227,6 +227,11 @@ __device__ __forceinline__ void tile_mfma(const float* Cs, const uint16_t* Cbs, 
       for (int s = 0; s < SB; ++s)
         acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], xv[s][q], acc[s], 0, 0, 0);
   }
+}
+
+// bfloat16 bits -> float32 of element q of a lane's bf16 chunk
+__device__ __forceinline__ float bf_elem(const i16x8& v, int e) {
+  return bf16_to_f32((uint16_t)v[e]);
 }
 
 // KS: padded dims per lane group; SB: 16-sample blocks per wave; W: waves
@@ -340,13 +345,31 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
   for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
     // Sample rows of this wave, kept in registers.
     const int64_t row0 = grp * group_rows + (int64_t)wave * (16 * SB);
-    float xv[SB][KS];
+    // float32 copy of the rows, except when bf16 rows feed the bf16 GEMM
+    // (then the bf16 bits are exact and the only copy kept)
+    constexpr bool KF = !(XBF && GBF);
+    float xv[SB][KF ? KS : 1];
     i16x8 xbv[SB][NB];
     float xerr[SB];  // ||x - bf16(x)||^2 partial when float32 X feeds the bf16 GEMM
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       xerr[s] = 0.f;
       const int64_t i = row0 + 16 * s + r16;
+      if constexpr (!KF) {
+        const uint16_t* xr = (const uint16_t*)a.X + i * d + g * KS;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (i < a.N && vec) {
+            xbv[s][q] = *(const i16x8*)(xr + 8 * q);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int k = g * KS + 8 * q + e;
+              xbv[s][q][e] = (i < a.N && k < d) ? (short)xr[8 * q + e] : (short)0;
+            }
+          }
+        }
+      } else {
       if (i < a.N) {
         load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xv[s]);
       } else {
@@ -365,6 +388,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
               xerr[s] = fmaf(df, df, xerr[s]);
             }
           }
+      }
       }
     }
 
@@ -419,9 +443,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
         sc = ns;
       }
       if (bi < 0 || bi >= K) bi = 0;
+      auto xf = [&](int q) -> float {
+        if constexpr (KF) return xv[s][q];
+        else return bf_elem(xbv[s][q >> 3], q & 7);
+      };
       float xs = 0.f;
 #pragma unroll
-      for (int q = 0; q < KS; ++q) xs = fmaf(xv[s][q], xv[s][q], xs);
+      for (int q = 0; q < KS; ++q) xs = fmaf(xf(q), xf(q), xs);
       xs += __shfl_xor(xs, 16, kWave);
       xs += __shfl_xor(xs, 32, kWave);
       const float nx = sqrtf(xs) * 1.0001f;
@@ -450,7 +478,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
           if (g * KS + q < d) {
-            const double df = (double)xv[s][q] - (double)cr[q];
+            const double df = (double)xf(q) - (double)cr[q];
             p = fma(df, df, p);
           }
         }
@@ -466,11 +494,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
         fm &= fm - 1;
         double dist;
         int j;
-        if (resident && !GBF) {
+        bool lds_path = false;
+        if constexpr (!GBF) lds_path = resident;
+        if (lds_path) {
           // the flagged row is spread over lanes r16 == f of the 4 lane groups
           if (r16 == f) {
 #pragma unroll
-            for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xv[s][q];
+            for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xf(q);
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -560,7 +590,12 @@ static KernelPick pick_one(int K) {
   // default: two 16-sample blocks per wave up to 64 padded dimensions per
   // lane group (measured best for d = 32: 190 us vs 213 us with four blocks
   // at N = 1e6, K = 256), one block beyond.
-  constexpr int SB0 = KS <= 32 ? 2 : 1;
+  // The bf16 GEMM on bf16 rows streams centroid chunks through LDS for large
+  // K: 16 waves of three 16-sample blocks share each staged chunk.  Wider or
+  // float32 rows need the register room of 4-wave workgroups.
+  constexpr bool BIG = GBF && XBF && KS <= 32;
+  constexpr int SB0 = BIG ? 3 : (KS <= 32 ? 2 : 1);
+  constexpr int W0 = BIG ? 16 : 4;
   // alternative shapes are only built for the benchmark widths (d = 32 in
   // float32, d = 128 in bfloat16) and the candidate role
   if constexpr (ROLE == kRoleCand && ((KS == 8 && !GBF) || (KS == 32 && GBF))) {
@@ -571,7 +606,7 @@ static KernelPick pick_one(int K) {
       default: break;
     }
   }
-  return make_pick<KS, ROLE, XBF, GBF, SB0, 4>(K);
+  return make_pick<KS, ROLE, XBF, GBF, SB0, W0>(K);
 }
 
 template <int ROLE, bool XBF, bool GBF>
