@@ -10,7 +10,9 @@
  *  - Array arguments named X, C, C0, C_out, rho, rho_prev, rho_out are
  *    DEVICE pointers (memory from hipMalloc or a framework allocator on the
  *    context's device), row-major and contiguous.  The caller owns them; the
- *    library never frees or retains them after the call returns.
+ *    library never frees or retains them after the call returns.  X, C, C0
+ *    and C_out start on a 16-byte boundary (allocator base pointers do);
+ *    otherwise the call returns KM_EINVAL.
  *  - Scalar outputs (E, iters) and statistics structs are HOST pointers.
  *  - X is N x d, stored as float32 (KM_X_F32) or as bfloat16 bit patterns
  *    (KM_X_BF16, uint16 per element).  C, C0 and C_out are K x d float32.

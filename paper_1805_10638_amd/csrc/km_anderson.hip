@@ -156,22 +156,21 @@ __device__ int ls_solve_group(const CombineArgs& a, int s_new, int len_new, int 
 
 // ---------------------------------------------------------------------------
 // C^{t+1} = G^t - sum_j theta_j dG_j and the fall-back iterate fl32(G^t),
-// each with its squared norms (and bfloat16 shadows): one wave per centroid.
+// each with its squared norms (and bfloat16 hi/lo pairs): one wave per centroid.
 // In the solver (gated) each workgroup first solves the least-squares
 // problem; workgroup 0 also records the new Gram row and the results.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float put_centroid(float* C, uint16_t* Cb, int64_t e, double v, double* nsq,
-                                              double* e2) {
+__device__ __forceinline__ float put_centroid(float* C, uint16_t* Cb, int64_t KD, int64_t e, double v,
+                                              double* nsq, double* e2) {
   const float f = (float)v;
   C[e] = f;
   *nsq = fma((double)f, (double)f, *nsq);
   if (Cb) {
-    uint32_t x = __float_as_uint(f);
-    x += 0x7FFFu + ((x >> 16) & 1u);
-    const uint16_t b = (uint16_t)(x >> 16);
-    Cb[e] = b;
-    const double df = (double)f - (double)__uint_as_float(((uint32_t)b) << 16);
-    *e2 = fma(df, df, *e2);
+    uint16_t h, l;
+    const double r = bf16_split(f, &h, &l);
+    Cb[e] = h;
+    Cb[KD + e] = l;
+    *e2 = fma(r, r, *e2);
   }
   return f;
 }
@@ -233,8 +232,8 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
       const int sl = (head - q + cap) % cap;
       v -= th[q] * a.ring_dG[(int64_t)sl * KD + e];
     }
-    put_centroid(a.C_cand, a.Cb_cand, e, v, &n_c, &e_c);
-    put_centroid(a.C_fb, a.Cb_fb, e, g, &n_f, &e_f);
+    put_centroid(a.C_cand, a.Cb_cand, KD, e, v, &n_c, &e_c);
+    put_centroid(a.C_fb, a.Cb_fb, KD, e, g, &n_f, &e_f);
   }
   n_c = wave_sum(n_c);
   e_c = wave_sum(e_c);

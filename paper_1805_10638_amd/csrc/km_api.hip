@@ -79,7 +79,7 @@ struct km_ctx {
   float* nc_cand = nullptr;
   float* nc_fb = nullptr;
   float* nc_tmp = nullptr;
-  uint16_t* Cb_cand = nullptr;  // bf16 shadows (bf16 GEMM only)
+  uint16_t* Cb_cand = nullptr;  // bf16 hi/lo pairs, 2 x K x d (bf16 GEMM only)
   uint16_t* Cb_fb = nullptr;
   uint16_t* Cb_tmp = nullptr;
   float* del_cand = nullptr;
@@ -103,6 +103,9 @@ static km_status hip_fail(km_ctx* c, hipError_t e, const char* where) {
     hipError_t _e = (expr);                           \
     if (_e != hipSuccess) return hip_fail(c, _e, where); \
   } while (0)
+
+// The kernels read rows and centroids with 16-byte vector loads.
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 static bool is_device_ptr(const void* p) {
   if (!p) return false;
@@ -170,9 +173,9 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
   const size_t o_nc = take((size_t)s.K * 4);
   const size_t o_nf = take((size_t)s.K * 4);
   const size_t o_nt = take((size_t)s.K * 4);
-  const size_t o_bcand = take(s.bf ? KD * 2 : 0);
-  const size_t o_bfb = take(s.bf ? KD * 2 : 0);
-  const size_t o_btmp = take(s.bf ? KD * 2 : 0);
+  const size_t o_bcand = take(s.bf ? KD * 4 : 0);
+  const size_t o_bfb = take(s.bf ? KD * 4 : 0);
+  const size_t o_btmp = take(s.bf ? KD * 4 : 0);
   const size_t o_dc = take(s.bf ? s.K * 4 : 0);
   const size_t o_df = take(s.bf ? s.K * 4 : 0);
   const size_t o_dtmp = take(s.bf ? s.K * 4 : 0);
@@ -238,6 +241,7 @@ static km_status check_common(km_ctx* c, const void* X, int xt, int64_t N, int32
   if (K > kMaxK) return fail(c, KM_EUNSUPPORTED, "K > 4096 is not supported");
   if (N >= ((int64_t)1 << 31)) return fail(c, KM_EUNSUPPORTED, "N >= 2^31 is not supported");
   if (!is_device_ptr(X)) return fail(c, KM_EINVAL, "X is not a device pointer");
+  if (!aligned16(X)) return fail(c, KM_EINVAL, "X must start on a 16-byte boundary");
   return KM_OK;
 }
 
@@ -343,6 +347,7 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   if (!E) return fail(c, KM_EINVAL, "E must be a host pointer");
   if (!is_device_ptr(C) || !is_device_ptr(rho) || !is_device_ptr(C_out))
     return fail(c, KM_EINVAL, "C, rho and C_out must be device pointers");
+  if (!aligned16(C) || !aligned16(C_out)) return fail(c, KM_EINVAL, "C and C_out must start on a 16-byte boundary");
   if (rho_prev && !is_device_ptr(rho_prev)) return fail(c, KM_EINVAL, "rho_prev must be a device pointer");
   const size_t xbytes = (size_t)N * d * (xt == KM_X_BF16 ? 2 : 4);
   const size_t cbytes = (size_t)K * d * 4;
@@ -413,6 +418,8 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   if (!E || !iters) return fail(c, KM_EINVAL, "E and iters must be host pointers");
   if (!is_device_ptr(C0) || !is_device_ptr(C_out) || !is_device_ptr(rho_out))
     return fail(c, KM_EINVAL, "C0, C_out and rho_out must be device pointers");
+  if (!aligned16(C0) || !aligned16(C_out))
+    return fail(c, KM_EINVAL, "C0 and C_out must start on a 16-byte boundary");
   if (opt.trace_C && !is_device_ptr(opt.trace_C)) return fail(c, KM_EINVAL, "trace_C must be a device pointer");
   if (opt.trace_rec && !is_device_ptr(opt.trace_rec))
     return fail(c, KM_EINVAL, "trace_rec must be a device pointer");

@@ -27,9 +27,15 @@
 // is provably the exact argmin.  The energy term of every sample is the
 // float64 direct-difference distance to its label.
 //
-// bfloat16 GEMM.  Centroids are rounded to bfloat16 (Cb); then s_j carries an
-// extra error of at most ||x|| * delta_j with delta_j = ||c_j - Cb_j||, which
-// is added to the bound.  X stored as bfloat16 is exact in both modes.
+// bfloat16 GEMM.  Each centroid is held as a bfloat16 pair hi + lo (hi the
+// rounding of c, lo the rounding of c - hi) and s_j accumulates x.hi + x.lo in
+// float32: bf16 x bf16 products are exact, so the error is the float32
+// summation of 2 dp + 3 terms plus ||x|| r_j, r_j = ||c_j - hi_j - lo_j|| <=
+// 2^-16 ||c_j||.  A single bfloat16 copy of c would leave an error near
+// 2^-9 ||x|| ||c||, about a hundred times the float32 bound, and the re-check
+// would then dominate.  Float32 rows are split the same way (x.hi + x.lo ~ x,
+// three products per slice, x_lo . c_lo and the residuals added to the bound).
+// X stored as bfloat16 is exact in both modes.
 
 #include <stdlib.h>
 
@@ -45,12 +51,6 @@ constexpr int kAssignLdsBudget = 60 * 1024;   // bytes of LDS for the centroid t
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
   return __uint_as_float(((uint32_t)b) << 16);
-}
-
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
 }
 
 __device__ __forceinline__ float ld_x(const void* X, int64_t idx, bool bf) {
@@ -110,18 +110,31 @@ __device__ __forceinline__ int wave_argmin(double bd, int bj, double* dist) {
   return bj;
 }
 
-// Centroids and the sample from global memory (any layout case).
-template <bool XBF>
-__device__ __forceinline__ int exact_argmin(const void* X, int64_t i, int d, const float* C, int K,
-                                         int lane, double* dist) {
+// Centroids from global memory, the sample staged in LDS (xrow, zero-padded
+// to DP): float64 differences over the d real dimensions.
+template <int DP>
+__device__ __forceinline__ int exact_argmin(const float* xrow, int d, const float* C, int K, int lane,
+                                            double* dist) {
   double bd = __builtin_inf();
   int bj = -1;
+  const bool v4 = (d % 4) == 0;
   for (int j = lane; j < K; j += kWave) {
     const float* cr = C + (int64_t)j * d;
     double s = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double df = (double)ld_x(X, i * d + k, XBF) - (double)cr[k];
-      s = fma(df, df, s);
+    if (v4) {
+      for (int k = 0; k < d; k += 4) {
+        const float4 x4 = *(const float4*)(xrow + k);
+        const float4 c4 = *(const float4*)(cr + k);
+        double df = (double)x4.x - (double)c4.x; s = fma(df, df, s);
+        df = (double)x4.y - (double)c4.y; s = fma(df, df, s);
+        df = (double)x4.z - (double)c4.z; s = fma(df, df, s);
+        df = (double)x4.w - (double)c4.w; s = fma(df, df, s);
+      }
+    } else {
+      for (int k = 0; k < d; ++k) {
+        const double df = (double)xrow[k] - (double)cr[k];
+        s = fma(df, df, s);
+      }
     }
     if (s < bd) { bd = s; bj = j; }
   }
@@ -162,9 +175,9 @@ __device__ __forceinline__ int exact_argmin_lds(const float* xrow, const float* 
 template <int KS, bool GBF>
 struct Tile {
   static constexpr int DP = 4 * KS;                    // padded dimension
-  static constexpr int NB = GBF ? KS / 8 : 1;          // bf16 MFMAs per tile
+  static constexpr int NB = GBF ? KS / 8 : 1;          // bf16 MFMAs per tile and operand half
   static constexpr int LD = DP + 4;                    // f32 LDS row stride (floats)
-  static constexpr int LDB = DP + 8;                   // bf16 LDS row stride (elements)
+  static constexpr int LDB = 2 * DP + 8;               // bf16 LDS row stride: hi[DP], lo[DP], pad
   static constexpr int ROW_BYTES = GBF ? LDB * 2 : LD * 4;
   // centroid rows per LDS chunk (multiple of 16) for a given K
   static __host__ __device__ int chunk_rows(int K) {
@@ -178,36 +191,44 @@ struct Tile {
   }
 };
 
-// Plain v_max_f32: the IEEE-mode lowering of fmaxf would first quiet both
-// operands (two extra instructions per compare on this hot path).  NaN
-// inputs only arise from non-finite data, which the energy reports anyway.
-__device__ __forceinline__ float vmax(float a, float b) {
-  float r;
-  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-
 // MFMAs of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk) against
 // the SB sample blocks of this wave; accumulators start at -||c||^2/2.
-template <int KS, int SB, bool GBF, typename XV>
+// bf16: x.hi + x.lo per slice (and x_lo.hi for float32 rows, XLO).
+template <int KS, int SB, bool GBF, bool XLO, typename XV>
 __device__ __forceinline__ void tile_mfma(const float* Cs, const uint16_t* Cbs, const float* ncs,
                                           int tt, int g, int r16, const XV& xv,
-                                          const i16x8 (&xbv)[SB][Tile<KS, GBF>::NB], f32x4 (&acc)[SB]) {
+                                          const i16x8 (&xbv)[SB][Tile<KS, GBF>::NB],
+                                          const i16x8 (&xlv)[SB][XLO ? Tile<KS, GBF>::NB : 1],
+                                          f32x4 (&acc)[SB]) {
   using T = Tile<KS, GBF>;
   const f32x4 n4 = *(const f32x4*)(ncs + tt + 4 * g);
 #pragma unroll
   for (int s = 0; s < SB; ++s) acc[s] = n4;
   if constexpr (GBF) {
-    i16x8 ab[T::NB];
-    const i16x8* cr = (const i16x8*)(Cbs + (tt + r16) * T::LDB + g * KS);
+    i16x8 ah[T::NB], al[T::NB];
+    const uint16_t* cr = Cbs + (tt + r16) * T::LDB + g * KS;
 #pragma unroll
-    for (int q = 0; q < T::NB; ++q) ab[q] = cr[q];
+    for (int q = 0; q < T::NB; ++q) {
+      ah[q] = *(const i16x8*)(cr + 8 * q);
+      al[q] = *(const i16x8*)(cr + T::DP + 8 * q);
+    }
 #pragma unroll
-    for (int q = 0; q < T::NB; ++q)
+    for (int q = 0; q < T::NB; ++q) {
 #pragma unroll
       for (int s = 0; s < SB; ++s)
         acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            __builtin_bit_cast(bf16x8, ab[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+            __builtin_bit_cast(bf16x8, ah[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf16x8, al[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+      if constexpr (XLO) {
+#pragma unroll
+        for (int s = 0; s < SB; ++s)
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, ah[q]), __builtin_bit_cast(bf16x8, xlv[s][q]), acc[s], 0, 0, 0);
+      }
+    }
   } else {
     float av[KS];
     const float* cr = Cs + (tt + r16) * T::LD + g * KS;
@@ -275,7 +296,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
   float* fred = ncs + kchunk;          // 2 W floats (W <= 16)
   double* dred = (double*)(fred + 32); // W doubles
 
-  // max_j ||c_j||^2 and max_j delta_j over the real centroids
+  // max_j ||c_j||^2 and max_j r_j over the real centroids
   float mx = 0.f, mdel = 0.f;
   for (int j = tid; j < K; j += NT) {
     mx = fmaxf(mx, a.nc[j]);
@@ -289,25 +310,34 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
 #pragma unroll
   for (int w = 0; w < W; ++w) { cm2 = fmaxf(cm2, fred[w]); dm = fmaxf(dm, fred[16 + w]); }
   const float cmax = sqrtf(cm2) * 1.0001f;
-  const float dmax = GBF ? dm * 1.0001f : 0.f;
+  const float rmax = GBF ? dm * 1.0001f : 0.f;
+  // float32 summation terms per s_j: dp products (f32), 2 dp or 3 dp exact
+  // bf16 products, plus the accumulator start and two roundings of margin
+  constexpr int NTERM = GBF ? (XBF ? 2 * DP + 3 : 3 * DP + 3) : DP + 3;
   const float u = 5.9604644775390625e-8f;  // 2^-24
-  const float gam = 2.0f * ((float)(DP + 3) * u) / (1.0f - (float)(DP + 3) * u) * 1.001f;
+  const float gam = 2.0f * ((float)NTERM * u) / (1.0f - (float)NTERM * u) * 1.001f;
+  // ||hi_j|| + ||lo_j|| <= (1 + 2^-7 + 2^-16) ||c_j||
+  const float cb = GBF ? cmax * 1.008f : cmax;
 
   // Stage centroid rows [c0, c0 + rows) into LDS (zero padding beyond d and K).
   auto stage = [&](int c0, int rows) {
     if constexpr (GBF) {
       const bool v8 = (d % 8) == 0;
-      for (int e = tid; e < rows * (DP / 8); e += NT) {
-        const int rr = e / (DP / 8), c8 = (e - rr * (DP / 8)) * 8, j = c0 + rr;
+      const int64_t KD = (int64_t)K * d;
+      constexpr int V = DP / 8;   // 8-element vectors per half row
+      for (int e = tid; e < rows * 2 * V; e += NT) {
+        const int rr = e / (2 * V), rem = e - rr * (2 * V);
+        const int half = rem >= V ? 1 : 0, c8 = (rem - half * V) * 8, j = c0 + rr;
+        const uint16_t* src = a.Cb + half * KD + (int64_t)j * d;
         i16x8 v;
         if (v8 && j < K && c8 < d) {
-          v = *(const i16x8*)(a.Cb + (int64_t)j * d + c8);
+          v = *(const i16x8*)(src + c8);
         } else {
 #pragma unroll
           for (int q = 0; q < 8; ++q)
-            v[q] = (j < K && c8 + q < d) ? (short)a.Cb[(int64_t)j * d + c8 + q] : (short)0;
+            v[q] = (j < K && c8 + q < d) ? (short)src[c8 + q] : (short)0;
         }
-        *(i16x8*)(Cbs + rr * LDB + c8) = v;
+        *(i16x8*)(Cbs + rr * LDB + half * DP + c8) = v;
       }
     } else {
       const bool v4 = (d % 4) == 0;
@@ -341,21 +371,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
   const bool vec = (d == DP);
   double e_wave = 0.0;
   unsigned n_changed = 0, n_flag = 0;
+  // float32 copy of the rows in registers only for the float32 GEMM; bf16 rows
+  // are exact as bf16; float32 rows on the bf16 GEMM keep hi and lo (XLO)
+  constexpr bool KF = !GBF;
+  constexpr bool XLO = GBF && !XBF;
 
   for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
     // Sample rows of this wave, kept in registers.
     const int64_t row0 = grp * group_rows + (int64_t)wave * (16 * SB);
-    // float32 copy of the rows, except when bf16 rows feed the bf16 GEMM
-    // (then the bf16 bits are exact and the only copy kept)
-    constexpr bool KF = !(XBF && GBF);
     float xv[SB][KF ? KS : 1];
     i16x8 xbv[SB][NB];
-    float xerr[SB];  // ||x - bf16(x)||^2 partial when float32 X feeds the bf16 GEMM
+    i16x8 xlv[SB][XLO ? NB : 1];
+    float xres[SB];  // ||x - hi - lo||^2 lane partial (XLO)
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
-      xerr[s] = 0.f;
+      xres[s] = 0.f;
       const int64_t i = row0 + 16 * s + r16;
-      if constexpr (!KF) {
+      if constexpr (GBF && XBF) {
         const uint16_t* xr = (const uint16_t*)a.X + i * d + g * KS;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -369,26 +401,31 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
             }
           }
         }
-      } else {
-      if (i < a.N) {
-        load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xv[s]);
-      } else {
+      } else if constexpr (XLO) {
+        float t[KS];
+        if (i < a.N) {
+          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, t);
+        } else {
 #pragma unroll
-        for (int q = 0; q < KS; ++q) xv[s][q] = 0.f;
-      }
-      if constexpr (GBF) {
+          for (int q = 0; q < KS; ++q) t[q] = 0.f;
+        }
 #pragma unroll
         for (int q = 0; q < NB; ++q)
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const uint16_t hb = f32_to_bf16_rne(xv[s][8 * q + e]);
-            xbv[s][q][e] = (short)hb;
-            if (!XBF) {
-              const float df = xv[s][8 * q + e] - bf16_to_f32(hb);
-              xerr[s] = fmaf(df, df, xerr[s]);
-            }
+            uint16_t h, l;
+            const float r = (float)bf16_split(t[8 * q + e], &h, &l);
+            xbv[s][q][e] = (short)h;
+            xlv[s][q][e] = (short)l;
+            xres[s] = fmaf(r, r, xres[s]);
           }
-      }
+      } else {
+        if (i < a.N) {
+          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xv[s]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) xv[s][q] = 0.f;
+        }
       }
     }
 
@@ -406,7 +443,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
       }
       for (int tt = 0; tt < rows; tt += 16) {
         f32x4 acc[SB];
-        tile_mfma<KS, SB, GBF>(Cs, Cbs, ncs, tt, g, r16, xv, xbv, acc);
+        tile_mfma<KS, SB, GBF, XLO>(Cs, Cbs, ncs, tt, g, r16, xv, xbv, xlv, acc);
         const int jb = c0 + tt;
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
@@ -414,9 +451,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
           for (int r = 0; r < 4; ++r) {
             const float v = acc[s][r];
             const bool gt = v > best[s];
-            // second best = median of (v, best, second) since second <= best
+            // second best = median of (v, best, second) since second <= best;
+            // best and its index follow the one compare (two selects).  No
+            // inline asm may read these MFMA results: the compiler inserts the
+            // MFMA-to-VALU wait states only for instructions it can see.
             sec[s] = __builtin_amdgcn_fmed3f(v, best[s], sec[s]);
-            best[s] = vmax(v, best[s]);
+            best[s] = gt ? v : best[s];
             bidx[s] = gt ? (jb + r) : bidx[s];
           }
         }
@@ -443,28 +483,42 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
         sc = ns;
       }
       if (bi < 0 || bi >= K) bi = 0;
-      auto xf = [&](int q) -> float {
-        if constexpr (KF) return xv[s][q];
-        else return bf_elem(xbv[s][q >> 3], q & 7);
-      };
+      // this lane's float32 values of its KS dimensions of the row
+      float xe[KS];
+      if constexpr (KF) {
+#pragma unroll
+        for (int q = 0; q < KS; ++q) xe[q] = xv[s][q];
+      } else if constexpr (XBF) {
+#pragma unroll
+        for (int q = 0; q < KS; ++q) xe[q] = bf_elem(xbv[s][q >> 3], q & 7);
+      } else {
+        if (valid) {
+          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xe);
+        } else {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) xe[q] = 0.f;
+        }
+      }
       float xs = 0.f;
 #pragma unroll
-      for (int q = 0; q < KS; ++q) xs = fmaf(xf(q), xf(q), xs);
+      for (int q = 0; q < KS; ++q) xs = fmaf(xe[q], xe[q], xs);
       xs += __shfl_xor(xs, 16, kWave);
       xs += __shfl_xor(xs, 32, kWave);
       const float nx = sqrtf(xs) * 1.0001f;
       float bound;
-      if (GBF) {
-        // s_j is computed from bf16(x) . bf16(c_j): |x.c - x^.c^| <= ex ||c|| + ||x^|| delta_j
-        float ex = 0.f;
-        if (!XBF) {
-          float e2 = xerr[s];
-          e2 += __shfl_xor(e2, 16, kWave);
-          e2 += __shfl_xor(e2, 32, kWave);
-          ex = sqrtf(e2) * 1.0001f;
-        }
-        const float cb = cmax + dmax;
-        bound = gam * (nx + ex + cb) * (nx + ex + cb) + 4.0f * (ex * cb + (nx + ex) * dmax);
+      if constexpr (GBF && XBF) {
+        // per s_j: summation error + ||x|| r_j; gap error twice that, margin 2
+        bound = gam * (nx + cb) * (nx + cb) + 4.0f * nx * rmax;
+      } else if constexpr (XLO) {
+        // x = xh + xl + rx: the dropped products are xh.r_j + xl.lo_j + xl.r_j
+        // + rx.c_j, with ||xh|| + ||xl|| <= 1.008 ||x||, ||xl|| <= 2^-8 1.004 ||x||
+        // and ||lo_j|| <= 2^-8 1.004 ||c_j||
+        float e2 = xres[s];
+        e2 += __shfl_xor(e2, 16, kWave);
+        e2 += __shfl_xor(e2, 32, kWave);
+        const float nrx = sqrtf(e2) * 1.0001f;
+        const float nxs = nx * 1.008f;
+        bound = gam * (nxs + cb) * (nxs + cb) + 4.0f * (nxs * rmax + nx * 1.6e-5f * cmax + nrx * cmax);
       } else {
         bound = gam * (nx + cmax) * (nx + cmax);
       }
@@ -478,7 +532,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
           if (g * KS + q < d) {
-            const double df = (double)xf(q) - (double)cr[q];
+            const double df = (double)xe[q] - (double)cr[q];
             p = fma(df, df, p);
           }
         }
@@ -492,26 +546,21 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu((!GBF &&
       while (fm) {
         const int f = __ffsll((long long)fm) - 1;
         fm &= fm - 1;
+        // the flagged row is spread over lanes r16 == f of the 4 lane groups
+        if (r16 == f) {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xe[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double dist;
         int j;
-        bool lds_path = false;
-        if constexpr (!GBF) lds_path = resident;
-        if (lds_path) {
-          // the flagged row is spread over lanes r16 == f of the 4 lane groups
-          if (r16 == f) {
-#pragma unroll
-            for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xf(q);
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        } else {
-          j = exact_argmin<XBF>(a.X, row0 + 16 * s + f, d, a.C, K, lane, &dist);
-        }
+        if (!GBF && resident) j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist);
+        else j = exact_argmin<DP>(xrow, d, a.C, K, lane, &dist);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (j >= 0 && r16 == f) { bi = j; term = dist; }
       }
 
@@ -591,18 +640,27 @@ static KernelPick pick_one(int K) {
   // lane group (measured best for d = 32: 190 us vs 213 us with four blocks
   // at N = 1e6, K = 256), one block beyond.
   // The bf16 GEMM on bf16 rows streams centroid chunks through LDS for large
-  // K: 16 waves of three 16-sample blocks share each staged chunk.  Wider or
-  // float32 rows need the register room of 4-wave workgroups.
+  // K: 16 waves of two 16-sample blocks share each staged chunk (three blocks
+  // exceed the 128 registers of a 1024-thread workgroup).  Float32 rows on
+  // the bf16 GEMM hold hi and lo operands: one block per wave.
   constexpr bool BIG = GBF && XBF && KS <= 32;
-  constexpr int SB0 = BIG ? 3 : (KS <= 32 ? 2 : 1);
+  constexpr int SB0 = BIG ? 2 : (GBF ? 1 : (KS <= 32 ? 2 : 1));
   constexpr int W0 = BIG ? 16 : 4;
   // alternative shapes are only built for the benchmark widths (d = 32 in
   // float32, d = 128 in bfloat16) and the candidate role
-  if constexpr (ROLE == kRoleCand && ((KS == 8 && !GBF) || (KS == 32 && GBF))) {
+  if constexpr (ROLE == kRoleCand && KS == 8 && !GBF) {
     switch (shape_override()) {
       case 1: return make_pick<KS, ROLE, XBF, GBF, SB0, 8>(K);
       case 2: return make_pick<KS, ROLE, XBF, GBF, 4, 4>(K);
       case 3: return make_pick<KS, ROLE, XBF, GBF, 1, 8>(K);
+      default: break;
+    }
+  }
+  if constexpr (ROLE == kRoleCand && KS == 32 && BIG) {
+    switch (shape_override()) {
+      case 1: return make_pick<KS, ROLE, XBF, GBF, 3, 8>(K);
+      case 2: return make_pick<KS, ROLE, XBF, GBF, 2, 8>(K);
+      case 3: return make_pick<KS, ROLE, XBF, GBF, 1, 16>(K);
       default: break;
     }
   }
@@ -694,7 +752,7 @@ hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Centroid preparation: ||c_j||^2 (float64 sum, rounded), bf16 shadow, delta_j
+// Centroid preparation: ||c_j||^2 (float64 sum, rounded), bf16 hi/lo pair, residual norms
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_prep(const float* C, int K, int d, float* nc, uint16_t* Cb,
@@ -703,15 +761,17 @@ __global__ __launch_bounds__(256) void k_prep(const float* C, int K, int d, floa
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= K) return;
   const float* cr = C + (int64_t)j * d;
+  const int64_t KD = (int64_t)K * d;
   double p = 0.0, e = 0.0;
   for (int k = lane; k < d; k += kWave) {
     const float c = cr[k];
     p = fma((double)c, (double)c, p);
     if (Cb) {
-      const uint16_t b = f32_to_bf16_rne(c);
-      Cb[(int64_t)j * d + k] = b;
-      const double df = (double)c - (double)bf16_to_f32(b);
-      e = fma(df, df, e);
+      uint16_t h, l;
+      const double r = bf16_split(c, &h, &l);
+      Cb[(int64_t)j * d + k] = h;
+      Cb[KD + (int64_t)j * d + k] = l;
+      e = fma(r, r, e);
     }
   }
   p = wave_sum(p);

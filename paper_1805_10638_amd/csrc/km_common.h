@@ -73,6 +73,24 @@ __device__ __forceinline__ float wave_max(float v) {
 
 // Drop a pending error of an unrelated earlier runtime call so that the
 // check after a launch reports that launch only.
+// bfloat16 pair for the distance GEMM: hi = rne(f), lo = rne(f - hi) (the
+// difference is exact in float32).  Returns the residual f - hi - lo, exact in
+// float64; |residual| <= 2^-16 |f| for normal values.
+__device__ __forceinline__ uint16_t bf16_rne_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ double bf16_split(float f, uint16_t* hi, uint16_t* lo) {
+  const uint16_t h = bf16_rne_bits(f);
+  const float fh = __uint_as_float(((uint32_t)h) << 16);
+  const float r1 = f - fh;
+  const uint16_t l = bf16_rne_bits(r1);
+  *hi = h;
+  *lo = l;
+  return (double)r1 - (double)__uint_as_float(((uint32_t)l) << 16);
+}
+
 inline void clear_pending_error() { (void)hipGetLastError(); }
 
 __device__ __forceinline__ unsigned popc64(unsigned long long m) { return __popcll(m); }

@@ -16,8 +16,8 @@ struct AssignArgs {
   int d, K;
   const float* C;         // K x d float32 centroids
   const float* nc;        // K squared norms of C (float32)
-  const uint16_t* Cb;     // K x d bfloat16 shadow of C (bf16 GEMM only)
-  const float* delta;     // K norms ||c_j - bf16(c_j)|| (bf16 GEMM only)
+  const uint16_t* Cb;     // bf16 GEMM only: 2 x K x d bfloat16 pair of C, hi rows then lo rows
+  const float* delta;     // bf16 GEMM only: K residual norms ||c_j - hi_j - lo_j||
   int* lab;               // label buffers: 3 x N (solver roles) or N (plain role)
   const int* lab_prev;    // plain role: labels to count changes against, or null
   double* e_part;         // per-workgroup energy partials of this pass
@@ -28,7 +28,7 @@ struct AssignArgs {
 int assign_grid(const AssignArgs& a);   // workgroups of one launch (persistent grid)
 hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s);
 
-// ||c_j||^2 (and the bfloat16 shadow with its error norms when Cb != null).
+// ||c_j||^2 (and the bfloat16 hi/lo pair with its residual norms when Cb != null).
 hipError_t launch_prep(const float* C, int K, int d, float* nc, uint16_t* Cb, float* delta,
                        hipStream_t s);
 

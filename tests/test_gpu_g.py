@@ -142,6 +142,10 @@ def test_invalid_arguments():
     with pytest.raises(km.KMError) as e:
         km.kmeans_solve(X, C, tol=-1.0)
     assert e.value.status == -1
+    Xo = torch.zeros(401, dtype=torch.float32, device="cuda")[1:].view(100, 4)  # 4-byte offset
+    with pytest.raises(km.KMError) as e:
+        km.kmeans_g(Xo, C)
+    assert e.value.status == -1
     Xn = _mixture(100, 4, 4, seed=0)
     Xn[3, 1] = np.nan
     with pytest.raises(km.KMError) as e:
