@@ -84,6 +84,19 @@ int km_version(void);
  * (1) or not (0, default).  Results appear in km_solve_stats.assign_ms. */
 km_status km_set_timing(km_ctx *ctx, int enable);
 
+/* Tile shape of the assignment kernel for later calls on this context whose
+ * precision, X type, padded width (from d) and K bucket (the power of two
+ * at or above K, at least 16) match (prec, xt, d, K).  shape 0 is the
+ * built-in default; 1 .. KM_TILE_SHAPES-1 select alternatives of the kernel
+ * family (rows per workgroup, waves, LDS chunk).  Labels and centroids do
+ * not depend on the shape; E may differ in its last bits (summation order
+ * of per-workgroup partials).  This is the hook of the autotuner.  Returns
+ * KM_EINVAL for a shape or size outside the supported range. */
+#define KM_TILE_SHAPES 4
+km_status km_set_tile_shape(km_ctx *ctx, km_prec prec, km_xtype xt, int32_t d, int32_t K, int32_t shape);
+/* Current shape for (prec, xt, d, K); -1 for invalid arguments. */
+int32_t km_get_tile_shape(const km_ctx *ctx, km_prec prec, km_xtype xt, int32_t d, int32_t K);
+
 typedef struct {
   int64_t changed;         /* rows whose label differs from rho_prev (0 if rho_prev NULL) */
   int64_t flagged_rows;    /* rows re-checked with float64 differences */

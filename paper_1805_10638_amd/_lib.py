@@ -93,6 +93,10 @@ def load_library(path: str | None = None):
     lib.km_set_stream.restype = ct.c_int
     lib.km_set_timing.argtypes = [vp, ct.c_int]
     lib.km_set_timing.restype = ct.c_int
+    lib.km_set_tile_shape.argtypes = [vp, ct.c_int, ct.c_int, i32, i32, i32]
+    lib.km_set_tile_shape.restype = ct.c_int
+    lib.km_get_tile_shape.argtypes = [vp, ct.c_int, ct.c_int, i32, i32]
+    lib.km_get_tile_shape.restype = ct.c_int
     lib.km_status_str.argtypes = [ct.c_int]
     lib.km_status_str.restype = ct.c_char_p
     lib.km_last_error.argtypes = [vp]
@@ -144,6 +148,15 @@ class Context:
     def set_timing(self, on: bool):
         self.lib.km_set_timing(self.h, 1 if on else 0)
 
+    def set_tile_shape(self, prec: str, xtype: str, d: int, K: int, shape: int):
+        """Assignment tile shape for calls whose (prec, X type, width, K bucket)
+        match; 0 is the built-in default (see km_set_tile_shape)."""
+        st = self.lib.km_set_tile_shape(self.h, _prec(prec), _xt_name(xtype), d, K, shape)
+        self._check(st, "km_set_tile_shape")
+
+    def tile_shape(self, prec: str, xtype: str, d: int, K: int) -> int:
+        return self.lib.km_get_tile_shape(self.h, _prec(prec), _xt_name(xtype), d, K)
+
     def _check(self, st: int, what: str, allow=(KM_OK,)):
         if st in allow:
             return
@@ -168,6 +181,14 @@ def _xtype(X: torch.Tensor) -> int:
     if X.dtype in (torch.bfloat16, torch.int16, torch.uint16):
         return KM_X_BF16
     raise TypeError(f"X must be float32 or bfloat16 (got {X.dtype})")
+
+
+def _xt_name(x) -> int:
+    if x in ("f32", "float32", KM_X_F32):
+        return KM_X_F32
+    if x in ("bf16", "bfloat16", KM_X_BF16):
+        return KM_X_BF16
+    raise ValueError(f"unknown X type {x!r}")
 
 
 def _prec(p) -> int:

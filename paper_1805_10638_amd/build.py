@@ -22,7 +22,8 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libkmaa.so")
 
-SOURCES = ["km_assign.hip", "km_update.hip", "km_anderson.hip", "km_api.hip"]
+SOURCES = ["km_assign_f32.hip", "km_assign_bf16.hip", "km_assign.hip", "km_update.hip", "km_anderson.hip",
+           "km_api.hip"]
 
 ARCH = "gfx950"
 # Packed-FP32 instructions are disabled for all device code.
@@ -51,7 +52,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2) // 2))
+    jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 2))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"

@@ -9,7 +9,7 @@
 #include <vector>
 
 #include "../../include/km.h"
-#include "km_launch.h"
+#include "km_assign_kernel.h"
 
 using namespace km;
 
@@ -50,6 +50,9 @@ struct km_ctx {
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipEvent_t ta[2] = {nullptr, nullptr}, tb[2] = {nullptr, nullptr};  // around assignment
+
+  // assignment tile shape per (precision, X type, padded width, K bucket)
+  int8_t tile_shape[2][2][10][9] = {};
 
   // per-iteration graphs (two, so that one can be inspected while the other runs)
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -229,6 +232,26 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
   return KM_OK;
 }
 
+// Tile-shape table index of (d, K): padded width class and K bucket.
+static bool tile_slot(int gemm_bf16, int32_t d, int32_t K, int* wi, int* kb) {
+  static const int widths[] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 64};
+  if (d < 1 || d > kMaxD || K < 1 || K > kMaxK) return false;
+  const int ks = pick_ks(d, gemm_bf16);
+  *wi = -1;
+  for (int i = 0; i < 10; ++i)
+    if (widths[i] == ks) *wi = i;
+  int b = 0;
+  while ((16 << b) < K) ++b;
+  *kb = b;
+  return *wi >= 0 && b < 9;
+}
+
+static int shape_for(const km_ctx* c, int gemm_bf16, int xbf, int32_t d, int32_t K) {
+  int wi, kb;
+  if (!tile_slot(gemm_bf16, d, K, &wi, &kb)) return 0;
+  return c->tile_shape[gemm_bf16 ? 1 : 0][xbf ? 1 : 0][wi][kb];
+}
+
 static km_status check_common(km_ctx* c, const void* X, int xt, int64_t N, int32_t d, int32_t K,
                               int prec) {
   if (!c) return KM_EINVAL;
@@ -319,6 +342,23 @@ km_status km_set_stream(km_ctx* c, void* stream) {
   return KM_OK;
 }
 
+km_status km_set_tile_shape(km_ctx* c, km_prec prec, km_xtype xt, int32_t d, int32_t K, int32_t shape) {
+  if (!c || (prec != KM_GEMM_F32 && prec != KM_GEMM_BF16) || (xt != KM_X_F32 && xt != KM_X_BF16) ||
+      shape < 0 || shape >= KM_TILE_SHAPES)
+    return KM_EINVAL;
+  int wi, kb;
+  if (!tile_slot(prec == KM_GEMM_BF16, d, K, &wi, &kb)) return KM_EINVAL;
+  c->tile_shape[prec == KM_GEMM_BF16 ? 1 : 0][xt == KM_X_BF16 ? 1 : 0][wi][kb] = (int8_t)shape;
+  return KM_OK;
+}
+
+int32_t km_get_tile_shape(const km_ctx* c, km_prec prec, km_xtype xt, int32_t d, int32_t K) {
+  if (!c || (prec != KM_GEMM_F32 && prec != KM_GEMM_BF16) || (xt != KM_X_F32 && xt != KM_X_BF16)) return -1;
+  int wi, kb;
+  if (!tile_slot(prec == KM_GEMM_BF16, d, K, &wi, &kb)) return -1;
+  return c->tile_shape[prec == KM_GEMM_BF16 ? 1 : 0][xt == KM_X_BF16 ? 1 : 0][wi][kb];
+}
+
 km_status km_set_timing(km_ctx* c, int enable) {
   if (!c) return KM_EINVAL;
   c->timing = enable != 0;
@@ -372,6 +412,7 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   a.Cb = gbf ? c->Cb_tmp : nullptr; a.delta = gbf ? c->del_tmp : nullptr;
   a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->e_part; a.ctl = c->ctl;
   a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
+  a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
   HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
   const int grid = assign_grid(a);
   HIP_TRY(c, launch_reduce_energy(c->e_part, grid, c->e_out, st_), "energy");
@@ -463,6 +504,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   a.Cb = gbf ? c->Cb_tmp : nullptr; a.delta = gbf ? c->del_tmp : nullptr;
   a.lab = c->labels; a.lab_prev = nullptr; a.e_part = c->e_part; a.ctl = c->ctl;
   a.xbf16 = xbf; a.gemm_bf16 = gbf;
+  a.shape = shape_for(c, gbf, xbf, d, K);
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xbf;
   u.lab = c->labels; u.lab_from_ctl = 1; u.lrank = c->lrank; u.blockcount = c->blockcount;
@@ -531,8 +573,8 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   };
 
   char keybuf[512];
-  snprintf(keybuf, sizeof keybuf, "%p|%d|%lld|%d|%d|%d|%d|%p|%p|%p", X, (int)xt, (long long)N, d, K,
-           cap, (int)gbf, (void*)opt.trace_C, (void*)opt.trace_rec, c->arena);
+  snprintf(keybuf, sizeof keybuf, "%p|%d|%lld|%d|%d|%d|%d|%d|%p|%p|%p", X, (int)xt, (long long)N, d, K,
+           cap, (int)gbf, a.shape, (void*)opt.trace_C, (void*)opt.trace_rec, c->arena);
   if (c->gkey != keybuf) {
     for (hipGraphExec_t& g : c->gexec) {
       if (g) (void)hipGraphExecDestroy(g);

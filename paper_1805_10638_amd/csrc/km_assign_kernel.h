@@ -1,0 +1,815 @@
+// Assignment step (Sec. 1, Eq. (3)) fused with the energy of Eq. (1).
+//
+// The squared distance ||x - c_j||^2 = ||x||^2 - 2 (x.c_j - ||c_j||^2 / 2), so
+// the argmin over j is the argmax of s_j = x.c_j - ||c_j||^2 / 2.  The s_j
+// of a 16-centroid x 16-sample tile come out of MFMA (v_mfma_f32_16x16x4f32,
+// or v_mfma_f32_16x16x32_bf16) with the accumulator pre-loaded with
+// -||c_j||^2 / 2; the running best and second-best s_j of each sample stay in
+// registers across the whole K loop.
+//
+// Operand layout of the 16x16 MFMAs: lane l supplies row l%16 of A and
+// column l%16 of B for the k-slice owned by lane group g = l/16, and
+// receives D[4g+r][l%16], r = 0..3.  A is a tile of 16 centroids, B a tile of
+// 16 samples, so each lane accumulates 4 centroids of one sample.  The
+// reduction index is permuted so that lane group g owns the contiguous
+// dimensions [g*KS, g*KS+KS): sample rows are read with wide contiguous loads
+// and kept in registers for the whole K loop.
+//
+// Workgroups are persistent: each stages the centroids into LDS once (when
+// they fit, else in chunks per row group) and then walks row groups a grid
+// apart.  The same body serves one instance (the launch grid) and batched
+// launches (a slice of the grid per instance).
+//
+// Exactness.  With u = 2^-24 and dp the padded dimension, every computed s_j
+// is within gamma/2 * (||x|| + max_j ||c_j||)^2 of its exact value, gamma =
+// (dp + 3) u / (1 - (dp + 3) u).  A sample whose best and second-best s_j
+// differ by at most twice that bound (with a further factor 2 of margin) is
+// re-checked: all K distances are recomputed as float64 sums of squared
+// float64 differences, ties to the lowest index.  Every other sample's label
+// is provably the exact argmin.  The energy term of every sample is the
+// float64 direct-difference distance to its label.
+//
+// bfloat16 GEMM.  Each centroid is held as a bfloat16 pair hi + lo (hi the
+// rounding of c, lo the rounding of c - hi) and s_j accumulates x.hi + x.lo in
+// float32: bf16 x bf16 products are exact, so the error is the float32
+// summation of 2 dp + 3 terms plus ||x|| r_j, r_j = ||c_j - hi_j - lo_j|| <=
+// 2^-16 ||c_j||.  A single bfloat16 copy of c would leave an error near
+// 2^-9 ||x|| ||c||, about a hundred times the float32 bound, and the re-check
+// would then dominate.  Float32 rows are split the same way (x.hi + x.lo ~ x,
+// three products per slice, x_lo . c_lo and the residuals added to the bound).
+// X stored as bfloat16 is exact in both modes.
+
+#pragma once
+
+#include "km_launch.h"
+
+namespace km {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+
+__device__ __forceinline__ float ld_x(const void* X, int64_t idx, bool bf) {
+  return bf ? bf16_to_f32(((const uint16_t*)X)[idx]) : ((const float*)X)[idx];
+}
+
+// Load dims [k0, k0 + KS) of row i as float32 (zero beyond d).
+template <int KS, bool XBF>
+__device__ __forceinline__ void load_chunk(const void* X, int64_t i, int d, int k0, bool vec,
+                                           float (&out)[KS]) {
+  if constexpr (KS % 4 == 0) {
+    if (vec) {
+      if constexpr (XBF) {
+        const uint2* p = (const uint2*)((const uint16_t*)X + i * d + k0);
+#pragma unroll
+        for (int q = 0; q < KS / 4; ++q) {
+          uint2 v = p[q];
+          out[4 * q + 0] = __uint_as_float(v.x << 16);
+          out[4 * q + 1] = __uint_as_float(v.x & 0xFFFF0000u);
+          out[4 * q + 2] = __uint_as_float(v.y << 16);
+          out[4 * q + 3] = __uint_as_float(v.y & 0xFFFF0000u);
+        }
+      } else {
+        const float4* p = (const float4*)((const float*)X + i * d + k0);
+#pragma unroll
+        for (int q = 0; q < KS / 4; ++q) {
+          float4 v = p[q];
+          out[4 * q + 0] = v.x;
+          out[4 * q + 1] = v.y;
+          out[4 * q + 2] = v.z;
+          out[4 * q + 3] = v.w;
+        }
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KS; ++q) {
+    const int k = k0 + q;
+    out[q] = (k < d) ? ld_x(X, i * d + k, XBF) : 0.f;
+  }
+}
+
+// Exact re-check of one flagged sample by the whole wave: float64 direct
+// differences to all K centroids, lowest index on ties.  Returns the label
+// (or -1 if every distance is NaN) and its distance in *dist.
+__device__ __forceinline__ int wave_argmin(double bd, int bj, double* dist) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ob = __shfl_xor(bd, off, kWave);
+    const int oj = __shfl_xor(bj, off, kWave);
+    const bool take = (ob < bd) || (ob == bd && (unsigned)oj < (unsigned)bj);
+    bd = take ? ob : bd;
+    bj = take ? oj : bj;
+  }
+  *dist = bd;
+  return bj;
+}
+
+// Centroids from global memory, the sample staged in LDS (xrow, zero-padded
+// to DP): float64 differences over the d real dimensions.
+template <int DP>
+__device__ __forceinline__ int exact_argmin(const float* xrow, int d, const float* C, int K, int lane,
+                                            double* dist) {
+  double bd = __builtin_inf();
+  int bj = -1;
+  const bool v4 = (d % 4) == 0;
+  for (int j = lane; j < K; j += kWave) {
+    const float* cr = C + (int64_t)j * d;
+    double s = 0.0;
+    if (v4) {
+      for (int k = 0; k < d; k += 4) {
+        const float4 x4 = *(const float4*)(xrow + k);
+        const float4 c4 = *(const float4*)(cr + k);
+        double df = (double)x4.x - (double)c4.x; s = fma(df, df, s);
+        df = (double)x4.y - (double)c4.y; s = fma(df, df, s);
+        df = (double)x4.z - (double)c4.z; s = fma(df, df, s);
+        df = (double)x4.w - (double)c4.w; s = fma(df, df, s);
+      }
+    } else {
+      for (int k = 0; k < d; ++k) {
+        const double df = (double)xrow[k] - (double)cr[k];
+        s = fma(df, df, s);
+      }
+    }
+    if (s < bd) { bd = s; bj = j; }
+  }
+  return wave_argmin(bd, bj, dist);
+}
+
+// Centroids resident in LDS (row stride ld, zero-padded to DP) and the
+// sample staged in LDS (xrow, zero-padded to DP).
+template <int DP>
+__device__ __forceinline__ int exact_argmin_lds(const float* xrow, const float* Cs, int ld, int K, int lane,
+                                             double* dist) {
+  double bd = __builtin_inf();
+  int bj = -1;
+  for (int j = lane; j < K; j += kWave) {
+    const float* cr = Cs + j * ld;
+    double s = 0.0;
+    if constexpr (DP % 4 == 0) {
+#pragma unroll 4
+      for (int k = 0; k < DP; k += 4) {
+        const float4 x4 = *(const float4*)(xrow + k);
+        const float4 c4 = *(const float4*)(cr + k);
+        double df = (double)x4.x - (double)c4.x; s = fma(df, df, s);
+        df = (double)x4.y - (double)c4.y; s = fma(df, df, s);
+        df = (double)x4.z - (double)c4.z; s = fma(df, df, s);
+        df = (double)x4.w - (double)c4.w; s = fma(df, df, s);
+      }
+    } else {
+      for (int k = 0; k < DP; ++k) {
+        const double df = (double)xrow[k] - (double)cr[k];
+        s = fma(df, df, s);
+      }
+    }
+    if (s < bd) { bd = s; bj = j; }
+  }
+  return wave_argmin(bd, bj, dist);
+}
+
+// Workgroup scratch after the centroid chunk and its norms (bytes): maxima
+// (32 floats), energy partials (16 doubles), re-check queue counters (3 ints,
+// padded), per-wave re-check winners (kQueue x 16 ints and doubles).  Staged
+// rows follow: kQueue queued rows and one row per wave for immediate
+// re-checks ((kQueue + 16) x DP floats).
+constexpr int kQueue = 4;
+constexpr int kAssignScratch = 128 + 128 + 128 + kQueue * 16 * 4 + kQueue * 16 * 8;
+
+// LB: bytes of LDS a workgroup may use (centroid chunk, norms, scratch).
+template <int KS, bool GBF, int LB>
+struct Tile {
+  static constexpr int DP = 4 * KS;                    // padded dimension
+  static constexpr int NB = GBF ? KS / 8 : 1;          // bf16 MFMAs per tile and operand half
+  static constexpr int LD = DP + 4;                    // f32 LDS row stride (floats)
+  static constexpr int LDB = 2 * DP + 8;               // bf16 LDS row stride: hi[DP], lo[DP], pad
+  static constexpr int ROW_BYTES = GBF ? LDB * 2 : LD * 4;
+  // centroid rows per LDS chunk (multiple of 16) for a given K
+  static __host__ __device__ int chunk_rows(int K) {
+    const int kpad = (K + 15) & ~15;
+    int c = ((LB - (kQueue + 16) * DP * 4 - kAssignScratch) / (ROW_BYTES + 4)) & ~15;
+    return c < kpad ? c : kpad;
+  }
+  static __host__ __device__ size_t lds_bytes(int K) {
+    const int c = chunk_rows(K);
+    return (size_t)c * ROW_BYTES + (size_t)c * 4 + kAssignScratch + (size_t)(kQueue + 16) * DP * 4;
+  }
+};
+
+// MFMAs of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk) against
+// the SB sample blocks of this wave; accumulators start at -||c||^2/2.
+// bf16: x.hi + x.lo per slice (and x_lo.hi for float32 rows, XLO).
+template <int KS, int SB, bool GBF, bool XLO, int LB, typename XV>
+__device__ __forceinline__ void tile_mfma(const float* Cs, const uint16_t* Cbs, const float* ncs,
+                                          int tt, int g, int r16, const XV& xv,
+                                          const i16x8 (&xbv)[SB][Tile<KS, GBF, LB>::NB],
+                                          const i16x8 (&xlv)[SB][XLO ? Tile<KS, GBF, LB>::NB : 1],
+                                          f32x4 (&acc)[SB]) {
+  using T = Tile<KS, GBF, LB>;
+  const f32x4 n4 = *(const f32x4*)(ncs + tt + 4 * g);
+#pragma unroll
+  for (int s = 0; s < SB; ++s) acc[s] = n4;
+  if constexpr (GBF) {
+    i16x8 ah[T::NB], al[T::NB];
+    const uint16_t* cr = Cbs + (tt + r16) * T::LDB + g * KS;
+#pragma unroll
+    for (int q = 0; q < T::NB; ++q) {
+      ah[q] = *(const i16x8*)(cr + 8 * q);
+      al[q] = *(const i16x8*)(cr + T::DP + 8 * q);
+    }
+#pragma unroll
+    for (int q = 0; q < T::NB; ++q) {
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf16x8, ah[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf16x8, al[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+      if constexpr (XLO) {
+#pragma unroll
+        for (int s = 0; s < SB; ++s)
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, ah[q]), __builtin_bit_cast(bf16x8, xlv[s][q]), acc[s], 0, 0, 0);
+      }
+    }
+  } else {
+    float av[KS];
+    const float* cr = Cs + (tt + r16) * T::LD + g * KS;
+    if constexpr (KS % 4 == 0) {
+#pragma unroll
+      for (int q = 0; q < KS; q += 4) {
+        const float4 v = *(const float4*)(cr + q);
+        av[q] = v.x; av[q + 1] = v.y; av[q + 2] = v.z; av[q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KS; ++q) av[q] = cr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < KS; ++q)
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], xv[s][q], acc[s], 0, 0, 0);
+  }
+}
+
+// bfloat16 bits -> float32 of element q of a lane's bf16 chunk
+__device__ __forceinline__ float bf_elem(const i16x8& v, int e) {
+  return bf16_to_f32((uint16_t)v[e]);
+}
+
+// KS: padded dims per lane group; SB: 16-sample blocks per wave; W: waves
+// per workgroup (they share one LDS copy of the centroids); LB: LDS bytes.
+// bx / gx: this workgroup's index and the number of workgroups working on
+// this instance.
+template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
+__device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx) {
+  constexpr int NT = 64 * W;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using T = Tile<KS, GBF, LB>;
+  constexpr int DP = T::DP, LD = T::LD, LDB = T::LDB, NB = T::NB;
+  Ctl* ctl = a.ctl;
+  const int role = a.role;
+  if (role != kRolePlain) {
+    if (ctl->done) return;
+    if (role == kRoleFallback && !ctl->reject) return;
+  }
+  int* rho;
+  const int* prev;
+  if (role == kRoleCand) {
+    rho = a.lab + (int64_t)ctl->lab_cand * a.N;
+    prev = a.lab + (int64_t)ctl->lab_prev * a.N;
+  } else if (role == kRoleFallback) {
+    rho = a.lab + (int64_t)ctl->lab_fb * a.N;
+    prev = a.lab + (int64_t)ctl->lab_prev * a.N;
+  } else {
+    rho = a.lab;
+    prev = a.lab_prev;
+  }
+  const int slot = (role == kRoleFallback) ? 1 : 0;
+
+  const int d = a.d, K = a.K;
+  const int Kpad = (K + 15) & ~15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+
+  // LDS: centroid tile, -||c||^2/2 per row, small reduction scratch.
+  const int kchunk = T::chunk_rows(K);
+  const bool resident = kchunk >= Kpad;
+  float* Cs = (float*)smem_raw;                                  // kchunk x LD (f32 path)
+  uint16_t* Cbs = (uint16_t*)smem_raw;                           // kchunk x LDB (bf16 path)
+  float* ncs = (float*)(smem_raw + (size_t)kchunk * T::ROW_BYTES);
+  float* fred = ncs + kchunk;                                // 2 W floats (W <= 16)
+  double* dred = (double*)(fred + 32);                       // W doubles
+  int* qcnt = (int*)(fred + 64);                             // 3 rotating queue counters
+  int* qj = qcnt + 32;                                       // kQueue rows x 16 waves
+  double* qd = (double*)(qj + kQueue * 16);                  // kQueue rows x 16 waves
+  float* qx = (float*)(qd + kQueue * 16);                    // (kQueue + 16) staged rows x DP
+  if (tid < 3) qcnt[tid] = 0;
+
+  // max_j ||c_j||^2 and max_j r_j over the real centroids
+  float mx = 0.f, mdel = 0.f;
+  for (int j = tid; j < K; j += NT) {
+    mx = fmaxf(mx, a.nc[j]);
+    if (GBF) mdel = fmaxf(mdel, a.delta[j]);
+  }
+  mx = wave_max(mx);
+  mdel = wave_max(mdel);
+  if (lane == 0) { fred[wave] = mx; fred[16 + wave] = mdel; }
+  __syncthreads();
+  float cm2 = 0.f, dm = 0.f;
+#pragma unroll
+  for (int w = 0; w < W; ++w) { cm2 = fmaxf(cm2, fred[w]); dm = fmaxf(dm, fred[16 + w]); }
+  const float cmax = sqrtf(cm2) * 1.0001f;
+  const float rmax = GBF ? dm * 1.0001f : 0.f;
+  // float32 summation terms per s_j: dp products (f32), 2 dp or 3 dp exact
+  // bf16 products, plus the accumulator start and two roundings of margin
+  constexpr int NTERM = GBF ? (XBF ? 2 * DP + 3 : 3 * DP + 3) : DP + 3;
+  const float u = 5.9604644775390625e-8f;  // 2^-24
+  const float gam = 2.0f * ((float)NTERM * u) / (1.0f - (float)NTERM * u) * 1.001f;
+  // ||hi_j|| + ||lo_j|| <= (1 + 2^-7 + 2^-16) ||c_j||
+  const float cb = GBF ? cmax * 1.008f : cmax;
+
+  // Stage centroid rows [c0, c0 + rows) into LDS (zero padding beyond d and K).
+  auto stage = [&](int c0, int rows) {
+    if constexpr (GBF) {
+      const bool v8 = (d % 8) == 0;
+      const int64_t KD = (int64_t)K * d;
+      constexpr int V = DP / 8;   // 8-element vectors per half row
+      for (int e = tid; e < rows * 2 * V; e += NT) {
+        const int rr = e / (2 * V), rem = e - rr * (2 * V);
+        const int half = rem >= V ? 1 : 0, c8 = (rem - half * V) * 8, j = c0 + rr;
+        const uint16_t* src = a.Cb + half * KD + (int64_t)j * d;
+        i16x8 v;
+        if (v8 && j < K && c8 < d) {
+          v = *(const i16x8*)(src + c8);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            v[q] = (j < K && c8 + q < d) ? (short)src[c8 + q] : (short)0;
+        }
+        *(i16x8*)(Cbs + rr * LDB + half * DP + c8) = v;
+      }
+    } else {
+      const bool v4 = (d % 4) == 0;
+      for (int e = tid; e < rows * (DP / 4); e += NT) {
+        const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
+        float4 v;
+        if (v4 && j < K && c4 < d) {
+          v = *(const float4*)(a.C + (int64_t)j * d + c4);
+        } else {
+          v.x = (j < K && c4 + 0 < d) ? a.C[(int64_t)j * d + c4 + 0] : 0.f;
+          v.y = (j < K && c4 + 1 < d) ? a.C[(int64_t)j * d + c4 + 1] : 0.f;
+          v.z = (j < K && c4 + 2 < d) ? a.C[(int64_t)j * d + c4 + 2] : 0.f;
+          v.w = (j < K && c4 + 3 < d) ? a.C[(int64_t)j * d + c4 + 3] : 0.f;
+        }
+        *(float4*)(Cs + rr * LD + c4) = v;
+      }
+    }
+    for (int rr = tid; rr < rows; rr += NT) {
+      const int j = c0 + rr;
+      ncs[rr] = (j < K) ? -0.5f * a.nc[j] : -__builtin_inff();
+    }
+  };
+  if (resident) {
+    stage(0, Kpad);
+    __syncthreads();
+  }
+  // Re-check queue: kQueue rows per row group shared by the waves (slots by
+  // LDS atomics; a row's result does not depend on its slot), and one row
+  // per wave for immediate re-checks once the queue is full.  Row group n
+  // counts on qcnt[n % 3]: the counter of group n + 1 is cleared before the
+  // first barrier of group n, after every wave has read the one of n - 2.
+  // With float32 centroids resident in LDS a single wave re-checks a row
+  // quickly and the queue's barrier per row group would cost more.
+  constexpr int QT = kQueue;
+  float* xrow = qx + (QT + wave) * DP;             // this wave's immediate row
+  const bool use_queue = GBF || !resident;         // uniform per launch
+  int rot = 0;
+
+  const int64_t group_rows = 16 * SB * W;
+  const int64_t groups = (a.N + group_rows - 1) / group_rows;
+  const bool vec = (d == DP);
+  double e_wave = 0.0;
+  unsigned n_changed = 0, n_flag = 0;
+  // float32 copy of the rows in registers only for the float32 GEMM; bf16 rows
+  // are exact as bf16; float32 rows on the bf16 GEMM keep hi and lo (XLO)
+  constexpr bool KF = !GBF;
+  constexpr bool XLO = GBF && !XBF;
+
+  for (int64_t grp = bx; grp < groups; grp += gx) {
+    // Sample rows of this wave, kept in registers.
+    const int64_t row0 = grp * group_rows + (int64_t)wave * (16 * SB);
+    float xv[SB][KF ? KS : 1];
+    i16x8 xbv[SB][NB];
+    i16x8 xlv[SB][XLO ? NB : 1];
+    float xres[SB];  // ||x - hi - lo||^2 lane partial (XLO)
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      xres[s] = 0.f;
+      const int64_t i = row0 + 16 * s + r16;
+      if constexpr (GBF && XBF) {
+        const uint16_t* xr = (const uint16_t*)a.X + i * d + g * KS;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (i < a.N && vec) {
+            xbv[s][q] = *(const i16x8*)(xr + 8 * q);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int k = g * KS + 8 * q + e;
+              xbv[s][q][e] = (i < a.N && k < d) ? (short)xr[8 * q + e] : (short)0;
+            }
+          }
+        }
+      } else if constexpr (XLO) {
+        float t[KS];
+        if (i < a.N) {
+          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, t);
+        } else {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) t[q] = 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            uint16_t h, l;
+            const float r = (float)bf16_split(t[8 * q + e], &h, &l);
+            xbv[s][q][e] = (short)h;
+            xlv[s][q][e] = (short)l;
+            xres[s] = fmaf(r, r, xres[s]);
+          }
+      } else {
+        if (i < a.N) {
+          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xv[s]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) xv[s][q] = 0.f;
+        }
+      }
+    }
+
+    float best[SB], sec[SB];
+    int bidx[SB];
+#pragma unroll
+    for (int s = 0; s < SB; ++s) { best[s] = -__builtin_inff(); sec[s] = -__builtin_inff(); bidx[s] = 0; }
+
+    for (int c0 = 0; c0 < Kpad; c0 += kchunk) {
+      const int rows = (Kpad - c0) < kchunk ? (Kpad - c0) : kchunk;
+      if (!resident) {
+        __syncthreads();
+        stage(c0, rows);
+        __syncthreads();
+      }
+      for (int tt = 0; tt < rows; tt += 16) {
+        f32x4 acc[SB];
+        tile_mfma<KS, SB, GBF, XLO, LB>(Cs, Cbs, ncs, tt, g, r16, xv, xbv, xlv, acc);
+        const int jb = c0 + tt;
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float v = acc[s][r];
+            const bool gt = v > best[s];
+            // second best = median of (v, best, second) since second <= best;
+            // best and its index follow the one compare (two selects).  No
+            // inline asm may read these MFMA results: the compiler inserts the
+            // MFMA-to-VALU wait states only for instructions it can see.
+            sec[s] = __builtin_amdgcn_fmed3f(v, best[s], sec[s]);
+            best[s] = gt ? v : best[s];
+            bidx[s] = gt ? (jb + r) : bidx[s];
+          }
+        }
+      }
+    }
+
+    // Epilogue: combine the 4 lane groups, flag near ties, exact energy terms.
+    int bi_s[SB], u_s[SB];
+    double term_s[SB];
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int64_t i = row0 + 16 * s + r16;
+      const bool valid = i < a.N;
+      float b = best[s], sc = sec[s];
+      int bi = bidx[s] + 4 * g;
+#pragma unroll
+      for (int off = 16; off <= 32; off <<= 1) {
+        const float ob = __shfl_xor(b, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        const float os = __shfl_xor(sc, off, kWave);
+        const float ns = fmaxf(fmaxf(sc, os), fminf(b, ob));
+        const bool take = (ob > b) || (ob == b && oi < bi);
+        b = take ? ob : b;
+        bi = take ? oi : bi;
+        sc = ns;
+      }
+      if (bi < 0 || bi >= K) bi = 0;
+      // this lane's float32 values of its KS dimensions of the row
+      float xe[KS];
+      if constexpr (KF) {
+#pragma unroll
+        for (int q = 0; q < KS; ++q) xe[q] = xv[s][q];
+      } else if constexpr (XBF) {
+#pragma unroll
+        for (int q = 0; q < KS; ++q) xe[q] = bf_elem(xbv[s][q >> 3], q & 7);
+      } else {
+        if (valid) {
+          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xe);
+        } else {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) xe[q] = 0.f;
+        }
+      }
+      float xs = 0.f;
+#pragma unroll
+      for (int q = 0; q < KS; ++q) xs = fmaf(xe[q], xe[q], xs);
+      xs += __shfl_xor(xs, 16, kWave);
+      xs += __shfl_xor(xs, 32, kWave);
+      const float nx = sqrtf(xs) * 1.0001f;
+      float bound;
+      if constexpr (GBF && XBF) {
+        // per s_j: summation error + ||x|| r_j; gap error twice that, margin 2
+        bound = gam * (nx + cb) * (nx + cb) + 4.0f * nx * rmax;
+      } else if constexpr (XLO) {
+        // x = xh + xl + rx: the dropped products are xh.r_j + xl.lo_j + xl.r_j
+        // + rx.c_j, with ||xh|| + ||xl|| <= 1.008 ||x||, ||xl|| <= 2^-8 1.004 ||x||
+        // and ||lo_j|| <= 2^-8 1.004 ||c_j||
+        float e2 = xres[s];
+        e2 += __shfl_xor(e2, 16, kWave);
+        e2 += __shfl_xor(e2, 32, kWave);
+        const float nrx = sqrtf(e2) * 1.0001f;
+        const float nxs = nx * 1.008f;
+        bound = gam * (nxs + cb) * (nxs + cb) + 4.0f * (nxs * rmax + nx * 1.6e-5f * cmax + nrx * cmax);
+      } else {
+        bound = gam * (nx + cmax) * (nx + cmax);
+      }
+      const bool flag = valid && !((b - sc) > bound);
+
+      // exact energy term of the provisional label
+      double term;
+      {
+        const float* cr = (resident && !GBF) ? Cs + bi * LD + g * KS : a.C + (int64_t)bi * d + g * KS;
+        double p = 0.0;
+        bool done4 = false;
+        if constexpr (KS % 4 == 0) {
+          if (vec) {  // whole chunk real: 16-byte loads of the centroid row
+#pragma unroll
+            for (int q = 0; q < KS; q += 4) {
+              const float4 c4 = *(const float4*)(cr + q);
+              double df = (double)xe[q] - (double)c4.x; p = fma(df, df, p);
+              df = (double)xe[q + 1] - (double)c4.y; p = fma(df, df, p);
+              df = (double)xe[q + 2] - (double)c4.z; p = fma(df, df, p);
+              df = (double)xe[q + 3] - (double)c4.w; p = fma(df, df, p);
+            }
+            done4 = true;
+          }
+        }
+        if (!done4) {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) {
+            if (g * KS + q < d) {
+              const double df = (double)xe[q] - (double)cr[q];
+              p = fma(df, df, p);
+            }
+          }
+        }
+        p += __shfl_xor(p, 16, kWave);
+        p += __shfl_xor(p, 32, kWave);
+        term = p;
+      }
+
+      // Flagged rows: queue them for the workgroup re-check below, or (queue
+      // full) re-check them now with this wave alone.  The row is spread over
+      // lanes r16 == f of the 4 lane groups.
+      int u_mine = -1;
+      unsigned long long fm = __ballot(flag) & 0xFFFFull;
+      n_flag += (unsigned)__popcll(fm);
+      while (fm) {
+        const int f = __ffsll((long long)fm) - 1;
+        fm &= fm - 1;
+        int slot = QT;
+        if (use_queue) {
+          if (lane == 0) slot = atomicAdd(&qcnt[rot], 1);
+          slot = __shfl(slot, 0, kWave);
+        }
+        if (slot < QT) {
+          float* dst = qx + slot * DP;
+          if (r16 == f) {
+#pragma unroll
+            for (int q = 0; q < KS; ++q) dst[g * KS + q] = xe[q];
+            u_mine = slot;
+          }
+          continue;
+        }
+        if (r16 == f) {
+#pragma unroll
+          for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xe[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double dist;
+        int j;
+        if (!GBF && resident) j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist);
+        else j = exact_argmin<DP>(xrow, d, a.C, K, lane, &dist);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (j >= 0 && r16 == f) { bi = j; term = dist; }
+      }
+      bi_s[s] = bi;
+      term_s[s] = term;
+      u_s[s] = u_mine;
+    }
+
+    // Workgroup re-check of the queued rows: every thread takes centroids
+    // tid, tid + NT, ... and scores each against all queued rows (float64
+    // direct differences, dimensions in order); per queued row the lowest
+    // distance wins, ties to the lowest index (waves in order).  The barrier
+    // also publishes the queue; it is taken by every wave of every group.
+    if (use_queue) {
+      if (tid == 0) qcnt[rot == 2 ? 0 : rot + 1] = 0;
+      __syncthreads();
+      int total = qcnt[rot];
+      total = total < QT ? total : QT;
+      rot = rot == 2 ? 0 : rot + 1;
+      if (total > 0) {
+        double bd[QT];
+        int bj[QT];
+#pragma unroll
+        for (int u = 0; u < QT; ++u) { bd[u] = __builtin_inf(); bj[u] = -1; }
+        const bool v4 = (d % 4) == 0;
+        for (int j = tid; j < K; j += NT) {
+          const float* cr = (!GBF && resident) ? Cs + j * LD : a.C + (int64_t)j * d;
+          double acc[QT];
+#pragma unroll
+          for (int u = 0; u < QT; ++u) acc[u] = 0.0;
+          if (v4) {
+            for (int k = 0; k < d; k += 4) {
+              const float4 c4 = *(const float4*)(cr + k);
+#pragma unroll
+              for (int u = 0; u < QT; ++u) {
+                if (u < total) {
+                  const float4 x4 = *(const float4*)(qx + u * DP + k);
+                  double df = (double)x4.x - (double)c4.x; acc[u] = fma(df, df, acc[u]);
+                  df = (double)x4.y - (double)c4.y; acc[u] = fma(df, df, acc[u]);
+                  df = (double)x4.z - (double)c4.z; acc[u] = fma(df, df, acc[u]);
+                  df = (double)x4.w - (double)c4.w; acc[u] = fma(df, df, acc[u]);
+                }
+              }
+            }
+          } else {
+            for (int k = 0; k < d; ++k) {
+              const double c = (double)cr[k];
+#pragma unroll
+              for (int u = 0; u < QT; ++u) {
+                if (u < total) {
+                  const double df = (double)qx[u * DP + k] - c;
+                  acc[u] = fma(df, df, acc[u]);
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < QT; ++u)
+            if (acc[u] < bd[u]) { bd[u] = acc[u]; bj[u] = j; }
+        }
+#pragma unroll
+        for (int u = 0; u < QT; ++u) {
+          if (u < total) {
+            double dist;
+            const int j = wave_argmin(bd[u], bj[u], &dist);
+            if (lane == 0) { qd[u * 16 + wave] = dist; qj[u * 16 + wave] = j; }
+          }
+        }
+        __syncthreads();
+        if (tid < total) {
+          double bdist = qd[tid * 16];
+          int bjj = qj[tid * 16];
+          for (int w = 1; w < W; ++w) {
+            const double od = qd[tid * 16 + w];
+            const int oj = qj[tid * 16 + w];
+            const bool take = (od < bdist) || (od == bdist && (unsigned)oj < (unsigned)bjj);
+            bdist = take ? od : bdist;
+            bjj = take ? oj : bjj;
+          }
+          qd[tid * 16] = bdist;
+          qj[tid * 16] = bjj;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+          if (u_s[s] >= 0) {
+            const int j = qj[u_s[s] * 16];
+            if (j >= 0) { bi_s[s] = j; term_s[s] = qd[u_s[s] * 16]; }
+          }
+        }
+      }
+    }
+
+    double e_lane = 0.0;
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int64_t i = row0 + 16 * s + r16;
+      const bool valid = i < a.N;
+      bool ch = false;
+      if (valid && g == 0) {
+        rho[i] = bi_s[s];
+        ch = (prev != nullptr) && (prev[i] != bi_s[s]);
+      }
+      n_changed += (unsigned)__popcll(__ballot(ch));
+      e_lane += (valid && g == 0) ? term_s[s] : 0.0;
+    }
+    e_wave += wave_sum(e_lane);
+  }
+
+  if (lane == 0) {
+    dred[wave] = e_wave;
+    if (n_changed) atomicAdd(&ctl->cnt_changed[slot], (unsigned long long)n_changed);
+    if (n_flag) atomicAdd(&ctl->cnt_flagged[slot], (unsigned long long)n_flag);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double e = dred[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) e += dred[w];
+    a.e_part[bx] = e;
+  }
+}
+
+// Waves per SIMD the register allocation must leave room for: 16-wave
+// workgroups need 4; small float32 tiles run best at 4 (latency hiding);
+// wide tiles (float32 rows on the bf16 GEMM, 8 sample blocks, d > 128 in
+// bf16, more than 64 dims x blocks in float32) get the whole register file;
+// the rest run 2 waves per SIMD.
+template <int KS, int SB, int W, bool XBF, bool GBF>
+constexpr int assign_wpe() {
+  if (W >= 16) return 4;
+  if (!GBF) return (KS * SB <= 16 && SB <= 2) ? 4 : (KS * SB > 64 ? 1 : 2);
+  if (!XBF || KS >= 48 || SB >= 8) return 1;
+  return 2;
+}
+
+template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(assign_wpe<KS, SB, W, XBF, GBF>())))
+void k_assign(AssignArgs a) {
+  assign_body<KS, SB, W, XBF, GBF, LB>(a, blockIdx.x, gridDim.x);
+}
+
+// Batched launch: the grid is the concatenation of every instance's slice.
+template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(assign_wpe<KS, SB, W, XBF, GBF>())))
+void k_assign_batch(BatchRef<AssignArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  const int b0 = t.prefix[b];
+  assign_body<KS, SB, W, XBF, GBF, LB>(t.tab[b], blockIdx.x - b0, t.prefix[b + 1] - b0);
+}
+
+// Host view of one kernel instantiation.
+struct KernelPick {
+  const void* fn = nullptr;        // k_assign
+  const void* fn_batch = nullptr;  // k_assign_batch
+  int rows = 0;                    // samples per row group (16 * SB * W)
+  int threads = 0;                 // 64 * W
+  int lb = 0;                      // LDS budget (bytes)
+  size_t lds = 0;                  // LDS bytes for the K of the call
+};
+
+template <int KS, bool XBF, bool GBF, int SB, int W, int LB>
+KernelPick make_pick(int K) {
+  KernelPick p;
+  p.fn = (const void*)&k_assign<KS, SB, W, XBF, GBF, LB>;
+  p.fn_batch = (const void*)&k_assign_batch<KS, SB, W, XBF, GBF, LB>;
+  p.rows = 16 * SB * W;
+  p.threads = 64 * W;
+  p.lb = LB;
+  p.lds = Tile<KS, GBF, LB>::lds_bytes(K);
+  return p;
+}
+
+// Padded dimensions per lane group for d (-1 beyond the supported range).
+inline int pick_ks(int d, int gemm_bf16) {
+  static const int f32_ks[] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 64};
+  static const int bf_ks[] = {8, 16, 24, 32, 48, 64};
+  const int need = (d + 3) / 4;
+  if (gemm_bf16) {
+    for (int k : bf_ks) if (k >= need) return k;
+  } else {
+    for (int k : f32_ks) if (k >= need) return k;
+  }
+  return -1;
+}
+
+// Kernel of the given tile shape (0 = default; see the per-family tables).
+KernelPick pick_f32(int ks, bool xbf, int K, int shape);
+KernelPick pick_bf16(int ks, bool xbf, int K, int shape);
+
+}  // namespace km

@@ -91,6 +91,25 @@ __device__ __forceinline__ double bf16_split(float f, uint16_t* hi, uint16_t* lo
   return (double)r1 - (double)__uint_as_float(((uint32_t)l) << 16);
 }
 
+// Batched launches: the grid is the concatenation of per-instance slices;
+// workgroup bx belongs to instance b with prefix[b] <= bx < prefix[b + 1]
+// (prefix has n + 1 entries; empty slices are skipped by the search).
+template <class A>
+struct BatchRef {
+  const A* tab;
+  const int* prefix;
+  int n;
+};
+
+__device__ __forceinline__ int batch_find(const int* prefix, int n, int bx) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= bx) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 inline void clear_pending_error() { (void)hipGetLastError(); }
 
 __device__ __forceinline__ unsigned popc64(unsigned long long m) { return __popcll(m); }

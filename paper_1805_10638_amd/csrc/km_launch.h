@@ -24,9 +24,15 @@ struct AssignArgs {
   Ctl* ctl;
   int xbf16;              // X stored as bfloat16
   int gemm_bf16;          // distance GEMM in bfloat16
+  int role;               // Role of the launch (set by launch_assign / the batch tables)
+  int shape;              // tile shape id (0 = default)
 };
 int assign_grid(const AssignArgs& a);   // workgroups of one launch (persistent grid)
 hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s);
+struct KernelPick;
+KernelPick assign_pick(const AssignArgs& a);
+// resident workgroups of kernel p on the device x frac, capped at N's row groups
+int64_t assign_resident(const KernelPick& p, int64_t N, double frac);
 
 // ||c_j||^2 (and the bfloat16 hi/lo pair with its residual norms when Cb != null).
 hipError_t launch_prep(const float* C, int K, int d, float* nc, uint16_t* Cb, float* delta,

@@ -206,3 +206,21 @@ def test_solve_bf16_gemm_matches_f32():
     assert a[3] == b[3]
     assert b[2] == pytest.approx(a[2], rel=1e-9)
     assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_g_many_flags_streamed_centroids(prec):
+    """Large common offset with K too large for LDS residency: most rows are
+    flagged, so the workgroup re-check queue fills and overflows into the
+    per-wave path; every label must still be the exact argmin."""
+    km = _lib()
+    rng = np.random.default_rng(11)
+    # bf16 keeps the offset small enough that the noise is not rounded away
+    X = ((300.0 if prec == "f32" else 40.0) + rng.normal(size=(3000, 64))).astype(np.float32)
+    if prec == "bf16":
+        X = synth.to_bf16_bits(X)
+    C = synth.init_centroids(X, 300, seed=3)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C), prec=prec)
+    r = check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
+    assert st.flagged_rows > 1000
+    assert r["mismatch"] <= r["near_ties"]
