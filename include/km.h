@@ -169,6 +169,74 @@ km_status kmeans_solve(km_ctx *ctx, const void *X, km_xtype xt, int64_t N, int32
                        float *C_out, int32_t *rho_out, double *E, int32_t *iters,
                        km_solve_stats *st);
 
+/* ---------------------------------------------------------------------
+ * Many instances at once (batched and served solving).
+ *
+ * A job is one kmeans_solve problem with its own X, sizes, C0 and outputs.
+ * An engine advances all its active jobs together, one iteration of
+ * Algorithm 1 each per step: every step of the method (assignment per tile
+ * shape, controller, update, finalisation, Anderson combination) is one
+ * batched launch over the active jobs, and while the set of jobs does not
+ * change the launches of an iteration are replayed from a HIP graph.
+ * A job gets the labels, iteration count and decisions of kmeans_solve on
+ * it alone; E and C may differ in the last bits where a different split of
+ * the per-workgroup energy partials rounds differently.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  const void *X;         /* N x d, device */
+  km_xtype xt;
+  int64_t N;
+  int32_t d, K;
+  const float *C0;       /* K x d float32, device */
+  float *C_out;          /* K x d float32, device, written when the job finishes */
+  int32_t *rho_out;      /* N int32, device, written when the job finishes */
+} km_job;
+
+typedef struct {
+  int64_t ticket;        /* from km_engine_submit; the job index for kmeans_solve_batch */
+  int32_t status;        /* KM_OK, KM_NOT_CONVERGED or KM_ENONFINITE */
+  int32_t iters;
+  double E;
+  int32_t accepted, rejected, assign_passes, m_final;
+  int64_t flagged_rows;
+  double latency_ms;     /* host time from submission to the result being ready */
+} km_job_result;
+
+typedef struct km_engine km_engine;
+
+/* Engine on ctx's device (its own internal stream, ordered after ctx's
+ * stream at creation).  Jobs share m_max, tol and opt (opt may be NULL; its
+ * trace pointers must be NULL).  hbm_budget bounds the bytes of job
+ * workspaces on the device at once (0: no bound); queued jobs are admitted
+ * in submission order when they fit.  graphs = 1 replays iterations from a
+ * HIP graph while the job set is unchanged. */
+km_status km_engine_create(km_ctx *ctx, int32_t m_max, double tol, const km_opts *opt,
+                           int64_t hbm_budget, int32_t graphs, km_engine **out);
+/* Waits for the device and releases everything; unfinished jobs are dropped. */
+void km_engine_destroy(km_engine *e);
+
+/* Device workspace bytes of a job (what the budget counts), or -1. */
+int64_t km_job_workspace_bytes(const km_job *job, int32_t m_max, km_prec prec);
+
+/* Queue a job (checked like kmeans_solve); *ticket names its result.  Its
+ * buffers must stay valid until km_engine_poll has returned the result.
+ * KM_ENOMEM if its workspace alone exceeds the budget. */
+km_status km_engine_submit(km_engine *e, const km_job *job, int64_t *ticket);
+
+/* Admit queued jobs that fit (at iteration boundaries), launch one
+ * iteration of every active job, collect finished ones.  Any count pointer
+ * may be NULL: jobs on the device, waiting for admission, results ready. */
+km_status km_engine_step(km_engine *e, int32_t *n_active, int32_t *n_queued, int32_t *n_ready);
+
+/* 1 and *res filled if a finished job's result was taken (oldest first), 0 if none. */
+int32_t km_engine_poll(km_engine *e, km_job_result *res);
+
+/* Solve n jobs as one batch (an engine without budget, graphs on) and wait;
+ * res[i] is job i's result.  KM_OK when every job ran (each job's status is
+ * in res[i]). */
+km_status kmeans_solve_batch(km_ctx *ctx, const km_job *jobs, int32_t n, int32_t m_max, double tol,
+                             const km_opts *opt, km_job_result *res);
+
 #ifdef __cplusplus
 }
 #endif

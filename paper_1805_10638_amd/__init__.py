@@ -8,10 +8,10 @@ if the library has not been built.
 
 import importlib
 
-__all__ = ["kmeans_g", "kmeans_solve", "Context", "KMError", "synth"]
+__all__ = ["kmeans_g", "kmeans_solve", "kmeans_solve_batch", "Engine", "Context", "KMError", "synth"]
 
-_LIB_NAMES = ("kmeans_g", "kmeans_solve", "Context", "KMError", "SolveStats", "GStats",
-              "load_library")
+_LIB_NAMES = ("kmeans_g", "kmeans_solve", "kmeans_solve_batch", "Engine", "Context", "KMError",
+              "SolveStats", "GStats", "JobResult", "load_library")
 
 
 def __getattr__(name):

@@ -50,6 +50,37 @@ class _SolveStats(ct.Structure):
                 ("device_ms", ct.c_double), ("assign_ms", ct.c_double)]
 
 
+class _Job(ct.Structure):
+    _fields_ = [("X", ct.c_void_p), ("xt", ct.c_int), ("N", ct.c_int64), ("d", ct.c_int32),
+                ("K", ct.c_int32), ("C0", ct.c_void_p), ("C_out", ct.c_void_p), ("rho_out", ct.c_void_p)]
+
+
+class _JobResult(ct.Structure):
+    _fields_ = [("ticket", ct.c_int64), ("status", ct.c_int32), ("iters", ct.c_int32),
+                ("E", ct.c_double), ("accepted", ct.c_int32), ("rejected", ct.c_int32),
+                ("assign_passes", ct.c_int32), ("m_final", ct.c_int32),
+                ("flagged_rows", ct.c_int64), ("latency_ms", ct.c_double)]
+
+
+@dataclass
+class JobResult:
+    ticket: int
+    status: int
+    iters: int
+    E: float
+    accepted: int
+    rejected: int
+    assign_passes: int
+    m_final: int
+    flagged_rows: int
+    latency_ms: float
+
+
+def _job_result(r: _JobResult) -> JobResult:
+    return JobResult(r.ticket, r.status, r.iters, r.E, r.accepted, r.rejected, r.assign_passes,
+                     r.m_final, r.flagged_rows, r.latency_ms)
+
+
 @dataclass
 class GStats:
     changed: int
@@ -97,6 +128,21 @@ def load_library(path: str | None = None):
     lib.km_set_tile_shape.restype = ct.c_int
     lib.km_get_tile_shape.argtypes = [vp, ct.c_int, ct.c_int, i32, i32]
     lib.km_get_tile_shape.restype = ct.c_int
+    lib.km_job_workspace_bytes.argtypes = [ct.POINTER(_Job), i32, ct.c_int]
+    lib.km_job_workspace_bytes.restype = i64
+    lib.km_engine_create.argtypes = [vp, i32, dbl, ct.POINTER(_Opts), i64, i32, ct.POINTER(vp)]
+    lib.km_engine_create.restype = ct.c_int
+    lib.km_engine_destroy.argtypes = [vp]
+    lib.km_engine_destroy.restype = None
+    lib.km_engine_submit.argtypes = [vp, ct.POINTER(_Job), ct.POINTER(ct.c_int64)]
+    lib.km_engine_submit.restype = ct.c_int
+    lib.km_engine_step.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
+    lib.km_engine_step.restype = ct.c_int
+    lib.km_engine_poll.argtypes = [vp, ct.POINTER(_JobResult)]
+    lib.km_engine_poll.restype = i32
+    lib.kmeans_solve_batch.argtypes = [vp, ct.POINTER(_Job), i32, i32, dbl, ct.POINTER(_Opts),
+                                       ct.POINTER(_JobResult)]
+    lib.kmeans_solve_batch.restype = ct.c_int
     lib.km_status_str.argtypes = [ct.c_int]
     lib.km_status_str.restype = ct.c_char_p
     lib.km_last_error.argtypes = [vp]
@@ -286,3 +332,127 @@ def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float 
     if trace:
         return C, rho, E.value, it.value, stats, tr
     return C, rho, E.value, it.value, stats
+
+
+# ---------------------------------------------------------------------------
+# Many instances at once
+# ---------------------------------------------------------------------------
+
+def _solver_opts(lib, m_init, max_iter, prec, eps1, eps2, ridge, fixed_m, literal_return):
+    o = _Opts()
+    lib.km_opts_default(ct.byref(o))
+    o.eps1, o.eps2, o.ridge = eps1, eps2, ridge
+    o.m_init, o.max_iter, o.prec = m_init, max_iter, _prec(prec)
+    o.flags = (KM_FLAG_FIXED_M if fixed_m else 0) | (KM_FLAG_LITERAL_RETURN if literal_return else 0)
+    return o
+
+
+def _make_job(X: torch.Tensor, C0: torch.Tensor, out, dev: int):
+    _check_dev(X, "X", dev)
+    _check_dev(C0, "C0", dev)
+    if C0.dtype != torch.float32:
+        raise TypeError("C0 must be float32")
+    N, d = X.shape
+    K = C0.shape[0]
+    if C0.shape[1] != d:
+        raise ValueError("C0 must be K x d")
+    if out is None:
+        C = torch.empty_like(C0)
+        rho = torch.empty(N, dtype=torch.int32, device=X.device)
+    else:
+        C, rho = out
+    j = _Job(X.data_ptr(), _xtype(X), N, d, K, C0.data_ptr(), C.data_ptr(), rho.data_ptr())
+    return j, (X, C0, C, rho)
+
+
+def kmeans_solve_batch(problems, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
+                       m_init: int = 2, prec="f32", eps1: float = 0.02, eps2: float = 0.5,
+                       ridge: float = 1e-10, fixed_m: bool = False, literal_return: bool = False,
+                       ctx: "Context | None" = None):
+    """Solve many instances together (kmeans_solve_batch in km.h).
+
+    ``problems`` is a list of (X, C0) pairs on one device.  Returns a list of
+    (C, rho, JobResult) in the same order."""
+    if not problems:
+        return []
+    dev = problems[0][0].device.index
+    ctx = ctx or _context(dev)
+    jobs = (_Job * len(problems))()
+    keep = []
+    for i, (X, C0) in enumerate(problems):
+        jobs[i], k = _make_job(X, C0, None, dev)
+        keep.append(k)
+    res = (_JobResult * len(problems))()
+    o = _solver_opts(ctx.lib, m_init, max_iter, prec, eps1, eps2, ridge, fixed_m, literal_return)
+    ctx._bind_stream()
+    st = ctx.lib.kmeans_solve_batch(ctx.h, jobs, len(problems), m_max, tol, ct.byref(o), res)
+    ctx._check(st, "kmeans_solve_batch")
+    return [(k[2], k[3], _job_result(res[i])) for i, k in enumerate(keep)]
+
+
+class Engine:
+    """Continuous batching of clustering jobs (km_engine_* in km.h).
+
+    ``submit`` queues a job (its tensors are kept alive until its result is
+    taken); ``step`` admits what fits the HBM budget and advances every
+    active job by one iteration; ``poll`` returns finished jobs as
+    (ticket, C, rho, JobResult)."""
+
+    def __init__(self, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500, m_init: int = 2,
+                 prec="f32", eps1: float = 0.02, eps2: float = 0.5, ridge: float = 1e-10,
+                 hbm_budget: int = 0, graphs: bool = False, ctx: "Context | None" = None,
+                 device: int | None = None):
+        dev = torch.cuda.current_device() if device is None else device
+        self.ctx = ctx or _context(dev)
+        self.lib = self.ctx.lib
+        self.device = dev
+        o = _solver_opts(self.lib, m_init, max_iter, prec, eps1, eps2, ridge, False, False)
+        self.prec = prec
+        self.m_max = m_max
+        h = ct.c_void_p()
+        self.ctx._bind_stream()
+        st = self.lib.km_engine_create(self.ctx.h, m_max, tol, ct.byref(o), hbm_budget,
+                                       1 if graphs else 0, ct.byref(h))
+        self.ctx._check(st, "km_engine_create")
+        self.h = h
+        self._jobs = {}
+
+    def workspace_bytes(self, X: torch.Tensor, K: int) -> int:
+        N, d = X.shape
+        j = _Job(0, _xtype(X), N, d, K, 0, 0, 0)
+        return int(self.lib.km_job_workspace_bytes(ct.byref(j), self.m_max, _prec(self.prec)))
+
+    def submit(self, X: torch.Tensor, C0: torch.Tensor, out=None) -> int:
+        j, keep = _make_job(X, C0, out, self.device)
+        t = ct.c_int64()
+        self.ctx._bind_stream()
+        st = self.lib.km_engine_submit(self.h, ct.byref(j), ct.byref(t))
+        self.ctx._check(st, "km_engine_submit")
+        self._jobs[t.value] = keep
+        return t.value
+
+    def step(self):
+        a, q, r = ct.c_int32(), ct.c_int32(), ct.c_int32()
+        st = self.lib.km_engine_step(self.h, ct.byref(a), ct.byref(q), ct.byref(r))
+        self.ctx._check(st, "km_engine_step")
+        return a.value, q.value, r.value
+
+    def poll(self):
+        out = []
+        r = _JobResult()
+        while self.lib.km_engine_poll(self.h, ct.byref(r)):
+            keep = self._jobs.pop(r.ticket)
+            out.append((r.ticket, keep[2], keep[3], _job_result(r)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.km_engine_destroy(self.h)
+            self.h = None
+            self._jobs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

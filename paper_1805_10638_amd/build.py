@@ -23,7 +23,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libkmaa.so")
 
 SOURCES = ["km_assign_f32.hip", "km_assign_bf16.hip", "km_assign.hip", "km_update.hip", "km_anderson.hip",
-           "km_api.hip"]
+           "km_api.hip", "km_engine.hip"]
 
 ARCH = "gfx950"
 # Packed-FP32 instructions are disabled for all device code.

@@ -175,7 +175,7 @@ __device__ __forceinline__ float put_centroid(float* C, uint16_t* Cb, int64_t KD
   return f;
 }
 
-__global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
+__device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
   Ctl* c = a.ctl;
   __shared__ double th[kMaxM], newrow[kMaxM], bvec[kMaxM], sc[kMaxM];
   __shared__ double Lm[kMaxM * kMaxM];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
       int m = c->m < t ? c->m : t;
       if (m > len_new) m = len_new;
       const int used = ls_solve_group(a, s_new, len_new, m, c->ridge, th, newrow, bvec, Lm, sc, cols, misc);
-      if (blockIdx.x == 0) {
+      if (bx == 0) {
         for (int q = threadIdx.x; q < len_new; q += blockDim.x) {
           const int sl = (s_new - q + cap) % cap;
           a.gram[s_new * cap + sl] = newrow[q];
@@ -212,14 +212,14 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
       }
       mt = used > 0 ? m : 0;
       head = s_new;
-    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    } else if (bx == 0 && threadIdx.x == 0) {
       c->mt = 0;
       c->used = 0;
       c->cand_is_lloyd = 1;
     }
   }
   const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int j = bx * 4 + (threadIdx.x >> 6);
   if (j >= a.K) return;
   const int d = a.d;
   const int64_t KD = (int64_t)a.K * d;
@@ -245,6 +245,22 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
     if (a.Cb_cand) a.delta_cand[j] = (float)sqrt(e_c);
     if (a.Cb_fb) a.delta_fb[j] = (float)sqrt(e_f);
   }
+}
+
+__global__ __launch_bounds__(256) void k_combine(CombineArgs a) { combine_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_combine_batch(BatchRef<CombineArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  combine_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
+
+int combine_grid(int K) { return (K + 3) / 4; }
+
+hipError_t launch_combine_batch(const CombineArgs* tab, const int* prefix, int n, int blocks, hipStream_t s) {
+  clear_pending_error();
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine_batch, dim3(blocks), dim3(256), 0, s, BatchRef<CombineArgs>{tab, prefix, n});
+  return hipGetLastError();
 }
 
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s) {

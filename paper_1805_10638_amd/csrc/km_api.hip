@@ -8,123 +8,8 @@
 #include <string>
 #include <vector>
 
-#include "../../include/km.h"
-#include "km_assign_kernel.h"
+#include "km_ctx.h"
 
-using namespace km;
-
-namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
-
-// Sizes that determine the workspace layout.
-struct Shape {
-  int64_t N = 0;
-  int d = 0, K = 0, cap = 0, bf = 0;
-  bool fits(const Shape& o) const {
-    return N >= o.N && d >= o.d && K >= o.K && cap >= o.cap && bf >= o.bf &&
-           (int64_t)K * d >= (int64_t)o.K * o.d;
-  }
-};
-
-}  // namespace
-
-struct km_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  bool timing = false;
-
-  void* arena = nullptr;
-  size_t arena_bytes = 0;
-  Shape shape;
-
-  Ctl* ctl = nullptr;           // device
-  Ctl* ctl_host = nullptr;      // pinned host mirror
-  int* done_host = nullptr;     // pinned poll slots
-  double* scal_host = nullptr;  // pinned scalars
-  hipStream_t q = nullptr;      // internal stream (graph capture needs a non-null stream)
-  hipEvent_t enter = nullptr;   // orders q after the caller's stream
-  hipEvent_t poll_ev[2] = {nullptr, nullptr};
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  hipEvent_t ta[2] = {nullptr, nullptr}, tb[2] = {nullptr, nullptr};  // around assignment
-
-  // assignment tile shape per (precision, X type, padded width, K bucket)
-  int8_t tile_shape[2][2][10][9] = {};
-
-  // per-iteration graphs (two, so that one can be inspected while the other runs)
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  std::string gkey;
-
-  // workspace carve-up
-  int* labels = nullptr;        // 3 x N
-  int* lrank = nullptr;         // N
-  int* perm = nullptr;          // N
-  int* blockcount = nullptr;    // nblk x K
-  int* counts = nullptr;        // K
-  int* seg_start = nullptr;     // K + 1
-  int* item_start = nullptr;    // K + 1
-  int* item_cluster = nullptr;  // max_items
-  double* e_part = nullptr;     // 2 x grid
-  double* partial = nullptr;    // max_items x d
-  double* G_last = nullptr;     // K x d
-  double* F_last = nullptr;     // K x d
-  double* ring_dF = nullptr;    // cap x K x d
-  double* ring_dG = nullptr;    // cap x K x d
-  double* gram = nullptr;       // cap x cap
-  double* dots = nullptr;       // fin_grid x 2 cap
-  double* e_out = nullptr;      // 1
-  float* C_cand = nullptr;      // K x d
-  float* C_fb = nullptr;        // K x d
-  float* C_tmp = nullptr;       // K x d (kmeans_g / prologue input copy)
-  float* nc_cand = nullptr;
-  float* nc_fb = nullptr;
-  float* nc_tmp = nullptr;
-  uint16_t* Cb_cand = nullptr;  // bf16 hi/lo pairs, 2 x K x d (bf16 GEMM only)
-  uint16_t* Cb_fb = nullptr;
-  uint16_t* Cb_tmp = nullptr;
-  float* del_cand = nullptr;
-  float* del_fb = nullptr;
-  float* del_tmp = nullptr;
-  int grid_assign = 0, max_items = 0, nblk = 0, fin_grid = 0;
-};
-
-static km_status fail(km_ctx* c, km_status s, const std::string& msg) {
-  if (c) c->err = msg;
-  return s;
-}
-
-static km_status hip_fail(km_ctx* c, hipError_t e, const char* where) {
-  std::string m = std::string(where) + ": " + hipGetErrorString(e);
-  return fail(c, e == hipErrorOutOfMemory ? KM_ENOMEM : KM_EDEVICE, m);
-}
-
-#define HIP_TRY(c, expr, where)                       \
-  do {                                                \
-    hipError_t _e = (expr);                           \
-    if (_e != hipSuccess) return hip_fail(c, _e, where); \
-  } while (0)
-
-// The kernels read rows and centroids with 16-byte vector loads.
-static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
-
-static bool is_device_ptr(const void* p) {
-  if (!p) return false;
-  hipPointerAttribute_t at;
-  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
-}
-
-static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-  const char* pa = (const char*)a;
-  const char* pb = (const char*)b;
-  return pa < pb + nb && pb < pa + na;
-}
 
 static km_status ensure_ws(km_ctx* c, const Shape& want) {
   if (c->arena && c->shape.fits(want)) return KM_OK;
@@ -144,44 +29,7 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
     }
     c->gkey.clear();
   }
-  const int64_t N = s.N;
-  const int64_t KD = (int64_t)s.K * s.d;
-  const int64_t grid = N / 64 + 1;   // upper bound of the assignment grid
-  const int max_items = update_max_items(N, s.K);
-  const int nblk = update_rank_blocks(N);
-  const int fin_grid = finalize_grid((int64_t)s.K * s.d);
-  size_t off = 0;
-  auto take = [&](size_t bytes) { size_t o = off; off += up(bytes); return o; };
-  const size_t o_ctl = take(sizeof(Ctl));
-  const size_t o_lab = take(3 * N * 4);
-  const size_t o_lr = take(N * 4);
-  const size_t o_perm = take(N * 4);
-  const size_t o_bc = take((size_t)nblk * s.K * 4);
-  const size_t o_cnt = take((size_t)s.K * 4);
-  const size_t o_ss = take((size_t)(s.K + 1) * 4);
-  const size_t o_is = take((size_t)(s.K + 1) * 4);
-  const size_t o_ic = take((size_t)max_items * 4);
-  const size_t o_ep = take((size_t)2 * grid * 8);
-  const size_t o_pa = take((size_t)max_items * s.d * 8);
-  const size_t o_gl = take(KD * 8);
-  const size_t o_fl = take(KD * 8);
-  const size_t o_rf = take((size_t)s.cap * KD * 8);
-  const size_t o_rg = take((size_t)s.cap * KD * 8);
-  const size_t o_gr = take((size_t)s.cap * s.cap * 8 + 8);
-  const size_t o_dt = take((size_t)fin_grid * 2 * s.cap * 8 + 8);
-  const size_t o_eo = take(8);
-  const size_t o_cc = take(KD * 4);
-  const size_t o_cf = take(KD * 4);
-  const size_t o_ct = take(KD * 4);
-  const size_t o_nc = take((size_t)s.K * 4);
-  const size_t o_nf = take((size_t)s.K * 4);
-  const size_t o_nt = take((size_t)s.K * 4);
-  const size_t o_bcand = take(s.bf ? KD * 4 : 0);
-  const size_t o_bfb = take(s.bf ? KD * 4 : 0);
-  const size_t o_btmp = take(s.bf ? KD * 4 : 0);
-  const size_t o_dc = take(s.bf ? s.K * 4 : 0);
-  const size_t o_df = take(s.bf ? s.K * 4 : 0);
-  const size_t o_dtmp = take(s.bf ? s.K * 4 : 0);
+  const size_t off = ws_layout(s, nullptr, nullptr);
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, off);
   if (e != hipSuccess) {
@@ -191,80 +39,10 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
     return fail(c, KM_ENOMEM, "workspace allocation of " + std::to_string(off) + " bytes failed");
   }
   HIP_TRY(c, hipMemsetAsync(p, 0, off, c->q), "hipMemsetAsync");
-  char* b = (char*)p;
   c->arena = p;
   c->arena_bytes = off;
   c->shape = s;
-  c->ctl = (Ctl*)(b + o_ctl);
-  c->labels = (int*)(b + o_lab);
-  c->lrank = (int*)(b + o_lr);
-  c->perm = (int*)(b + o_perm);
-  c->blockcount = (int*)(b + o_bc);
-  c->counts = (int*)(b + o_cnt);
-  c->seg_start = (int*)(b + o_ss);
-  c->item_start = (int*)(b + o_is);
-  c->item_cluster = (int*)(b + o_ic);
-  c->e_part = (double*)(b + o_ep);
-  c->partial = (double*)(b + o_pa);
-  c->G_last = (double*)(b + o_gl);
-  c->F_last = (double*)(b + o_fl);
-  c->ring_dF = (double*)(b + o_rf);
-  c->ring_dG = (double*)(b + o_rg);
-  c->gram = (double*)(b + o_gr);
-  c->dots = (double*)(b + o_dt);
-  c->e_out = (double*)(b + o_eo);
-  c->C_cand = (float*)(b + o_cc);
-  c->C_fb = (float*)(b + o_cf);
-  c->C_tmp = (float*)(b + o_ct);
-  c->nc_cand = (float*)(b + o_nc);
-  c->nc_fb = (float*)(b + o_nf);
-  c->nc_tmp = (float*)(b + o_nt);
-  c->Cb_cand = s.bf ? (uint16_t*)(b + o_bcand) : nullptr;
-  c->Cb_fb = s.bf ? (uint16_t*)(b + o_bfb) : nullptr;
-  c->Cb_tmp = s.bf ? (uint16_t*)(b + o_btmp) : nullptr;
-  c->del_cand = s.bf ? (float*)(b + o_dc) : nullptr;
-  c->del_fb = s.bf ? (float*)(b + o_df) : nullptr;
-  c->del_tmp = s.bf ? (float*)(b + o_dtmp) : nullptr;
-  c->grid_assign = grid;
-  c->max_items = max_items;
-  c->nblk = nblk;
-  c->fin_grid = fin_grid;
-  return KM_OK;
-}
-
-// Tile-shape table index of (d, K): padded width class and K bucket.
-static bool tile_slot(int gemm_bf16, int32_t d, int32_t K, int* wi, int* kb) {
-  static const int widths[] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 64};
-  if (d < 1 || d > kMaxD || K < 1 || K > kMaxK) return false;
-  const int ks = pick_ks(d, gemm_bf16);
-  *wi = -1;
-  for (int i = 0; i < 10; ++i)
-    if (widths[i] == ks) *wi = i;
-  int b = 0;
-  while ((16 << b) < K) ++b;
-  *kb = b;
-  return *wi >= 0 && b < 9;
-}
-
-static int shape_for(const km_ctx* c, int gemm_bf16, int xbf, int32_t d, int32_t K) {
-  int wi, kb;
-  if (!tile_slot(gemm_bf16, d, K, &wi, &kb)) return 0;
-  return c->tile_shape[gemm_bf16 ? 1 : 0][xbf ? 1 : 0][wi][kb];
-}
-
-static km_status check_common(km_ctx* c, const void* X, int xt, int64_t N, int32_t d, int32_t K,
-                              int prec) {
-  if (!c) return KM_EINVAL;
-  c->err.clear();
-  if (N < 1 || d < 1 || K < 1) return fail(c, KM_EINVAL, "N, d and K must be positive");
-  if (K > N) return fail(c, KM_EINVAL, "K must not exceed N");
-  if (xt != KM_X_F32 && xt != KM_X_BF16) return fail(c, KM_EINVAL, "unknown X type");
-  if (prec != KM_GEMM_F32 && prec != KM_GEMM_BF16) return fail(c, KM_EINVAL, "unknown precision");
-  if (d > kMaxD) return fail(c, KM_EUNSUPPORTED, "d > 256 is not supported");
-  if (K > kMaxK) return fail(c, KM_EUNSUPPORTED, "K > 4096 is not supported");
-  if (N >= ((int64_t)1 << 31)) return fail(c, KM_EUNSUPPORTED, "N >= 2^31 is not supported");
-  if (!is_device_ptr(X)) return fail(c, KM_EINVAL, "X is not a device pointer");
-  if (!aligned16(X)) return fail(c, KM_EINVAL, "X must start on a 16-byte boundary");
+  ws_layout(s, (char*)p, &c->w);
   return KM_OK;
 }
 
@@ -404,33 +182,33 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   HIP_TRY(c, hipEventRecord(c->enter, c->stream), "hipEventRecord");
   HIP_TRY(c, hipStreamWaitEvent(st_, c->enter, 0), "hipStreamWaitEvent");
 
-  HIP_TRY(c, hipMemsetAsync(c->ctl, 0, sizeof(Ctl), st_), "hipMemsetAsync");
-  HIP_TRY(c, launch_prep(C, K, d, c->nc_tmp, gbf ? c->Cb_tmp : nullptr, gbf ? c->del_tmp : nullptr, st_),
+  HIP_TRY(c, hipMemsetAsync(c->w.ctl, 0, sizeof(Ctl), st_), "hipMemsetAsync");
+  HIP_TRY(c, launch_prep(C, K, d, c->w.nc_tmp, gbf ? c->w.Cb_tmp : nullptr, gbf ? c->w.del_tmp : nullptr, st_),
           "prep");
   AssignArgs a{};
-  a.X = X; a.N = N; a.d = d; a.K = K; a.C = C; a.nc = c->nc_tmp;
-  a.Cb = gbf ? c->Cb_tmp : nullptr; a.delta = gbf ? c->del_tmp : nullptr;
-  a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->e_part; a.ctl = c->ctl;
+  a.X = X; a.N = N; a.d = d; a.K = K; a.C = C; a.nc = c->w.nc_tmp;
+  a.Cb = gbf ? c->w.Cb_tmp : nullptr; a.delta = gbf ? c->w.del_tmp : nullptr;
+  a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->w.e_part; a.ctl = c->w.ctl;
   a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
   HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
   const int grid = assign_grid(a);
-  HIP_TRY(c, launch_reduce_energy(c->e_part, grid, c->e_out, st_), "energy");
+  HIP_TRY(c, launch_reduce_energy(c->w.e_part, grid, c->w.e_out, st_), "energy");
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
-  u.lab = rho; u.lab_from_ctl = 0; u.lrank = c->lrank; u.blockcount = c->blockcount;
-  u.counts = c->counts; u.seg_start = c->seg_start; u.item_start = c->item_start;
-  u.item_cluster = c->item_cluster; u.perm = c->perm; u.partial = c->partial;
-  u.max_items = update_max_items(N, K); u.ctl = c->ctl; u.gated = 0;
+  u.lab = rho; u.lab_from_ctl = 0; u.lrank = c->w.lrank; u.blockcount = c->w.blockcount;
+  u.counts = c->w.counts; u.seg_start = c->w.seg_start; u.item_start = c->w.item_start;
+  u.item_cluster = c->w.item_cluster; u.perm = c->w.perm; u.partial = c->w.partial;
+  u.max_items = update_max_items(N, K); u.ctl = c->w.ctl; u.gated = 0;
   HIP_TRY(c, launch_update_sums(u, st_), "update");
   FinalizeArgs f{};
-  f.d = d; f.K = K; f.cap = 0; f.partial = c->partial; f.item_start = c->item_start;
-  f.counts = c->counts; f.C_in = C; f.C_out = C_out; f.ctl = c->ctl; f.mode = kFinG;
+  f.d = d; f.K = K; f.cap = 0; f.partial = c->w.partial; f.item_start = c->w.item_start;
+  f.counts = c->w.counts; f.C_in = C; f.C_out = C_out; f.ctl = c->w.ctl; f.mode = kFinG;
   f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
   f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
   HIP_TRY(c, launch_finalize(f, st_), "finalize");
-  HIP_TRY(c, hipMemcpyAsync(c->scal_host, c->e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
-  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
+  HIP_TRY(c, hipMemcpyAsync(c->scal_host, c->w.e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
+  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
   HIP_TRY(c, hipStreamSynchronize(st_), "hipStreamSynchronize");
   *E = c->scal_host[0];
   if (st) {
@@ -496,69 +274,69 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   HIP_TRY(c, hipEventRecord(c->enter, c->stream), "hipEventRecord");
   HIP_TRY(c, hipStreamWaitEvent(q, c->enter, 0), "hipStreamWaitEvent");
   HIP_TRY(c, hipEventRecord(c->t0, q), "hipEventRecord");
-  HIP_TRY(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
+  HIP_TRY(c, hipMemcpyAsync(c->w.ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
 
   // ---- kernel arguments ----
   AssignArgs a{};
-  a.X = X; a.N = N; a.d = d; a.K = K; a.C = c->C_tmp; a.nc = c->nc_tmp;
-  a.Cb = gbf ? c->Cb_tmp : nullptr; a.delta = gbf ? c->del_tmp : nullptr;
-  a.lab = c->labels; a.lab_prev = nullptr; a.e_part = c->e_part; a.ctl = c->ctl;
+  a.X = X; a.N = N; a.d = d; a.K = K; a.C = c->w.C_tmp; a.nc = c->w.nc_tmp;
+  a.Cb = gbf ? c->w.Cb_tmp : nullptr; a.delta = gbf ? c->w.del_tmp : nullptr;
+  a.lab = c->w.labels; a.lab_prev = nullptr; a.e_part = c->w.e_part; a.ctl = c->w.ctl;
   a.xbf16 = xbf; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xbf, d, K);
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xbf;
-  u.lab = c->labels; u.lab_from_ctl = 1; u.lrank = c->lrank; u.blockcount = c->blockcount;
-  u.counts = c->counts; u.seg_start = c->seg_start; u.item_start = c->item_start;
-  u.item_cluster = c->item_cluster; u.perm = c->perm; u.partial = c->partial;
-  u.max_items = update_max_items(N, K); u.ctl = c->ctl; u.gated = 1;
+  u.lab = c->w.labels; u.lab_from_ctl = 1; u.lrank = c->w.lrank; u.blockcount = c->w.blockcount;
+  u.counts = c->w.counts; u.seg_start = c->w.seg_start; u.item_start = c->w.item_start;
+  u.item_cluster = c->w.item_cluster; u.perm = c->w.perm; u.partial = c->w.partial;
+  u.max_items = update_max_items(N, K); u.ctl = c->w.ctl; u.gated = 1;
   FinalizeArgs f{};
-  f.d = d; f.K = K; f.cap = cap; f.partial = c->partial; f.item_start = c->item_start;
-  f.counts = c->counts; f.C_in = c->C_tmp; f.C_out = nullptr;
-  f.C_cand = c->C_cand; f.C_fb = c->C_fb;
-  f.G_last = c->G_last; f.F_last = c->F_last; f.ring_dF = c->ring_dF; f.ring_dG = c->ring_dG;
-  f.dots = c->dots; f.ctl = c->ctl; f.mode = kFinInit;
+  f.d = d; f.K = K; f.cap = cap; f.partial = c->w.partial; f.item_start = c->w.item_start;
+  f.counts = c->w.counts; f.C_in = c->w.C_tmp; f.C_out = nullptr;
+  f.C_cand = c->w.C_cand; f.C_fb = c->w.C_fb;
+  f.G_last = c->w.G_last; f.F_last = c->w.F_last; f.ring_dF = c->w.ring_dF; f.ring_dG = c->w.ring_dG;
+  f.dots = c->w.dots; f.ctl = c->w.ctl; f.mode = kFinInit;
   CombineArgs cb{};
-  cb.ctl = c->ctl; cb.gated = 0; cb.G_last = c->G_last; cb.ring_dG = c->ring_dG;
+  cb.ctl = c->w.ctl; cb.gated = 0; cb.G_last = c->w.G_last; cb.ring_dG = c->w.ring_dG;
   cb.K = K; cb.d = d; cb.cap = cap;
-  cb.C_cand = c->C_cand; cb.nc_cand = c->nc_cand; cb.Cb_cand = gbf ? c->Cb_cand : nullptr;
-  cb.delta_cand = gbf ? c->del_cand : nullptr;
-  cb.C_fb = c->C_fb; cb.nc_fb = c->nc_fb; cb.Cb_fb = gbf ? c->Cb_fb : nullptr;
-  cb.delta_fb = gbf ? c->del_fb : nullptr;
+  cb.C_cand = c->w.C_cand; cb.nc_cand = c->w.nc_cand; cb.Cb_cand = gbf ? c->w.Cb_cand : nullptr;
+  cb.delta_cand = gbf ? c->w.del_cand : nullptr;
+  cb.C_fb = c->w.C_fb; cb.nc_fb = c->w.nc_fb; cb.Cb_fb = gbf ? c->w.Cb_fb : nullptr;
+  cb.delta_fb = gbf ? c->w.del_fb : nullptr;
 
   // ---- prologue: P^0 = Assign(C^0), G^0 = Update(P^0), F^0 = G^0 - C^0, C^1 = G^0 ----
-  HIP_TRY(c, hipMemcpyAsync(c->C_tmp, C0, cbytes, hipMemcpyDeviceToDevice, q), "copy C0");
-  HIP_TRY(c, launch_prep(c->C_tmp, K, d, c->nc_tmp, gbf ? c->Cb_tmp : nullptr,
-                         gbf ? c->del_tmp : nullptr, q), "prep");
+  HIP_TRY(c, hipMemcpyAsync(c->w.C_tmp, C0, cbytes, hipMemcpyDeviceToDevice, q), "copy C0");
+  HIP_TRY(c, launch_prep(c->w.C_tmp, K, d, c->w.nc_tmp, gbf ? c->w.Cb_tmp : nullptr,
+                         gbf ? c->w.del_tmp : nullptr, q), "prep");
   HIP_TRY(c, launch_assign(a, kRolePlain, q), "assignment");
   HIP_TRY(c, launch_update_sums(u, q), "update");
   HIP_TRY(c, launch_finalize(f, q), "finalize");
   HIP_TRY(c, launch_combine(cb, q), "combine");
   // counters of the first candidate pass start from zero
-  HIP_TRY(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
+  HIP_TRY(c, hipMemcpyAsync(c->w.ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
 
   // ---- per-iteration launch sequence, captured once into two graphs ----
   const int grid = assign_grid(a);
   if (grid <= 0) return fail(c, KM_EUNSUPPORTED, "no assignment kernel for this shape");
   AssignArgs ac = a;
-  ac.C = c->C_cand; ac.nc = c->nc_cand; ac.Cb = gbf ? c->Cb_cand : nullptr;
-  ac.delta = gbf ? c->del_cand : nullptr; ac.e_part = c->e_part;
+  ac.C = c->w.C_cand; ac.nc = c->w.nc_cand; ac.Cb = gbf ? c->w.Cb_cand : nullptr;
+  ac.delta = gbf ? c->w.del_cand : nullptr; ac.e_part = c->w.e_part;
   AssignArgs af = a;
-  af.C = c->C_fb; af.nc = c->nc_fb; af.Cb = gbf ? c->Cb_fb : nullptr;
-  af.delta = gbf ? c->del_fb : nullptr; af.e_part = c->e_part + grid;
+  af.C = c->w.C_fb; af.nc = c->w.nc_fb; af.Cb = gbf ? c->w.Cb_fb : nullptr;
+  af.delta = gbf ? c->w.del_fb : nullptr; af.e_part = c->w.e_part + grid;
   FinalizeArgs fi = f;
   fi.mode = kFinIter; fi.C_in = nullptr;
   CombineArgs ci = cb;
   ci.gated = 1;
-  ci.dots = c->dots; ci.n_dots = finalize_grid(KD); ci.gram = c->gram; ci.trace_rec = opt.trace_rec;
+  ci.dots = c->w.dots; ci.n_dots = finalize_grid(KD); ci.gram = c->w.gram; ci.trace_rec = opt.trace_rec;
 
   // The candidate assignment is launched directly (between two HIP events
   // when timing is on); the rest of the iteration is replayed from a graph.
   CtlArgs k1{};
-  k1.ctl = c->ctl; k1.e_part = c->e_part; k1.n_part = grid; k1.stage = 1;
-  k1.tr.trace_C = opt.trace_C; k1.tr.trace_rec = opt.trace_rec; k1.tr.C_cand = c->C_cand;
+  k1.ctl = c->w.ctl; k1.e_part = c->w.e_part; k1.n_part = grid; k1.stage = 1;
+  k1.tr.trace_C = opt.trace_C; k1.tr.trace_rec = opt.trace_rec; k1.tr.C_cand = c->w.C_cand;
   k1.tr.K = K; k1.tr.d = d;
   CtlArgs k2 = k1;
-  k2.e_part = c->e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
+  k2.e_part = c->w.e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
 
   auto enqueue_rest = [&](int p) -> km_status {
     HIP_TRY(c, launch_controller(k1, q), "controller");
@@ -567,7 +345,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     HIP_TRY(c, launch_update_sums(u, q), "update");
     HIP_TRY(c, launch_finalize(fi, q), "finalize");
     HIP_TRY(c, launch_combine(ci, q), "combine");
-    HIP_TRY(c, hipMemcpyAsync(&c->done_host[p], &c->ctl->done, sizeof(int), hipMemcpyDeviceToHost, q),
+    HIP_TRY(c, hipMemcpyAsync(&c->done_host[p], &c->w.ctl->done, sizeof(int), hipMemcpyDeviceToHost, q),
             "poll copy");
     return KM_OK;
   };
@@ -622,7 +400,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     }
     ++launched;
   }
-  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, q), "copy ctl");
+  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, q), "copy ctl");
   HIP_TRY(c, hipStreamSynchronize(q), "hipStreamSynchronize");
   if (c->timing && !finished) {  // the last launched iteration was not inspected in the loop
     float ms = 0.f;
@@ -634,9 +412,9 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   }
   Ctl r = *c->ctl_host;
   if (!r.done) return fail(c, KM_EDEVICE, "solver did not reach a final state");
-  const float* Cres = r.acc_src == 1 ? c->C_fb : c->C_cand;
+  const float* Cres = r.acc_src == 1 ? c->w.C_fb : c->w.C_cand;
   HIP_TRY(c, hipMemcpyAsync(C_out, Cres, cbytes, hipMemcpyDeviceToDevice, q), "copy C");
-  HIP_TRY(c, hipMemcpyAsync(rho_out, c->labels + (size_t)r.lab_prev * N, (size_t)N * 4,
+  HIP_TRY(c, hipMemcpyAsync(rho_out, c->w.labels + (size_t)r.lab_prev * N, (size_t)N * 4,
                             hipMemcpyDeviceToDevice, q), "copy rho");
   HIP_TRY(c, hipEventRecord(c->t1, q), "hipEventRecord");
   HIP_TRY(c, hipStreamSynchronize(q), "hipStreamSynchronize");

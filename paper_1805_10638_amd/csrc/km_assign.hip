@@ -100,10 +100,10 @@ hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s) {
 // Centroid preparation: ||c_j||^2 (float64 sum, rounded), bf16 hi/lo pair, residual norms
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_prep(const float* C, int K, int d, float* nc, uint16_t* Cb,
-                                              float* delta) {
+__device__ __forceinline__ void prep_body(const float* C, int K, int d, float* nc, uint16_t* Cb, float* delta,
+                                          int bx) {
   const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int j = bx * 4 + (threadIdx.x >> 6);
   if (j >= K) return;
   const float* cr = C + (int64_t)j * d;
   const int64_t KD = (int64_t)K * d;
@@ -125,6 +125,24 @@ __global__ __launch_bounds__(256) void k_prep(const float* C, int K, int d, floa
     nc[j] = (float)p;
     if (Cb) delta[j] = (float)sqrt(e);
   }
+}
+
+__global__ __launch_bounds__(256) void k_prep(const float* C, int K, int d, float* nc, uint16_t* Cb,
+                                              float* delta) {
+  prep_body(C, K, d, nc, Cb, delta, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_prep_batch(BatchRef<PrepArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  const PrepArgs& p = t.tab[b];
+  prep_body(p.C, p.K, p.d, p.nc, p.Cb, p.delta, blockIdx.x - t.prefix[b]);
+}
+
+hipError_t launch_prep_batch(const PrepArgs* tab, const int* prefix, int n, int blocks, hipStream_t s) {
+  clear_pending_error();
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep_batch, dim3(blocks), dim3(256), 0, s, BatchRef<PrepArgs>{tab, prefix, n});
+  return hipGetLastError();
 }
 
 hipError_t launch_prep(const float* C, int K, int d, float* nc, uint16_t* Cb, float* delta,
@@ -153,6 +171,32 @@ __global__ __launch_bounds__(256) void k_controller(CtlArgs a) {
   __shared__ double red[256];
   if (a.ctl->done) return;
   controller_stage(a.ctl, a.e_part, a.n_part, a.stage, a.tr, red);
+}
+
+__global__ __launch_bounds__(256) void k_controller_batch(const CtlArgs* tab) {
+  __shared__ double red[256];
+  const CtlArgs& a = tab[blockIdx.x];
+  if (a.ctl->done) return;
+  controller_stage(a.ctl, a.e_part, a.n_part, a.stage, a.tr, red);
+}
+
+hipError_t launch_controller_batch(const CtlArgs* tab, int n, hipStream_t s) {
+  clear_pending_error();
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_controller_batch, dim3(n), dim3(256), 0, s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign_batch(const KernelPick& p, const AssignArgs* tab, const int* prefix, int n, int blocks,
+                               size_t lds, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (!p.fn_batch || blocks <= 0) return hipErrorInvalidValue;
+  hipError_t e = allow_lds(p);
+  if (e != hipSuccess) return e;
+  BatchRef<AssignArgs> ref{tab, prefix, n};
+  void* params[] = {&ref};
+  clear_pending_error();
+  return hipLaunchKernel(p.fn_batch, dim3(blocks), dim3(p.threads), params, lds, s);
 }
 
 hipError_t launch_controller(const CtlArgs& a, hipStream_t s) {

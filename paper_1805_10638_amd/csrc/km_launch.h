@@ -37,6 +37,19 @@ int64_t assign_resident(const KernelPick& p, int64_t N, double frac);
 // ||c_j||^2 (and the bfloat16 hi/lo pair with its residual norms when Cb != null).
 hipError_t launch_prep(const float* C, int K, int d, float* nc, uint16_t* Cb, float* delta,
                        hipStream_t s);
+struct PrepArgs {
+  const float* C;
+  int K, d;
+  float* nc;
+  uint16_t* Cb;
+  float* delta;
+};
+inline int prep_grid(int K) { return (K + 3) / 4; }
+hipError_t launch_prep_batch(const PrepArgs* tab, const int* prefix, int n, int blocks, hipStream_t s);
+// Batched assignment: every instance of tab uses the kernel of p (same
+// template), grid slices per prefix; lds = the largest LDS need of them.
+hipError_t launch_assign_batch(const KernelPick& p, const AssignArgs* tab, const int* prefix, int n, int blocks,
+                               size_t lds, hipStream_t s);
 
 // ----- update step (Sec. 1, Eq. (4)): counting sort + segmented sum -----
 struct UpdateArgs {
@@ -60,6 +73,18 @@ struct UpdateArgs {
 int update_max_items(int64_t N, int K);
 int update_rank_blocks(int64_t N);
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s);
+// workgroups of update kernel `which` (0 rank, 1 scan, 2 scatter, 3 segsum)
+int update_grid(const UpdateArgs& u, int which);
+// Batched update: tab (device) one UpdateArgs per instance; prefix[w]
+// (device, n + 1 entries) the cumulative workgroups of kernel w; blocks[w]
+// the launch size.  The offsets kernel runs one workgroup per instance.
+struct UpdateBatch {
+  const UpdateArgs* tab;
+  const int* prefix[4];
+  int blocks[4];
+  int n;
+};
+hipError_t launch_update_sums_batch(const UpdateBatch& ub, hipStream_t s);
 
 // Finalisation of the means and, in the solver, the residual/history push.
 enum FinMode : int { kFinG = 0, kFinInit = 1, kFinIter = 2 };
@@ -82,6 +107,7 @@ struct FinalizeArgs {
 };
 int finalize_grid(int64_t KD);
 hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s);
+hipError_t launch_finalize_batch(const FinalizeArgs* tab, const int* prefix, int n, int blocks, hipStream_t s);
 
 // ----- controller (Algorithm 1) -----
 struct CtlArgs {
@@ -92,6 +118,8 @@ struct CtlArgs {
   CtlTrace tr;
 };
 hipError_t launch_controller(const CtlArgs& a, hipStream_t s);
+// one workgroup per instance
+hipError_t launch_controller_batch(const CtlArgs* tab, int n, hipStream_t s);
 
 // ----- Anderson step (Sec. 2.1, Eq. (7)-(8)) -----
 struct CombineArgs {
@@ -108,6 +136,8 @@ struct CombineArgs {
   float* C_fb; float* nc_fb; uint16_t* Cb_fb; float* delta_fb;
 };
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s);
+int combine_grid(int K);
+hipError_t launch_combine_batch(const CombineArgs* tab, const int* prefix, int n, int blocks, hipStream_t s);
 
 // Plain energy reduction for stand-alone G(C): sum of partials in fixed order.
 hipError_t launch_reduce_energy(const double* e_part, int n, double* out, hipStream_t s);

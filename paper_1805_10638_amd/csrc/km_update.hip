@@ -31,7 +31,7 @@ __device__ __forceinline__ const int* labels_of(const UpdateArgs& u) {
 // ---------------------------------------------------------------------------
 // 1. ranks within blocks of kRankRows rows
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rank(UpdateArgs u) {
+__device__ __forceinline__ void rank_body(const UpdateArgs& u, int bx) {
   if (u.gated && u.ctl->done) return;
   __shared__ int cnt[4][kMaxK];
   const int* L = labels_of(u);
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) {
   const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int kChunks = kRankRows / 256;   // 64-row chunks per wave
-  const int64_t base = (int64_t)blockIdx.x * kRankRows + (int64_t)w * (kChunks * 64);
+  const int64_t base = (int64_t)bx * kRankRows + (int64_t)w * (kChunks * 64);
   int labs[kChunks], rk[kChunks];
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) {
       cnt[ww][j] = s;
       s += v;
     }
-    u.blockcount[(int64_t)j * nblk + blockIdx.x] = s;
+    u.blockcount[(int64_t)j * nblk + bx] = s;
   }
   __syncthreads();
 #pragma unroll
@@ -105,11 +105,11 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 // ---------------------------------------------------------------------------
 // 2. per-label prefix over blocks: one workgroup per label
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scan(UpdateArgs u) {
+__device__ __forceinline__ void scan_body(const UpdateArgs& u, int bx) {
   if (u.gated && u.ctl->done) return;
   __shared__ int wsum[4];
   __shared__ int carry;
-  const int j = blockIdx.x;
+  const int j = bx;
   const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int* row = u.blockcount + (int64_t)j * nblk;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_scan(UpdateArgs u) {
 // ---------------------------------------------------------------------------
 // 3. segment starts and work items (one workgroup of 1024 threads)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_offsets(UpdateArgs u) {
+__device__ __forceinline__ void offsets_body(const UpdateArgs& u) {
   if (u.gated && u.ctl->done) return;
   __shared__ int wc[16], wi[16];
   __shared__ int empty_sh;
@@ -179,10 +179,10 @@ __global__ __launch_bounds__(1024) void k_offsets(UpdateArgs u) {
 // ---------------------------------------------------------------------------
 // 4. stable scatter
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scatter(UpdateArgs u) {
+__device__ __forceinline__ void scatter_body(const UpdateArgs& u, int bx) {
   if (u.gated && u.ctl->done) return;
   const int* L = labels_of(u);
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)bx * 256 + threadIdx.x;
   if (i >= u.N) return;
   const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
   int lab = L[i];
@@ -195,10 +195,10 @@ __global__ __launch_bounds__(256) void k_scatter(UpdateArgs u) {
 // ---------------------------------------------------------------------------
 // 5. segmented sums: one workgroup per work item
 // ---------------------------------------------------------------------------
-template <bool XBF>
-__global__ __launch_bounds__(256) void k_segsum(UpdateArgs u) {
+__device__ __forceinline__ void segsum_body(const UpdateArgs& u, int bx) {
   if (u.gated && u.ctl->done) return;
-  const int item = blockIdx.x;
+  const int item = bx;
+  const bool XBF = u.xbf16 != 0;
   if (item >= u.ctl->total_items) return;
   __shared__ double red[256 * 4];
   const int d = u.d;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_segsum(UpdateArgs u) {
       const int64_t pp = p + (int64_t)kPf * rpp;
       pidx[kPf - 1] = pp < p1 ? u.perm[pp] : 0;
     }
-    if (XBF) {
+    if (XBF) {   // uniform per workgroup
       const uint16_t* xr = (const uint16_t*)u.X + i * d;
       if (vec) {
         const uint2 v = *(const uint2*)(xr + k0);
@@ -274,22 +274,63 @@ __global__ __launch_bounds__(256) void k_segsum(UpdateArgs u) {
 int update_rank_blocks(int64_t N) { return (int)((N + kRankRows - 1) / kRankRows); }
 int update_max_items(int64_t N, int K) { return (int)((N + kSegRows - 1) / kSegRows) + K; }
 
+__global__ __launch_bounds__(256) void k_rank(UpdateArgs u) { rank_body(u, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_scan(UpdateArgs u) { scan_body(u, blockIdx.x); }
+__global__ __launch_bounds__(1024) void k_offsets(UpdateArgs u) { offsets_body(u); }
+__global__ __launch_bounds__(256) void k_scatter(UpdateArgs u) { scatter_body(u, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_segsum(UpdateArgs u) { segsum_body(u, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_rank_batch(BatchRef<UpdateArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  rank_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
+__global__ __launch_bounds__(256) void k_scan_batch(BatchRef<UpdateArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  scan_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
+__global__ __launch_bounds__(1024) void k_offsets_batch(BatchRef<UpdateArgs> t) {
+  offsets_body(t.tab[blockIdx.x]);   // one workgroup per instance
+}
+__global__ __launch_bounds__(256) void k_scatter_batch(BatchRef<UpdateArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  scatter_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
+__global__ __launch_bounds__(256) void k_segsum_batch(BatchRef<UpdateArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  segsum_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
+
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
   if (u.K > kMaxK || u.d > kMaxD) return hipErrorInvalidValue;
   const int nblk = update_rank_blocks(u.N);
   clear_pending_error();
   hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(256), 0, s, u);
-  clear_pending_error();
   hipLaunchKernelGGL(k_scan, dim3(u.K), dim3(256), 0, s, u);
-  clear_pending_error();
   hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, u);
-  clear_pending_error();
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)((u.N + 255) / 256)), dim3(256), 0, s, u);
-  if (u.xbf16)
-    hipLaunchKernelGGL(k_segsum<true>, dim3(u.max_items), dim3(256), 0, s, u);
-  else
-    hipLaunchKernelGGL(k_segsum<false>, dim3(u.max_items), dim3(256), 0, s, u);
+  hipLaunchKernelGGL(k_segsum, dim3(u.max_items), dim3(256), 0, s, u);
   return hipGetLastError();
+}
+
+hipError_t launch_update_sums_batch(const UpdateBatch& ub, hipStream_t s) {
+  clear_pending_error();
+  if (ub.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rank_batch, dim3(ub.blocks[0]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[0], ub.n});
+  hipLaunchKernelGGL(k_scan_batch, dim3(ub.blocks[1]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[1], ub.n});
+  hipLaunchKernelGGL(k_offsets_batch, dim3(ub.n), dim3(1024), 0, s, BatchRef<UpdateArgs>{ub.tab, nullptr, ub.n});
+  hipLaunchKernelGGL(k_scatter_batch, dim3(ub.blocks[2]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[2], ub.n});
+  hipLaunchKernelGGL(k_segsum_batch, dim3(ub.blocks[3]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[3], ub.n});
+  return hipGetLastError();
+}
+
+int update_grid(const UpdateArgs& u, int which) {
+  switch (which) {
+    case 0: return update_rank_blocks(u.N);
+    case 1: return u.K;
+    case 2: return (int)((u.N + 255) / 256);
+    case 3: return u.max_items;
+  }
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -297,14 +338,14 @@ hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int kDotGroup = 8;    // history slots reduced per pass over the elements
 
-__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
+__device__ __forceinline__ void finalize_body(const FinalizeArgs& f, int bx, int gx) {
   Ctl* ctl = f.ctl;
   if (f.mode == kFinIter && ctl->done) return;
   __shared__ double red[2 * kDotGroup][4];
   const int tid = threadIdx.x;
   const int d = f.d, cap = f.cap;
   const int64_t KD = (int64_t)f.K * d;
-  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t stride = (int64_t)gx * 256;
 
   int s_new = 0, len_new = 0;
   if (f.mode == kFinIter && cap > 0) {
@@ -315,7 +356,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
   }
   const float* Cacc = (f.mode == kFinIter && ctl->acc_src == 1) ? f.C_fb : f.C_cand;
 
-  for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < KD; e += stride) {
+  for (int64_t e = (int64_t)bx * 256 + tid; e < KD; e += stride) {
     const int j = (int)((uint32_t)e / (uint32_t)d);   // K*d < 2^31
     const int n = f.counts[j];
     const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
@@ -347,7 +388,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
     double pa[kDotGroup], pb[kDotGroup];
 #pragma unroll
     for (int g = 0; g < kDotGroup; ++g) { pa[g] = 0.0; pb[g] = 0.0; }
-    for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < KD; e += stride) {
+    for (int64_t e = (int64_t)bx * 256 + tid; e < KD; e += stride) {
       const double dfn = f.ring_dF[(int64_t)s_new * KD + e];
       const double fv = f.F_last[e];
 #pragma unroll
@@ -375,8 +416,8 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
     __syncthreads();
     if (tid < kDotGroup && q0 + tid < len_new) {
       const int sl = (s_new - (q0 + tid) + cap) % cap;
-      f.dots[(int64_t)blockIdx.x * 2 * cap + sl] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
-      f.dots[(int64_t)blockIdx.x * 2 * cap + cap + sl] =
+      f.dots[(int64_t)bx * 2 * cap + sl] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+      f.dots[(int64_t)bx * 2 * cap + cap + sl] =
           ((red[kDotGroup + tid][0] + red[kDotGroup + tid][1]) + red[kDotGroup + tid][2]) + red[kDotGroup + tid][3];
     }
     __syncthreads();
@@ -386,6 +427,21 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
 int finalize_grid(int64_t KD) {
   const int64_t g = (KD + 255) / 256;
   return (int)(g < 128 ? (g > 0 ? g : 1) : 128);
+}
+
+__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) { finalize_body(f, blockIdx.x, gridDim.x); }
+
+__global__ __launch_bounds__(256) void k_finalize_batch(BatchRef<FinalizeArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  const int b0 = t.prefix[b];
+  finalize_body(t.tab[b], blockIdx.x - b0, t.prefix[b + 1] - b0);
+}
+
+hipError_t launch_finalize_batch(const FinalizeArgs* tab, const int* prefix, int n, int blocks, hipStream_t s) {
+  clear_pending_error();
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize_batch, dim3(blocks), dim3(256), 0, s, BatchRef<FinalizeArgs>{tab, prefix, n});
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s) {

@@ -1,0 +1,138 @@
+// Workspace of one solve: the device buffers of Algorithm 1 for one
+// instance, carved out of a single allocation.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "km_launch.h"
+
+namespace km {
+
+constexpr size_t kWsAlign = 256;
+inline size_t ws_up(size_t v) { return (v + kWsAlign - 1) & ~(kWsAlign - 1); }
+
+// Sizes that determine the workspace layout.
+struct Shape {
+  int64_t N = 0;
+  int d = 0, K = 0, cap = 0, bf = 0;
+  bool fits(const Shape& o) const {
+    return N >= o.N && d >= o.d && K >= o.K && cap >= o.cap && bf >= o.bf &&
+           (int64_t)K * d >= (int64_t)o.K * o.d;
+  }
+};
+
+struct Ws {
+  Ctl* ctl = nullptr;
+  int* labels = nullptr;        // 3 x N
+  int* lrank = nullptr;         // N
+  int* perm = nullptr;          // N
+  int* blockcount = nullptr;    // nblk x K
+  int* counts = nullptr;        // K
+  int* seg_start = nullptr;     // K + 1
+  int* item_start = nullptr;    // K + 1
+  int* item_cluster = nullptr;  // max_items
+  double* e_part = nullptr;     // 2 x (N / 64 + 1): partials of the candidate and fall-back passes
+  double* partial = nullptr;    // max_items x d
+  double* G_last = nullptr;     // K x d
+  double* F_last = nullptr;     // K x d
+  double* ring_dF = nullptr;    // cap x K x d
+  double* ring_dG = nullptr;    // cap x K x d
+  double* gram = nullptr;       // cap x cap
+  double* dots = nullptr;       // fin_grid x 2 cap
+  double* e_out = nullptr;      // 1
+  float* C_cand = nullptr;      // K x d
+  float* C_fb = nullptr;        // K x d
+  float* C_tmp = nullptr;       // K x d (kmeans_g / prologue input copy)
+  float* nc_cand = nullptr;
+  float* nc_fb = nullptr;
+  float* nc_tmp = nullptr;
+  uint16_t* Cb_cand = nullptr;  // bf16 hi/lo pairs, 2 x K x d (bf16 GEMM only)
+  uint16_t* Cb_fb = nullptr;
+  uint16_t* Cb_tmp = nullptr;
+  float* del_cand = nullptr;
+  float* del_fb = nullptr;
+  float* del_tmp = nullptr;
+  int max_items = 0, nblk = 0, fin_grid = 0;
+};
+
+// Bytes of the workspace for s; with base != null also fills w.
+inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
+  const int64_t N = s.N;
+  const int64_t KD = (int64_t)s.K * s.d;
+  const int64_t grid = N / 64 + 1;   // upper bound of an assignment grid
+  const int max_items = update_max_items(N, s.K);
+  const int nblk = update_rank_blocks(N);
+  const int fin_grid = finalize_grid(KD);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += ws_up(bytes); return o; };
+  const size_t o_ctl = take(sizeof(Ctl));
+  const size_t o_lab = take(3 * N * 4);
+  const size_t o_lr = take(N * 4);
+  const size_t o_perm = take(N * 4);
+  const size_t o_bc = take((size_t)nblk * s.K * 4);
+  const size_t o_cnt = take((size_t)s.K * 4);
+  const size_t o_ss = take((size_t)(s.K + 1) * 4);
+  const size_t o_is = take((size_t)(s.K + 1) * 4);
+  const size_t o_ic = take((size_t)max_items * 4);
+  const size_t o_ep = take((size_t)2 * grid * 8);
+  const size_t o_pa = take((size_t)max_items * s.d * 8);
+  const size_t o_gl = take(KD * 8);
+  const size_t o_fl = take(KD * 8);
+  const size_t o_rf = take((size_t)s.cap * KD * 8);
+  const size_t o_rg = take((size_t)s.cap * KD * 8);
+  const size_t o_gr = take((size_t)s.cap * s.cap * 8 + 8);
+  const size_t o_dt = take((size_t)fin_grid * 2 * s.cap * 8 + 8);
+  const size_t o_eo = take(8);
+  const size_t o_cc = take(KD * 4);
+  const size_t o_cf = take(KD * 4);
+  const size_t o_ct = take(KD * 4);
+  const size_t o_nc = take((size_t)s.K * 4);
+  const size_t o_nf = take((size_t)s.K * 4);
+  const size_t o_nt = take((size_t)s.K * 4);
+  const size_t o_bcand = take(s.bf ? KD * 4 : 0);
+  const size_t o_bfb = take(s.bf ? KD * 4 : 0);
+  const size_t o_btmp = take(s.bf ? KD * 4 : 0);
+  const size_t o_dc = take(s.bf ? s.K * 4 : 0);
+  const size_t o_df = take(s.bf ? s.K * 4 : 0);
+  const size_t o_dtmp = take(s.bf ? s.K * 4 : 0);
+  if (base && w) {
+    char* b = base;
+    w->ctl = (Ctl*)(b + o_ctl);
+    w->labels = (int*)(b + o_lab);
+    w->lrank = (int*)(b + o_lr);
+    w->perm = (int*)(b + o_perm);
+    w->blockcount = (int*)(b + o_bc);
+    w->counts = (int*)(b + o_cnt);
+    w->seg_start = (int*)(b + o_ss);
+    w->item_start = (int*)(b + o_is);
+    w->item_cluster = (int*)(b + o_ic);
+    w->e_part = (double*)(b + o_ep);
+    w->partial = (double*)(b + o_pa);
+    w->G_last = (double*)(b + o_gl);
+    w->F_last = (double*)(b + o_fl);
+    w->ring_dF = (double*)(b + o_rf);
+    w->ring_dG = (double*)(b + o_rg);
+    w->gram = (double*)(b + o_gr);
+    w->dots = (double*)(b + o_dt);
+    w->e_out = (double*)(b + o_eo);
+    w->C_cand = (float*)(b + o_cc);
+    w->C_fb = (float*)(b + o_cf);
+    w->C_tmp = (float*)(b + o_ct);
+    w->nc_cand = (float*)(b + o_nc);
+    w->nc_fb = (float*)(b + o_nf);
+    w->nc_tmp = (float*)(b + o_nt);
+    w->Cb_cand = s.bf ? (uint16_t*)(b + o_bcand) : nullptr;
+    w->Cb_fb = s.bf ? (uint16_t*)(b + o_bfb) : nullptr;
+    w->Cb_tmp = s.bf ? (uint16_t*)(b + o_btmp) : nullptr;
+    w->del_cand = s.bf ? (float*)(b + o_dc) : nullptr;
+    w->del_fb = s.bf ? (float*)(b + o_df) : nullptr;
+    w->del_tmp = s.bf ? (float*)(b + o_dtmp) : nullptr;
+    w->max_items = max_items;
+    w->nblk = nblk;
+    w->fin_grid = fin_grid;
+  }
+  return off;
+}
+
+}  // namespace km

@@ -1,0 +1,181 @@
+"""Batched and served solving: each job's result equals kmeans_solve on that
+job alone (labels, iteration count and decisions exactly; centroids and
+energy within the float rounding of differently split energy partials),
+and agrees with the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from oracle import kmeans_oracle as ko
+from paper_1805_10638_amd import synth
+
+from helpers import dev, x_tensor, x_values
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_1805_10638_amd as km
+    return km
+
+
+def _problems(sizes, seed0=0, bf16=False):
+    out = []
+    for i, (n, d, k) in enumerate(sizes):
+        x, _ = synth.instance(n, d, k, seed=seed0 + i)
+        if bf16:
+            x = synth.to_bf16_bits(x)
+        c0 = synth.init_centroids(x, k, seed0 + i)
+        out.append((x, c0))
+    return out
+
+
+def _solo(km, X, C0, **kw):
+    C, rho, E, it, st = km.kmeans_solve(X, C0, **kw)
+    return C.cpu().numpy(), rho.cpu().numpy(), E, it, st
+
+
+def _same(solo, batched):
+    C1, r1, E1, it1, st1 = solo
+    C2, r2, res = batched
+    C2 = C2.cpu().numpy()
+    r2 = r2.cpu().numpy()
+    assert res.iters == it1
+    assert (res.accepted, res.rejected, res.assign_passes) == (st1.accepted, st1.rejected, st1.assign_passes)
+    assert np.array_equal(r1, r2)
+    assert res.E == pytest.approx(E1, rel=1e-12)
+    scale = np.maximum(np.abs(C1), 1.0)
+    assert np.max(np.abs(C1 - C2) / scale) <= 1e-6
+
+
+MIXED = [(2000, 3, 8), (5000, 16, 40), (3000, 64, 100), (12000, 3, 200), (2500, 16, 8),
+         (8000, 64, 24), (4000, 3, 60), (6000, 16, 130), (2100, 64, 300)]
+
+
+def test_batch_matches_solo():
+    km = _lib()
+    probs = _problems(MIXED, seed0=10)
+    ts = [(x_tensor(x), dev(c)) for x, c in probs]
+    kw = dict(m_max=10, tol=1e-6)
+    solo = [_solo(km, X, C0, **kw) for X, C0 in ts]
+    out = km.kmeans_solve_batch(ts, **kw)
+    assert len(out) == len(ts)
+    for s, b in zip(solo, out):
+        assert b[2].status in (0, 1)
+        _same(s, b)
+
+
+def test_batch_against_oracle():
+    km = _lib()
+    probs = _problems([(1500, 3, 8), (1200, 16, 20)], seed0=40)
+    out = km.kmeans_solve_batch([(x_tensor(x), dev(c)) for x, c in probs], m_max=10, tol=1e-6)
+    for (x, c0), (C, rho, res) in zip(probs, out):
+        o = ko.solve(x_values(x), c0.astype(np.float64), m_max=10, tol=1e-6)
+        assert res.iters == o.iters
+        assert res.E == pytest.approx(o.E, rel=1e-6)
+        a = ko.assign(x_values(x), C.cpu().numpy().astype(np.float64))
+        r = rho.cpu().numpy()
+        assert np.all((a.rho == r) | a.near_tie)
+
+
+def test_batch_bf16_gemm_matches_solo():
+    km = _lib()
+    probs = _problems([(3000, 16, 30), (2000, 64, 70), (4000, 3, 12)], seed0=60, bf16=True)
+    ts = [(x_tensor(x), dev(c)) for x, c in probs]
+    kw = dict(m_max=10, tol=1e-6, prec="bf16")
+    solo = [_solo(km, X, C0, **kw) for X, C0 in ts]
+    out = km.kmeans_solve_batch(ts, **kw)
+    for s, b in zip(solo, out):
+        _same(s, b)
+
+
+def test_batch_many_instances_compaction():
+    """64 instances: finished jobs are compacted out several times while the
+    rest continue; every result equals its solo solve."""
+    km = _lib()
+    sizes = synth.instance_sizes(64, rep=3)
+    sizes = [(min(n, 20000), d, min(k, 128)) for n, d, k in sizes]
+    probs = _problems(sizes, seed0=100)
+    ts = [(x_tensor(x), dev(c)) for x, c in probs]
+    out = km.kmeans_solve_batch(ts, m_max=10, tol=1e-6)
+    for i in range(0, 64, 7):
+        _same(_solo(km, *ts[i], m_max=10, tol=1e-6), out[i])
+
+
+def test_engine_staggered_admission():
+    """Jobs submitted while others run (continuous batching) give the same
+    results as alone."""
+    km = _lib()
+    probs = _problems(MIXED[:7], seed0=200)
+    ts = [(x_tensor(x), dev(c)) for x, c in probs]
+    eng = km.Engine(m_max=10, tol=1e-6, graphs=False)
+    tickets = {}
+    got = {}
+    for i in range(3):
+        tickets[eng.submit(*ts[i])] = i
+    for _ in range(4):
+        eng.step()
+        for t, C, rho, res in eng.poll():
+            got[tickets[t]] = (C, rho, res)
+    for i in range(3, 7):
+        tickets[eng.submit(*ts[i])] = i
+        eng.step()
+        for t, C, rho, res in eng.poll():
+            got[tickets[t]] = (C, rho, res)
+    for _ in range(2000):
+        if len(got) == len(ts):
+            break
+        eng.step()
+        for t, C, rho, res in eng.poll():
+            got[tickets[t]] = (C, rho, res)
+    eng.close()
+    assert len(got) == len(ts)
+    for i, (X, C0) in enumerate(ts):
+        _same(_solo(km, X, C0, m_max=10, tol=1e-6), got[i])
+        assert got[i][2].latency_ms > 0
+
+
+def test_engine_budget_admission():
+    """With a budget of about two workspaces, jobs wait for room; the device
+    never holds more than the budget."""
+    km = _lib()
+    probs = _problems([(6000, 16, 40)] * 5, seed0=300)
+    ts = [(x_tensor(x), dev(c)) for x, c in probs]
+    probe = km.Engine(m_max=10, tol=1e-6)
+    ws = probe.workspace_bytes(ts[0][0], 40)
+    probe.close()
+    budget = int(2.5 * ws)
+    eng = km.Engine(m_max=10, tol=1e-6, hbm_budget=budget, graphs=True)
+    tickets = {eng.submit(X, C0): i for i, (X, C0) in enumerate(ts)}
+    got = {}
+    max_active = 0
+    saw_queue = False
+    for _ in range(5000):
+        a, q, r = eng.step()
+        max_active = max(max_active, a)
+        saw_queue |= q > 0
+        for t, C, rho, res in eng.poll():
+            got[tickets[t]] = (C, rho, res)
+        if len(got) == len(ts):
+            break
+    eng.close()
+    assert len(got) == len(ts)
+    assert saw_queue and max_active * ws <= budget
+    for i, (X, C0) in enumerate(ts):
+        _same(_solo(km, X, C0, m_max=10, tol=1e-6), got[i])
+
+
+def test_engine_rejects_bad_jobs():
+    km = _lib()
+    x, _ = synth.instance(500, 3, 8, seed=1)
+    X = x_tensor(x)
+    eng = km.Engine(m_max=10, tol=1e-6, hbm_budget=1024)
+    with pytest.raises(km.KMError) as e:
+        eng.submit(X, dev(synth.init_centroids(x, 8, 1)))
+    assert e.value.status == -2          # workspace beyond the budget
+    eng.close()
+    eng = km.Engine(m_max=10, tol=1e-6)
+    with pytest.raises(km.KMError) as e:
+        eng.submit(X, dev(np.zeros((600, 3), np.float32)))   # K > N
+    assert e.value.status == -1
+    eng.close()
