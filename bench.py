@@ -41,9 +41,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time budget of the oracle baseline sample")
-    ap.add_argument("--workload", choices=["plain", "precision"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "precision", "batched", "served"], default="plain",
                     help="plain: N=1e6 d=32 K=256 float32 (default line); precision: "
-                         "N=4e6 d=128 K=1024 bfloat16-stored X, float32 vs bfloat16 GEMM")
+                         "N=4e6 d=128 K=1024 bfloat16-stored X, float32 vs bfloat16 GEMM; batched: "
+                         "512 uneven instances in one engine vs one at a time; served: Poisson arrivals "
+                         "(200 jobs/s) through the continuous-batching engine vs a FIFO loop")
+    ap.add_argument("--instances", type=int, default=512, help="batched: number of instances")
+    ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -101,6 +106,12 @@ def main():
     from paper_1805_10638_amd import synth
     if args.workload == "precision":
         precision_workload(args, km, synth, torch)
+        return
+    if args.workload == "batched":
+        batched_workload(args, km, synth, torch)
+        return
+    if args.workload == "served":
+        served_workload(args, km, synth, torch)
         return
 
     w = WORKLOAD
@@ -247,6 +258,148 @@ def precision_workload(args, km, synth, torch):
                       "steps": steps, "results": res,
                       "bf16_speedup": res["bf16"]["solves_per_s"] / res["f32"]["solves_per_s"],
                       "energy_rel_diff_bf16_vs_f32": abs(eb - ef) / ef}), flush=True)
+
+
+def batched_workload(args, km, synth, torch):
+    """Many uneven instances (N log-uniform in [2e3, 2e5], d in {3, 16, 64},
+    K log-uniform in [8, 512], float32, per-instance seeded init) solved by
+    one batched engine run, against the same instances solved one at a time
+    with kmeans_solve.  Both use the tuned tile shapes."""
+    n_inst = args.instances
+    sizes = synth.instance_sizes(n_inst, rep=0)
+    probs = [synth.device_instance(n, d, k, seed=i) for i, (n, d, k) in enumerate(sizes)]
+    torch.cuda.synchronize()
+    ctx = km.Context(0)
+    kw = dict(m_max=10, tol=1e-6, max_iter=500)
+    km.kmeans_solve_batch(probs[:8], ctx=ctx, **kw)          # warm-up (code objects, pools)
+    for X, C0 in probs[:8]:
+        km.kmeans_solve(X, C0, ctx=ctx, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = km.kmeans_solve_batch(probs, ctx=ctx, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    solo = []
+    for X, C0 in probs:
+        _, _, E, it, st = km.kmeans_solve(X, C0, ctx=ctx, **kw)
+        solo.append((E, it, st.assign_passes))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    flops = sum(2.0 * n * k * d * r[2].assign_passes for (n, d, k), r in zip(sizes, out))
+    dist = sum(float(n) * k * r[2].assign_passes for (n, d, k), r in zip(sizes, out))
+    it_mismatch = sum(int(r[2].iters != s[1]) for r, s in zip(out, solo))
+    e_rel = max(abs(r[2].E - s[0]) / max(abs(s[0]), 1e-300) for r, s in zip(out, solo))
+    ach = flops / t_batch / 1e12
+    print(json.dumps({
+        "metric": "batched: instances solved per second, one engine vs one at a time",
+        "value": n_inst / t_batch, "unit": "solves/s", "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": f"{n_inst} gaussian-mixture instances, N log-uniform [2e3,2e5], "
+                               "d in {3,16,64}, K log-uniform [8,512], float32, m_max=10 tol=1e-6",
+                   "total_rows": int(sum(n for n, _, _ in sizes)),
+                   "tuned_shape_entries": ctx.tuned_entries},
+        "batched_s": t_batch, "one_at_a_time_s": t_seq, "one_at_a_time_solves_per_s": n_inst / t_seq,
+        "speedup": t_seq / t_batch,
+        "iters_mean": statistics.mean(r[2].iters for r in out),
+        "iters_mismatch_vs_solo": it_mismatch, "max_E_rel_diff_vs_solo": e_rel,
+        "assign_flop": flops, "dist_evals_per_s": dist / t_batch,
+        "assignment_tflops_over_run": ach, "frac_fp32_mfma_peak_over_run": ach / FP32_MFMA_PEAK_TFLOPS,
+    }), flush=True)
+
+
+def served_workload(args, km, synth, torch):
+    """Poisson arrivals (rate per second, for `duration` seconds) of jobs
+    sized like the batched mix, plus 2 % large jobs (N=2e6, d=96, K=2048,
+    bfloat16 X, bfloat16 GEMM).  Each job's data is generated on the device
+    when it arrives (excluded from its latency); the engine admits jobs
+    under a 200 GB workspace budget while others run.  The baseline runs
+    the same jobs through a FIFO loop of float32 kmeans_solve calls, one at
+    a time, with latency = finish - arrival."""
+    rng = np.random.default_rng([180510638, 5, 0])
+    arrivals = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / args.rate)
+        if t > args.duration:
+            break
+        arrivals.append(t)
+    n = len(arrivals)
+    small = synth.instance_sizes(n, rep=0, cfg=5)
+    large = rng.random(n) < 0.02
+    spec = [((2_000_000, 96, 2048, True) if large[i] else (*small[i], False)) for i in range(n)]
+
+    def make(i):
+        nn, d, k, bf = spec[i]
+        return synth.device_instance(nn, d, k, seed=10_000 + i, bf16=bf)
+
+    ctx = km.Context(0)
+    kw = dict(m_max=10, tol=1e-6, max_iter=500)
+    eng = km.Engine(hbm_budget=200 * 10**9, graphs=False, ctx=ctx, **kw)
+    warm = min(3, n)                                # warm-up jobs, not timed
+    for i in range(warm):
+        X, C0 = make(i)
+        eng.submit(X, C0, prec="bf16" if spec[i][3] else "f32")
+    while warm > 0:
+        eng.step()
+        warm -= len(eng.poll())
+
+    lat, lag, lat_large = [], [], []
+    t_sub = {}
+    t_start = time.perf_counter()
+    i = done = 0
+    while done < n:
+        now = time.perf_counter() - t_start
+        while i < n and arrivals[i] <= now:
+            X, C0 = make(i)
+            tk = eng.submit(X, C0, prec="bf16" if spec[i][3] else "f32")
+            t_sub[tk] = (i, time.perf_counter())
+            lag.append(time.perf_counter() - t_start - arrivals[i])
+            i += 1
+        a, q, _ = eng.step()
+        for tk, C, rho, res in eng.poll():
+            j, ts = t_sub.pop(tk)
+            dt = (time.perf_counter() - ts) * 1e3
+            lat.append(dt)
+            if spec[j][3]:
+                lat_large.append(dt)
+            done += 1
+        if a == 0 and q == 0 and i < n:
+            time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t_start))))
+    t_served = time.perf_counter() - t_start
+    eng.close()
+
+    # FIFO baseline: float32 GEMM, one job at a time, in arrival order
+    fin = 0.0
+    base_lat = []
+    busy = 0.0
+    for j in range(n):
+        X, C0 = make(j)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        km.kmeans_solve(X, C0, ctx=ctx, prec="f32", **kw)
+        torch.cuda.synchronize()
+        dur = time.perf_counter() - t0
+        busy += dur
+        start = max(arrivals[j], fin)
+        fin = start + dur
+        base_lat.append((fin - arrivals[j]) * 1e3)
+        del X, C0
+
+    def pct(v, p):
+        v = sorted(v)
+        return v[min(len(v) - 1, max(0, int(round(p / 100.0 * (len(v) - 1)))))] if v else None
+
+    print(json.dumps({
+        "metric": "served: p50/p99 latency and solves/s, continuous batching vs FIFO float32",
+        "value": n / t_served, "unit": "solves/s", "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": f"Poisson {args.rate:g} jobs/s for {args.duration:g} s; sizes as the batched "
+                               "mix, 2% large (N=2e6 d=96 K=2048 bfloat16 X, bfloat16 GEMM); HBM budget 200 GB",
+                   "jobs": n, "large_jobs": int(large.sum())},
+        "served": {"solves_per_s": n / t_served, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                   "large_p50_ms": pct(lat_large, 50), "mean_submit_lag_ms": 1e3 * statistics.mean(lag)},
+        "fifo_f32": {"solves_per_s": n / fin, "p50_ms": pct(base_lat, 50), "p99_ms": pct(base_lat, 99),
+                     "busy_s": busy},
+    }), flush=True)
 
 
 if __name__ == "__main__":

@@ -190,6 +190,7 @@ typedef struct {
   const float *C0;       /* K x d float32, device */
   float *C_out;          /* K x d float32, device, written when the job finishes */
   int32_t *rho_out;      /* N int32, device, written when the job finishes */
+  km_prec prec;          /* distance-GEMM precision of this job */
 } km_job;
 
 typedef struct {
@@ -209,14 +210,15 @@ typedef struct km_engine km_engine;
  * trace pointers must be NULL).  hbm_budget bounds the bytes of job
  * workspaces on the device at once (0: no bound); queued jobs are admitted
  * in submission order when they fit.  graphs = 1 replays iterations from a
- * HIP graph while the job set is unchanged. */
+ * HIP graph while the job set is unchanged.  Each job's GEMM precision is
+ * its own (km_job.prec; opt->prec is not used). */
 km_status km_engine_create(km_ctx *ctx, int32_t m_max, double tol, const km_opts *opt,
                            int64_t hbm_budget, int32_t graphs, km_engine **out);
 /* Waits for the device and releases everything; unfinished jobs are dropped. */
 void km_engine_destroy(km_engine *e);
 
 /* Device workspace bytes of a job (what the budget counts), or -1. */
-int64_t km_job_workspace_bytes(const km_job *job, int32_t m_max, km_prec prec);
+int64_t km_job_workspace_bytes(const km_job *job, int32_t m_max);
 
 /* Queue a job (checked like kmeans_solve); *ticket names its result.  Its
  * buffers must stay valid until km_engine_poll has returned the result.

@@ -52,7 +52,8 @@ class _SolveStats(ct.Structure):
 
 class _Job(ct.Structure):
     _fields_ = [("X", ct.c_void_p), ("xt", ct.c_int), ("N", ct.c_int64), ("d", ct.c_int32),
-                ("K", ct.c_int32), ("C0", ct.c_void_p), ("C_out", ct.c_void_p), ("rho_out", ct.c_void_p)]
+                ("K", ct.c_int32), ("C0", ct.c_void_p), ("C_out", ct.c_void_p), ("rho_out", ct.c_void_p),
+                ("prec", ct.c_int)]
 
 
 class _JobResult(ct.Structure):
@@ -128,7 +129,7 @@ def load_library(path: str | None = None):
     lib.km_set_tile_shape.restype = ct.c_int
     lib.km_get_tile_shape.argtypes = [vp, ct.c_int, ct.c_int, i32, i32]
     lib.km_get_tile_shape.restype = ct.c_int
-    lib.km_job_workspace_bytes.argtypes = [ct.POINTER(_Job), i32, ct.c_int]
+    lib.km_job_workspace_bytes.argtypes = [ct.POINTER(_Job), i32]
     lib.km_job_workspace_bytes.restype = i64
     lib.km_engine_create.argtypes = [vp, i32, dbl, ct.POINTER(_Opts), i64, i32, ct.POINTER(vp)]
     lib.km_engine_create.restype = ct.c_int
@@ -165,7 +166,7 @@ def load_library(path: str | None = None):
 class Context:
     """A libkmaa context bound to one device (workspace + stream)."""
 
-    def __init__(self, device: int | None = None):
+    def __init__(self, device: int | None = None, tuned: bool = True):
         self.lib = load_library()
         if device is None:
             device = torch.cuda.current_device()
@@ -175,6 +176,10 @@ class Context:
         if st != KM_OK:
             raise KMError(st, "km_create failed: " + self.lib.km_status_str(st).decode())
         self.h = h
+        self.tuned_entries = 0
+        if tuned:  # tile shapes measured by the autotuner (tiles_gfx950.json), if present
+            from . import autotune
+            self.tuned_entries = autotune.apply_table(self, autotune.load_table())
 
     def close(self):
         if getattr(self, "h", None):
@@ -347,7 +352,7 @@ def _solver_opts(lib, m_init, max_iter, prec, eps1, eps2, ridge, fixed_m, litera
     return o
 
 
-def _make_job(X: torch.Tensor, C0: torch.Tensor, out, dev: int):
+def _make_job(X: torch.Tensor, C0: torch.Tensor, out, dev: int, prec):
     _check_dev(X, "X", dev)
     _check_dev(C0, "C0", dev)
     if C0.dtype != torch.float32:
@@ -361,7 +366,7 @@ def _make_job(X: torch.Tensor, C0: torch.Tensor, out, dev: int):
         rho = torch.empty(N, dtype=torch.int32, device=X.device)
     else:
         C, rho = out
-    j = _Job(X.data_ptr(), _xtype(X), N, d, K, C0.data_ptr(), C.data_ptr(), rho.data_ptr())
+    j = _Job(X.data_ptr(), _xtype(X), N, d, K, C0.data_ptr(), C.data_ptr(), rho.data_ptr(), _prec(prec))
     return j, (X, C0, C, rho)
 
 
@@ -371,16 +376,17 @@ def kmeans_solve_batch(problems, m_max: int = 10, tol: float = 1e-6, max_iter: i
                        ctx: "Context | None" = None):
     """Solve many instances together (kmeans_solve_batch in km.h).
 
-    ``problems`` is a list of (X, C0) pairs on one device.  Returns a list of
-    (C, rho, JobResult) in the same order."""
+    ``problems`` is a list of (X, C0) or (X, C0, prec) tuples on one device
+    (``prec`` defaults to the argument).  Returns a list of (C, rho,
+    JobResult) in the same order."""
     if not problems:
         return []
     dev = problems[0][0].device.index
     ctx = ctx or _context(dev)
     jobs = (_Job * len(problems))()
     keep = []
-    for i, (X, C0) in enumerate(problems):
-        jobs[i], k = _make_job(X, C0, None, dev)
+    for i, p in enumerate(problems):
+        jobs[i], k = _make_job(p[0], p[1], None, dev, p[2] if len(p) > 2 else prec)
         keep.append(k)
     res = (_JobResult * len(problems))()
     o = _solver_opts(ctx.lib, m_init, max_iter, prec, eps1, eps2, ridge, fixed_m, literal_return)
@@ -417,13 +423,14 @@ class Engine:
         self.h = h
         self._jobs = {}
 
-    def workspace_bytes(self, X: torch.Tensor, K: int) -> int:
+    def workspace_bytes(self, X: torch.Tensor, K: int, prec=None) -> int:
         N, d = X.shape
-        j = _Job(0, _xtype(X), N, d, K, 0, 0, 0)
-        return int(self.lib.km_job_workspace_bytes(ct.byref(j), self.m_max, _prec(self.prec)))
+        j = _Job(0, _xtype(X), N, d, K, 0, 0, 0, _prec(prec or self.prec))
+        return int(self.lib.km_job_workspace_bytes(ct.byref(j), self.m_max))
 
-    def submit(self, X: torch.Tensor, C0: torch.Tensor, out=None) -> int:
-        j, keep = _make_job(X, C0, out, self.device)
+    def submit(self, X: torch.Tensor, C0: torch.Tensor, out=None, prec=None) -> int:
+        """Queue a job; ``prec`` (GEMM precision) defaults to the engine's."""
+        j, keep = _make_job(X, C0, out, self.device, prec or self.prec)
         t = ct.c_int64()
         self.ctx._bind_stream()
         st = self.lib.km_engine_submit(self.h, ct.byref(j), ct.byref(t))

@@ -1,0 +1,110 @@
+"""Tile-shape autotuner for the assignment kernel.
+
+For each (GEMM precision, X type, d, K) bucket it times one application of
+G (kmeans_g) with every tile shape of the kernel family on seeded
+synthetic data and keeps the fastest; the table is written as JSON and
+applied to every Context created afterwards (see ``load_table``).
+
+    python -m paper_1805_10638_amd.autotune [--out FILE] [--rows N] [--reps R]
+
+Buckets: K rounds up to a power of two (at least 16) and d to the padded
+width of the kernel, exactly as km_set_tile_shape keys them.  The default
+bucket list covers the benchmark configurations: the batched mix (d in
+{3, 16, 64}, K from 8 to 512), d = 32 / K = 256 float32, d = 128 /
+K = 1024 and d = 96 / K = 2048 on bfloat16 rows.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tiles_gfx950.json")
+SHAPES = 4
+
+# (prec, xtype, d, K, rows)
+DEFAULT_BUCKETS = (
+    [("f32", "f32", d, k, 200_000) for d in (3, 16, 64) for k in (16, 32, 64, 128, 256, 512)]
+    + [("f32", "f32", 32, 256, 1_000_000),
+       ("bf16", "bf16", 128, 1024, 1_000_000), ("f32", "bf16", 128, 1024, 1_000_000),
+       ("bf16", "bf16", 96, 2048, 500_000)]
+)
+
+
+def load_table(path: str = TABLE):
+    """Entries of a tuning table, [] when there is none."""
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return json.load(f).get("entries", [])
+
+
+def apply_table(ctx, entries) -> int:
+    n = 0
+    for e in entries:
+        ctx.set_tile_shape(e["prec"], e["xtype"], int(e["d"]), int(e["K"]), int(e["shape"]))
+        n += 1
+    return n
+
+
+def _data(rows, d, k, xtype, seed):
+    from . import synth
+    x, _ = synth.plain_large(rep=seed, n=rows, d=d, k=max(2, k // 2), cfg=200)
+    if xtype == "bf16":
+        x = synth.to_bf16_bits(x)
+    return x, synth.init_centroids(x, k, seed)
+
+
+def tune(buckets=DEFAULT_BUCKETS, reps=5, rows=None, log=print):
+    import torch
+    from . import _lib
+    ctx = _lib.Context(0, tuned=False)
+    out = []
+    for prec, xtype, d, k, n in buckets:
+        n = rows or n
+        x, c0 = _data(n, d, k, xtype, seed=d * 1000 + k)
+        X = torch.from_numpy(x.view(np.int16) if xtype == "bf16" else x).to("cuda")
+        C = torch.from_numpy(c0).to("cuda")
+        times = []
+        for sh in range(SHAPES):
+            ctx.set_tile_shape(prec, xtype, d, k, sh)
+            _lib.kmeans_g(X, C, prec=prec, ctx=ctx)          # warm-up (workspace, code load)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                _lib.kmeans_g(X, C, prec=prec, ctx=ctx)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) * 1e3 / reps)
+        best = int(np.argmin(times))
+        ctx.set_tile_shape(prec, xtype, d, k, 0)
+        out.append({"prec": prec, "xtype": xtype, "d": d, "K": k, "rows": n, "shape": best,
+                    "us_per_g": [round(t, 1) for t in times]})
+        log(json.dumps(out[-1]), flush=True)
+        del X, C
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--rows", type=int, default=None)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args()
+    t0 = time.time()
+    entries = tune(reps=a.reps, rows=a.rows)
+    doc = {"device": "MI355X (gfx950)", "what": "fastest assignment tile shape per bucket, timed as "
+           "whole kmeans_g calls", "seconds": round(time.time() - t0, 1), "entries": entries}
+    with open(a.out, "w") as f:
+        json.dump(doc, f, indent=1)
+    print("wrote", a.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -601,9 +601,9 @@ void collect(km_engine* e) {
 
 extern "C" {
 
-int64_t km_job_workspace_bytes(const km_job* job, int32_t m_max, km_prec prec) {
+int64_t km_job_workspace_bytes(const km_job* job, int32_t m_max) {
   if (!job || job->N < 1 || job->d < 1 || job->K < 1 || m_max < 0 || m_max > KM_M_MAX_LIMIT) return -1;
-  return (int64_t)ws_layout(job_shape(*job, m_max, prec == KM_GEMM_BF16), nullptr, nullptr);
+  return (int64_t)ws_layout(job_shape(*job, m_max, job->prec == KM_GEMM_BF16), nullptr, nullptr);
 }
 
 km_status km_engine_create(km_ctx* c, int32_t m_max, double tol, const km_opts* opt_in, int64_t hbm_budget,
@@ -618,7 +618,6 @@ km_status km_engine_create(km_ctx* c, int32_t m_max, double tol, const km_opts* 
   if (!(opt.ridge >= 0.0) || !isfinite(opt.ridge) || !isfinite(opt.eps1) || !isfinite(opt.eps2))
     return fail(c, KM_EINVAL, "eps1, eps2 and ridge must be finite (ridge >= 0)");
   if (opt.trace_C || opt.trace_rec) return fail(c, KM_EINVAL, "the engine does not trace");
-  if (opt.prec != KM_GEMM_F32 && opt.prec != KM_GEMM_BF16) return fail(c, KM_EINVAL, "unknown precision");
   if (hbm_budget < 0) return fail(c, KM_EINVAL, "hbm_budget must be >= 0");
   if (hipSetDevice(c->device) != hipSuccess) return hip_fail(c, hipGetLastError(), "hipSetDevice");
   km_engine* e = new km_engine();
@@ -669,7 +668,7 @@ void km_engine_destroy(km_engine* e) {
 km_status km_engine_submit(km_engine* e, const km_job* job, int64_t* ticket) {
   if (!e || !job) return KM_EINVAL;
   km_ctx* c = e->ctx;
-  km_status s = check_common(c, job->X, job->xt, job->N, job->d, job->K, e->opt.prec);
+  km_status s = check_common(c, job->X, job->xt, job->N, job->d, job->K, job->prec);
   if (s != KM_OK) return s;
   if (!is_device_ptr(job->C0) || !is_device_ptr(job->C_out) || !is_device_ptr(job->rho_out))
     return fail(c, KM_EINVAL, "C0, C_out and rho_out must be device pointers");
@@ -681,7 +680,7 @@ km_status km_engine_submit(km_engine* e, const km_job* job, int64_t* ticket) {
       overlap(job->rho_out, (size_t)job->N * 4, job->C_out, cbytes) ||
       overlap(job->rho_out, (size_t)job->N * 4, job->C0, cbytes))
     return fail(c, KM_EINVAL, "outputs must not alias X or each other");
-  const bool gbf = e->opt.prec == KM_GEMM_BF16;
+  const bool gbf = job->prec == KM_GEMM_BF16;
   Job* j = new Job();
   j->spec = *job;
   j->ticket = e->next_ticket;

@@ -137,3 +137,30 @@ def init_centroids(x: np.ndarray, k: int, seed: int) -> np.ndarray:
     if rows.dtype == np.uint16:
         rows = bf16_bits_to_f32(rows)
     return np.ascontiguousarray(rows, dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------
+# On-device generation for the batched and served streams (torch generator;
+# the law of plain_large, drawn on the GPU so that thousands of instances
+# cost milliseconds each)
+# ---------------------------------------------------------------------------
+
+def device_instance(n: int, d: int, k: int, seed: int, device="cuda", bf16: bool = False):
+    """(X, C0) on ``device``: a k-component mixture with centres N(0, 25 I),
+    per-component per-dimension std U[0.5, 2], Dirichlet(1) weights; X float32,
+    or bfloat16 stored as int16 bit patterns (round to nearest even); C0 = k
+    distinct rows of X as float32."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(SEED_BASE * 7919 + int(seed))
+    centers = 5.0 * torch.randn(k, d, generator=g, device=device)
+    stds = 0.5 + 1.5 * torch.rand(k, d, generator=g, device=device)
+    w = -torch.log(torch.rand(k, generator=g, device=device).clamp_min(1e-30))   # Gamma(1) draws
+    z = torch.multinomial(w / w.sum(), n, replacement=True, generator=g)
+    x = centers[z] + stds[z] * torch.randn(n, d, generator=g, device=device)
+    idx = torch.randperm(n, generator=g, device=device)[:k]
+    if bf16:
+        xb = x.to(torch.bfloat16)
+        c0 = xb[idx].to(torch.float32).contiguous()
+        return xb.view(torch.int16).contiguous(), c0
+    return x.contiguous(), x[idx].contiguous()

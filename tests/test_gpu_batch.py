@@ -179,3 +179,14 @@ def test_engine_rejects_bad_jobs():
         eng.submit(X, dev(np.zeros((600, 3), np.float32)))   # K > N
     assert e.value.status == -1
     eng.close()
+
+
+def test_batch_mixed_precisions():
+    """float32 and bfloat16 GEMM jobs in one batch, each equal to its solo solve."""
+    km = _lib()
+    p32 = _problems([(3000, 16, 30), (2500, 64, 50)], seed0=400)
+    p16 = _problems([(3500, 16, 25), (2000, 64, 64)], seed0=410, bf16=True)
+    items = [(x_tensor(x), dev(c), "f32") for x, c in p32] + [(x_tensor(x), dev(c), "bf16") for x, c in p16]
+    out = km.kmeans_solve_batch(items, m_max=10, tol=1e-6)
+    for (X, C0, prec), b in zip(items, out):
+        _same(_solo(km, X, C0, m_max=10, tol=1e-6, prec=prec), b)
