@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--instances", type=int, default=512, help="batched: number of instances")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
+    ap.add_argument("--engines", type=int, choices=[1, 2], default=1,
+                    help="served: one engine for all jobs, or one per size class (large jobs on "
+                         "3/4 of the assignment workgroups)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -311,8 +314,10 @@ def served_workload(args, km, synth, torch):
     """Poisson arrivals (rate per second, for `duration` seconds) of jobs
     sized like the batched mix, plus 2 % large jobs (N=2e6, d=96, K=2048,
     bfloat16 X, bfloat16 GEMM).  Each job's data is generated on the device
-    when it arrives (excluded from its latency); the engine admits jobs
-    under a 200 GB workspace budget while others run.  The baseline runs
+    when it arrives (excluded from its latency); the engine (or, with
+    --engines 2, one per size class, large jobs on at most 3/4 of the
+    assignment workgroups) admits jobs under a 200 GB workspace budget while
+    others run, stepped without blocking from one host loop.  The baseline runs
     the same jobs through a FIFO loop of float32 kmeans_solve calls, one at
     a time, with latency = finish - arrival."""
     rng = np.random.default_rng([180510638, 5, 0])
@@ -334,14 +339,33 @@ def served_workload(args, km, synth, torch):
 
     ctx = km.Context(0)
     kw = dict(m_max=10, tol=1e-6, max_iter=500)
-    eng = km.Engine(hbm_budget=200 * 10**9, graphs=False, ctx=ctx, **kw)
-    warm = min(3, n)                                # warm-up jobs, not timed
-    for i in range(warm):
-        X, C0 = make(i)
-        eng.submit(X, C0, prec="bf16" if spec[i][3] else "f32")
+    # two size classes, each its own engine and stream: large bfloat16 jobs
+    # take at most 3/4 of the assignment workgroups so small jobs keep moving
+    budget = 200 * 10**9
+    if args.engines == 2:
+        eng_s = km.Engine(hbm_budget=budget // 4, graphs=False, ctx=ctx, **kw)
+        eng_l = km.Engine(hbm_budget=budget - budget // 4, graphs=False, ctx=ctx, prec="bf16", **kw)
+        eng_l.set_share(0.75)
+        engines = (eng_s, eng_l)
+    else:
+        eng_s = eng_l = km.Engine(hbm_budget=budget, graphs=False, ctx=ctx, **kw)
+        engines = (eng_s,)
+
+    def route(i):
+        return eng_l if spec[i][3] else eng_s
+
+    warm = 0                                        # warm-up jobs, not timed
+    for i in range(n):
+        if warm == 3:
+            break
+        if i < 2 or spec[i][3]:
+            X, C0 = make(i)
+            route(i).submit(X, C0, prec="bf16" if spec[i][3] else "f32")
+            warm += 1
     while warm > 0:
-        eng.step()
-        warm -= len(eng.poll())
+        for e in engines:
+            e.step()
+            warm -= len(e.poll())
 
     lat, lag, lat_large = [], [], []
     t_sub = {}
@@ -351,22 +375,27 @@ def served_workload(args, km, synth, torch):
         now = time.perf_counter() - t_start
         while i < n and arrivals[i] <= now:
             X, C0 = make(i)
-            tk = eng.submit(X, C0, prec="bf16" if spec[i][3] else "f32")
-            t_sub[tk] = (i, time.perf_counter())
+            e = route(i)
+            tk = e.submit(X, C0, prec="bf16" if spec[i][3] else "f32")
+            t_sub[(id(e), tk)] = (i, time.perf_counter())
             lag.append(time.perf_counter() - t_start - arrivals[i])
             i += 1
-        a, q, _ = eng.step()
-        for tk, C, rho, res in eng.poll():
-            j, ts = t_sub.pop(tk)
-            dt = (time.perf_counter() - ts) * 1e3
-            lat.append(dt)
-            if spec[j][3]:
-                lat_large.append(dt)
-            done += 1
-        if a == 0 and q == 0 and i < n:
+        busy = 0
+        for e in engines:
+            a, q, _ = e.step(wait=False)
+            busy += a + q
+            for tk, C, rho, res in e.poll():
+                j, ts = t_sub.pop((id(e), tk))
+                dt = (time.perf_counter() - ts) * 1e3
+                lat.append(dt)
+                if spec[j][3]:
+                    lat_large.append(dt)
+                done += 1
+        if busy == 0 and i < n:
             time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t_start))))
     t_served = time.perf_counter() - t_start
-    eng.close()
+    for e in engines:
+        e.close()
 
     # FIFO baseline: float32 GEMM, one job at a time, in arrival order
     fin = 0.0
@@ -394,7 +423,7 @@ def served_workload(args, km, synth, torch):
         "value": n / t_served, "unit": "solves/s", "n_gpus": 1, "data": "synthetic",
         "config": {"workload": f"Poisson {args.rate:g} jobs/s for {args.duration:g} s; sizes as the batched "
                                "mix, 2% large (N=2e6 d=96 K=2048 bfloat16 X, bfloat16 GEMM); HBM budget 200 GB",
-                   "jobs": n, "large_jobs": int(large.sum())},
+                   "jobs": n, "large_jobs": int(large.sum()), "engines": args.engines},
         "served": {"solves_per_s": n / t_served, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
                    "large_p50_ms": pct(lat_large, 50), "mean_submit_lag_ms": 1e3 * statistics.mean(lag)},
         "fifo_f32": {"solves_per_s": n / fin, "p50_ms": pct(base_lat, 50), "p99_ms": pct(base_lat, 99),

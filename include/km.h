@@ -226,9 +226,19 @@ int64_t km_job_workspace_bytes(const km_job *job, int32_t m_max);
 km_status km_engine_submit(km_engine *e, const km_job *job, int64_t *ticket);
 
 /* Admit queued jobs that fit (at iteration boundaries), launch one
- * iteration of every active job, collect finished ones.  Any count pointer
- * may be NULL: jobs on the device, waiting for admission, results ready. */
-km_status km_engine_step(km_engine *e, int32_t *n_active, int32_t *n_queued, int32_t *n_ready);
+ * iteration of every active job when fewer than three are in flight, and
+ * collect the iterations that have completed.  wait = 1: if nothing could
+ * be launched or collected, block until the oldest iteration in flight
+ * completes; wait = 0 never blocks except while the job set changes (the
+ * engine then drains its own stream).  Any count pointer may be NULL: jobs
+ * on the device, waiting for admission, results ready. */
+km_status km_engine_step(km_engine *e, int32_t wait, int32_t *n_active, int32_t *n_queued, int32_t *n_ready);
+
+/* Fraction (0, 1] of the device's resident assignment workgroups this
+ * engine's launches may take (1: all, and twice as many for balance).
+ * Below 1 the rest of the device stays free for work on other streams,
+ * e.g. a second engine serving small jobs while this one serves large ones. */
+km_status km_engine_set_share(km_engine *e, double frac);
 
 /* 1 and *res filled if a finished job's result was taken (oldest first), 0 if none. */
 int32_t km_engine_poll(km_engine *e, km_job_result *res);

@@ -137,7 +137,9 @@ def load_library(path: str | None = None):
     lib.km_engine_destroy.restype = None
     lib.km_engine_submit.argtypes = [vp, ct.POINTER(_Job), ct.POINTER(ct.c_int64)]
     lib.km_engine_submit.restype = ct.c_int
-    lib.km_engine_step.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
+    lib.km_engine_step.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
+    lib.km_engine_set_share.argtypes = [vp, dbl]
+    lib.km_engine_set_share.restype = ct.c_int
     lib.km_engine_step.restype = ct.c_int
     lib.km_engine_poll.argtypes = [vp, ct.POINTER(_JobResult)]
     lib.km_engine_poll.restype = i32
@@ -438,11 +440,16 @@ class Engine:
         self._jobs[t.value] = keep
         return t.value
 
-    def step(self):
+    def step(self, wait: bool = True):
+        """Admit, launch, collect (see km_engine_step); returns (active, queued, ready)."""
         a, q, r = ct.c_int32(), ct.c_int32(), ct.c_int32()
-        st = self.lib.km_engine_step(self.h, ct.byref(a), ct.byref(q), ct.byref(r))
+        st = self.lib.km_engine_step(self.h, 1 if wait else 0, ct.byref(a), ct.byref(q), ct.byref(r))
         self.ctx._check(st, "km_engine_step")
         return a.value, q.value, r.value
+
+    def set_share(self, frac: float):
+        """Fraction of the device's resident assignment workgroups to use."""
+        self.ctx._check(self.lib.km_engine_set_share(self.h, frac), "km_engine_set_share")
 
     def poll(self):
         out = []

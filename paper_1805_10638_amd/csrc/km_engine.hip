@@ -101,15 +101,18 @@ struct km_engine {
   size_t o_k1 = 0, o_k2 = 0, o_u = 0, o_upre[4] = {}, o_fi = 0, o_fpre = 0, o_cb = 0, o_cpre = 0, o_ctls = 0;
   int ublocks[4] = {}, fblocks = 0, cblocks = 0, n_it = 0;
 
-  // done flags, two slots of n_it ints (pinned) and the device gather buffer
+  // Up to kSlots iterations in flight, each with its slot of done flags
+  // (pinned), its poll event and its graph.
+  static constexpr int kSlots = 3;
   int* hdone = nullptr;
   int* ddone = nullptr;
   size_t done_cap = 0;
-  hipEvent_t poll_ev[2] = {nullptr, nullptr};
-  std::deque<int> inflight;      // parities of launched, unharvested iterations
-  int parity = 0;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipEvent_t poll_ev[kSlots] = {};
+  std::deque<int> inflight;      // slots of launched, unharvested iterations
+  int slot = 0;
+  hipGraphExec_t gexec[kSlots] = {};
   int64_t iterations = 0;
+  double share = 1.0;            // fraction of resident assignment workgroups to use
 };
 
 namespace {
@@ -156,8 +159,10 @@ Shape job_shape(const km_job& j, int m_max, bool gbf) {
 
 // Workgroups of each job's assignment pass: a share of the device's resident
 // workgroups for that kernel proportional to the job's work (rows x padded
-// K), at least one, at most its row groups.
-void size_assignment(const std::vector<Job*>& jobs) {
+// K), at least one, at most its row groups.  With frac = 1 the launches ask
+// for twice the resident workgroups (balance); with frac < 1 for that
+// fraction of them, leaving the rest of the device to other streams.
+void size_assignment(const std::vector<Job*>& jobs, double frac) {
   struct Acc { double work = 0.0; int64_t cap = 0; };
   std::vector<std::pair<const void*, Acc>> acc;
   auto find = [&](const void* fn) -> Acc& {
@@ -174,7 +179,8 @@ void size_assignment(const std::vector<Job*>& jobs) {
     const Acc& a = find(j->pick.fn);
     const int64_t groups = (j->spec.N + j->pick.rows - 1) / j->pick.rows;
     const double share = (double)j->spec.N * (double)((j->spec.K + 15) & ~15) / a.work;
-    int64_t b = (int64_t)(2.0 * (double)a.cap * share + 0.5);
+    const double total = frac >= 1.0 ? 2.0 * (double)a.cap : frac * (double)a.cap;
+    int64_t b = (int64_t)(total * share + 0.5);
     if (b < 1) b = 1;
     if (b > groups) b = groups;
     j->assign_blocks = (int)b;
@@ -387,7 +393,7 @@ km_status rebuild(km_engine* e) {
   }
   std::vector<Job*> all = e->active;
   all.insert(all.end(), admitted.begin(), admitted.end());
-  size_assignment(all);
+  size_assignment(all, e->share);
 
   Packer pk;
   // ---- prologue tables of the admitted jobs ----
@@ -485,7 +491,8 @@ km_status rebuild(km_engine* e) {
     e->hdone = nullptr;
     e->ddone = nullptr;
     size_t cap = std::max<size_t>(e->n_it * 2, 64);
-    ENG_TRY(e, hipHostMalloc((void**)&e->hdone, 2 * cap * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+    ENG_TRY(e, hipHostMalloc((void**)&e->hdone, km_engine::kSlots * cap * sizeof(int), hipHostMallocDefault),
+            "hipHostMalloc");
     ENG_TRY(e, hipMalloc((void**)&e->ddone, cap * sizeof(int)), "hipMalloc");
     e->done_cap = cap;
   }
@@ -521,7 +528,7 @@ km_status rebuild(km_engine* e) {
 
   // ---- iteration graphs ----
   if (e->graphs && e->n_it > 0) {
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < km_engine::kSlots; ++p) {
       hipGraph_t g = nullptr;
       ENG_TRY(e, hipStreamBeginCapture(q, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
       km_status es = enqueue_iteration(e, p);
@@ -537,7 +544,7 @@ km_status rebuild(km_engine* e) {
   return KM_OK;
 }
 
-// Results of iteration with parity p: start the finishing copies of newly
+// Results of the iteration in slot p: start the finishing copies of newly
 // finished jobs.
 km_status harvest(km_engine* e, int p) {
   ENG_TRY(e, hipEventSynchronize(e->poll_ev[p]), "hipEventSynchronize");
@@ -627,9 +634,9 @@ km_status km_engine_create(km_ctx* c, int32_t m_max, double tol, const km_opts* 
   e->opt = opt;
   e->budget = hbm_budget;
   e->graphs = graphs != 0;
-  bool ok = hipStreamCreateWithFlags(&e->q, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&e->poll_ev[0], hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&e->poll_ev[1], hipEventDisableTiming) == hipSuccess;
+  bool ok = hipStreamCreateWithFlags(&e->q, hipStreamNonBlocking) == hipSuccess;
+  for (int k = 0; k < km_engine::kSlots && ok; ++k)
+    ok = hipEventCreateWithFlags(&e->poll_ev[k], hipEventDisableTiming) == hipSuccess;
   if (ok) {  // order the engine after work already on the context's stream
     ok = hipEventRecord(c->enter, c->stream) == hipSuccess && hipStreamWaitEvent(e->q, c->enter, 0) == hipSuccess;
   }
@@ -713,7 +720,14 @@ km_status km_engine_submit(km_engine* e, const km_job* job, int64_t* ticket) {
   return KM_OK;
 }
 
-km_status km_engine_step(km_engine* e, int32_t* n_active, int32_t* n_queued, int32_t* n_ready) {
+km_status km_engine_set_share(km_engine* e, double frac) {
+  if (!e || !(frac > 0.0) || frac > 1.0) return KM_EINVAL;
+  e->share = frac;
+  e->change = true;   // grids are sized at the next rebuild
+  return KM_OK;
+}
+
+km_status km_engine_step(km_engine* e, int32_t wait, int32_t* n_active, int32_t* n_queued, int32_t* n_ready) {
   if (!e) return KM_EINVAL;
   km_ctx* c = e->ctx;
   c->err.clear();
@@ -731,23 +745,39 @@ km_status km_engine_step(km_engine* e, int32_t* n_active, int32_t* n_queued, int
   }
   bool live = false;
   for (Job* j : e->active) live |= !j->done_dev;
-  if (live) {
-    const int p = e->parity;
-    e->parity ^= 1;
+  bool progressed = false;
+  if (live && !e->change && (int)e->inflight.size() < km_engine::kSlots) {
+    const int p = e->slot;
+    e->slot = (e->slot + 1) % km_engine::kSlots;
     if (e->graphs) ENG_TRY(e, hipGraphLaunch(e->gexec[p], e->q), "hipGraphLaunch");
     else if ((s = enqueue_iteration(e, p)) != KM_OK) return s;
     ENG_TRY(e, hipEventRecord(e->poll_ev[p], e->q), "hipEventRecord");
     e->inflight.push_back(p);
     ++e->iterations;
+    progressed = true;
   }
-  // keep one iteration in flight while the previous one is inspected
-  while (e->inflight.size() > (live ? 1u : 0u)) {
+  // collect completed iterations without waiting
+  while (!e->inflight.empty() && !e->change) {
+    const hipError_t qe = hipEventQuery(e->poll_ev[e->inflight.front()]);
+    if (qe == hipErrorNotReady) {
+      clear_pending_error();
+      break;
+    }
+    if (qe != hipSuccess) return hip_fail(c, qe, "hipEventQuery");
+    s = harvest(e, e->inflight.front());
+    if (s != KM_OK) return s;
+    e->inflight.pop_front();
+    progressed = true;
+  }
+  if (wait && !progressed && !e->inflight.empty()) {
     s = harvest(e, e->inflight.front());
     if (s != KM_OK) return s;
     e->inflight.pop_front();
   }
-  if (!live && e->inflight.empty() && (!e->queued.empty() || !e->active.empty())) e->change = true;
-  if (!live && e->inflight.empty()) ENG_TRY(e, hipStreamSynchronize(e->q), "hipStreamSynchronize");
+  if (!live && e->inflight.empty()) {
+    if (!e->queued.empty() || !e->active.empty()) e->change = true;
+    ENG_TRY(e, hipStreamSynchronize(e->q), "hipStreamSynchronize");
+  }
   collect(e);
   int act = 0;
   for (Job* j : e->active) act += j->state == kActive;
@@ -780,7 +810,7 @@ km_status kmeans_solve_batch(km_ctx* c, const km_job* jobs, int32_t n, int32_t m
   int got = 0;
   while (s == KM_OK && got < n) {
     int32_t na = 0, nq = 0, nr = 0;
-    s = km_engine_step(e, &na, &nq, &nr);
+    s = km_engine_step(e, 1, &na, &nq, &nr);
     km_job_result r;
     while (s == KM_OK && km_engine_poll(e, &r)) {
       res[r.ticket] = r;

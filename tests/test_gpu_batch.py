@@ -190,3 +190,35 @@ def test_batch_mixed_precisions():
     out = km.kmeans_solve_batch(items, m_max=10, tol=1e-6)
     for (X, C0, prec), b in zip(items, out):
         _same(_solo(km, X, C0, m_max=10, tol=1e-6, prec=prec), b)
+
+
+def test_two_engines_concurrently():
+    """Two engines on their own streams (one restricted to part of the
+    device) stepped without blocking: every result equals its solo solve."""
+    km = _lib()
+    ps = _problems([(4000, 16, 20), (3000, 3, 40), (5000, 64, 30)], seed0=500)
+    pl = _problems([(20000, 64, 256)], seed0=510, bf16=True)
+    small = [(x_tensor(x), dev(c)) for x, c in ps]
+    large = [(x_tensor(x), dev(c)) for x, c in pl]
+    es = km.Engine(m_max=10, tol=1e-6)
+    el = km.Engine(m_max=10, tol=1e-6, prec="bf16")
+    el.set_share(0.5)
+    ts = {es.submit(X, C0): i for i, (X, C0) in enumerate(small)}
+    tl = {el.submit(X, C0): i for i, (X, C0) in enumerate(large)}
+    gs, gl = {}, {}
+    for _ in range(20000):
+        es.step(wait=False)
+        el.step(wait=False)
+        for t, C, rho, res in es.poll():
+            gs[ts[t]] = (C, rho, res)
+        for t, C, rho, res in el.poll():
+            gl[tl[t]] = (C, rho, res)
+        if len(gs) == len(small) and len(gl) == len(large):
+            break
+    es.close()
+    el.close()
+    assert len(gs) == len(small) and len(gl) == len(large)
+    for i, (X, C0) in enumerate(small):
+        _same(_solo(km, X, C0, m_max=10, tol=1e-6), gs[i])
+    for i, (X, C0) in enumerate(large):
+        _same(_solo(km, X, C0, m_max=10, tol=1e-6, prec="bf16"), gl[i])
