@@ -30,7 +30,7 @@ WORKLOAD = dict(N=1_000_000, d=32, K=256, m_max=10, tol=1e-6, max_iter=500)
 # WRITE_SIZE, each scaled by its reading for a plain copy of known size
 # (profiles/assign_f32_N1M_d32_K256_traffic.md).  Set to None when the kernel
 # changes until it is measured again.
-TRAFFIC_BYTES_PER_LAUNCH = 136784244
+TRAFFIC_BYTES_PER_LAUNCH = 136249831
 
 
 def parse():
@@ -41,11 +41,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time budget of the oracle baseline sample")
-    ap.add_argument("--workload", choices=["plain", "precision", "batched", "served"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "precision", "batched", "served", "studies"],
+                    default="plain",
                     help="plain: N=1e6 d=32 K=256 float32 (default line); precision: "
                          "N=4e6 d=128 K=1024 bfloat16-stored X, float32 vs bfloat16 GEMM; batched: "
                          "512 uneven instances in one engine vs one at a time; served: Poisson arrivals "
-                         "(200 jobs/s) through the continuous-batching engine vs a FIFO loop")
+                         "(200 jobs/s) through the continuous-batching engine vs a FIFO loop; studies: fixed vs "
+                         "dynamic m and Lloyd vs Anderson on synthetic mixtures")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of instances")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
@@ -115,6 +117,9 @@ def main():
         return
     if args.workload == "served":
         served_workload(args, km, synth, torch)
+        return
+    if args.workload == "studies":
+        studies_workload(args, km, synth, torch)
         return
 
     w = WORKLOAD
@@ -429,6 +434,77 @@ def served_workload(args, km, synth, torch):
         "fifo_f32": {"solves_per_s": n / fin, "p50_ms": pct(base_lat, 50), "p99_ms": pct(base_lat, 99),
                      "busy_s": busy},
     }), flush=True)
+
+
+STUDY_SETS = [  # (name, N, d, mixture components)
+    ("mix2d", 200_000, 2, 50), ("mix8d", 1_000_000, 8, 128), ("mix16d", 200_000, 16, 64),
+    ("mix32d", 500_000, 32, 256), ("mix64d", 200_000, 64, 32), ("mix128d", 200_000, 128, 64),
+]
+
+
+def studies_workload(args, km, synth, torch):
+    """Synthetic analogues of the paper's two experiments (its datasets are
+    not available): (1) fixed m vs dynamic m with m initialised to 2 and 5,
+    m_max = 30, eps1 = 0.02, eps2 = 0.5 (Sec. 3.1), reporting time and
+    accepted/total iterations; (2) Lloyd vs Anderson (dynamic m) for K = 10,
+    100, 1000 from the same random-sample initialisation, reporting
+    iterations, time and final mean squared error (Sec. 3.2).  Both run to
+    convergence (tol = 0: no assignment changes, as the paper does) and with
+    the benchmark's stopping rule (tol = 1e-6 relative energy change).
+    Times are whole GPU solves (median of 3)."""
+    for tol in (0.0, 1e-6):
+        _studies(args, km, synth, torch, tol)
+
+
+def _studies(args, km, synth, torch, tol):
+    ctx = km.Context(0)
+    data = [(name, *synth.device_instance(n, d, comps, seed=7 + i)) for i, (name, n, d, comps) in
+            enumerate(STUDY_SETS)]
+    torch.cuda.synchronize()
+
+    def run(X, C0, **kw):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, E, it, st = km.kmeans_solve(X, C0, ctx=ctx, max_iter=500, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return {"ms": 1e3 * statistics.median(ts), "iters": it, "accepted": st.accepted, "E": E}
+
+    km.kmeans_solve(data[0][1], data[0][1][:10].contiguous(), ctx=ctx, max_iter=5)   # warm-up
+    m_rows = []
+    for i, (name, X, _) in enumerate(data):
+        K = STUDY_SETS[i][3]
+        C0 = X[torch.from_numpy(synth.init_indices(X.shape[0], K, 11 + i)).to(X.device)].contiguous()
+        row = {"set": name, "N": X.shape[0], "d": X.shape[1], "K": K}
+        for m0 in (2, 5):
+            row[f"fixed_m{m0}"] = run(X, C0, m_max=30, m_init=m0, fixed_m=True, tol=tol)
+            row[f"dynamic_m{m0}"] = run(X, C0, m_max=30, m_init=m0, tol=tol)
+        m_rows.append(row)
+        print(json.dumps({"study": "fixed_vs_dynamic_m", "tol": tol, **row}), flush=True)
+    k_rows = []
+    for i, (name, X, _) in enumerate(data):
+        for K in (10, 100, 1000):
+            C0 = X[torch.from_numpy(synth.init_indices(X.shape[0], K, 31 + i)).to(X.device)].contiguous()
+            lloyd = run(X, C0, m_max=0, tol=tol)
+            aa = run(X, C0, m_max=30, m_init=2, tol=tol)
+            # the printed return: stop as soon as any candidate repeats the assignment
+            lit = run(X, C0, m_max=30, m_init=2, tol=tol, literal_return=True)
+            n = X.shape[0]
+            row = {"set": name, "N": n, "d": X.shape[1], "K": K,
+                   "lloyd": {**lloyd, "mse": lloyd["E"] / n}, "aa": {**aa, "mse": aa["E"] / n},
+                   "aa_printed_return": {**lit, "mse": lit["E"] / n},
+                   "time_ratio": aa["ms"] / lloyd["ms"], "time_ratio_printed_return": lit["ms"] / lloyd["ms"]}
+            k_rows.append(row)
+            print(json.dumps({"study": "lloyd_vs_aa", "tol": tol, **row}), flush=True)
+    wins = sum(1 for r in k_rows if r["time_ratio"] < 1.0)
+    wins_lit = sum(1 for r in k_rows if r["time_ratio_printed_return"] < 1.0)
+    dyn_better = sum(1 for r in m_rows for m0 in (2, 5) if r[f"dynamic_m{m0}"]["ms"] < r[f"fixed_m{m0}"]["ms"])
+    print(json.dumps({"study": "summary", "tol": tol, "aa_faster_than_lloyd": f"{wins}/{len(k_rows)}",
+                      "aa_printed_return_faster_than_lloyd": f"{wins_lit}/{len(k_rows)}",
+                      "mean_time_ratio_aa_over_lloyd": statistics.mean(r["time_ratio"] for r in k_rows),
+                      "dynamic_faster_than_fixed": f"{dyn_better}/{2 * len(m_rows)}"}), flush=True)
 
 
 if __name__ == "__main__":

@@ -88,9 +88,21 @@ struct km_engine {
   std::deque<Job*> ready;
   bool change = true;            // membership must be rebuilt before the next launch
 
-  // device tables of the active set (and the prologue of newly admitted jobs)
-  char* dtab = nullptr;
-  size_t dtab_cap = 0;
+  // Device tables of the active set (and the prologue of newly admitted
+  // jobs).  Two buffers alternate so that new tables can be uploaded while
+  // iterations that read the previous ones are still in flight; tab_ev[k]
+  // marks the end of the work that used buffer k.  Each has a pinned
+  // staging buffer for the asynchronous upload.
+  char* dtab = nullptr;          // current buffer
+  char* dbuf[2] = {nullptr, nullptr};
+  size_t dcap[2] = {0, 0};
+  char* stage[2] = {nullptr, nullptr};
+  size_t scap[2] = {0, 0};
+  hipEvent_t tab_ev[2] = {nullptr, nullptr};
+  int cur = 0;
+  std::vector<hipGraphExec_t> old_graphs;   // replaced while possibly in flight
+  int64_t drains = 0, appends = 0;
+  double rebuild_ms = 0.0;
   struct Bucket {
     KernelPick pick;
     size_t o_cand = 0, o_fb = 0, o_pre = 0;
@@ -108,7 +120,7 @@ struct km_engine {
   int* ddone = nullptr;
   size_t done_cap = 0;
   hipEvent_t poll_ev[kSlots] = {};
-  std::deque<int> inflight;      // slots of launched, unharvested iterations
+  std::deque<std::pair<int, int>> inflight;   // (slot, jobs in its tables) of unharvested iterations
   int slot = 0;
   hipGraphExec_t gexec[kSlots] = {};
   int64_t iterations = 0;
@@ -295,15 +307,30 @@ void add_bucket(std::vector<HostBucket>& bs, const KernelPick& p, const AssignAr
   hb->lds = std::max(hb->lds, p.lds);
 }
 
+// Upload new tables into the other buffer, after the work that last used it.
 km_status upload(km_engine* e, const Packer& pk) {
-  if (pk.buf.size() > e->dtab_cap) {
-    if (e->dtab) ENG_TRY(e, hipFree(e->dtab), "hipFree");
-    e->dtab = nullptr;
-    size_t cap = std::max<size_t>(pk.buf.size() * 2, 1 << 16);
-    ENG_TRY(e, hipMalloc((void**)&e->dtab, cap), "hipMalloc");
-    e->dtab_cap = cap;
+  const int k = e->cur ^ 1;
+  ENG_TRY(e, hipEventRecord(e->tab_ev[e->cur], e->q), "hipEventRecord");
+  ENG_TRY(e, hipEventSynchronize(e->tab_ev[k]), "hipEventSynchronize");
+  const size_t need = pk.buf.size();
+  if (need > e->dcap[k]) {
+    if (e->dbuf[k]) ENG_TRY(e, hipFree(e->dbuf[k]), "hipFree");
+    e->dbuf[k] = nullptr;
+    const size_t cap = std::max<size_t>(need * 2, 1 << 20);
+    ENG_TRY(e, hipMalloc((void**)&e->dbuf[k], cap), "hipMalloc");
+    e->dcap[k] = cap;
   }
-  ENG_TRY(e, hipMemcpy(e->dtab, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice), "hipMemcpy");
+  if (need > e->scap[k]) {
+    if (e->stage[k]) ENG_TRY(e, hipHostFree(e->stage[k]), "hipHostFree");
+    e->stage[k] = nullptr;
+    const size_t cap = std::max<size_t>(need * 2, 1 << 20);
+    ENG_TRY(e, hipHostMalloc((void**)&e->stage[k], cap, hipHostMallocDefault), "hipHostMalloc");
+    e->scap[k] = cap;
+  }
+  memcpy(e->stage[k], pk.buf.data(), need);
+  ENG_TRY(e, hipMemcpyAsync(e->dbuf[k], e->stage[k], need, hipMemcpyHostToDevice, e->q), "table upload");
+  e->cur = k;
+  e->dtab = e->dbuf[k];
   return KM_OK;
 }
 
@@ -344,28 +371,38 @@ void drop_graphs(km_engine* e) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
+  for (hipGraphExec_t g : e->old_graphs) (void)hipGraphExecDestroy(g);
+  e->old_graphs.clear();
 }
 
-// Drain, retire finished jobs, admit queued ones, run their prologue and
-// rebuild the iteration tables.  Called with nothing in flight.
-km_status rebuild(km_engine* e) {
-  ENG_TRY(e, hipStreamSynchronize(e->q), "hipStreamSynchronize");
-  drop_graphs(e);
-  // retire finished jobs (their finishing copies were enqueued before the drain)
-  std::vector<Job*> keep;
-  for (Job* j : e->active) {
-    if (j->state == kActive) {
-      keep.push_back(j);
-      continue;
+constexpr size_t kDoneCap = 4096;   // jobs in the tables between two drains
+
+// Admit queued jobs, run their prologue and rebuild the iteration tables.
+// drain = true: called with nothing in flight; the stream is drained and
+// finished jobs are retired first.  drain = false: iterations may be in
+// flight; admitted jobs are appended after the current ones (whose table
+// positions stay valid for the iterations in flight) and nothing is freed.
+km_status rebuild(km_engine* e, bool drain) {
+  const double t_in = now_ms();
+  if (drain) {
+    ENG_TRY(e, hipStreamSynchronize(e->q), "hipStreamSynchronize");
+    drop_graphs(e);
+    // retire finished jobs (their finishing copies were enqueued before the drain)
+    std::vector<Job*> keep;
+    for (Job* j : e->active) {
+      if (j->state == kActive) {
+        keep.push_back(j);
+        continue;
+      }
+      if (j->mem) {
+        ENG_TRY(e, hipFreeAsync(j->mem, e->q), "hipFreeAsync");
+        j->mem = nullptr;
+        e->used -= (int64_t)j->bytes;
+      }
+      if (j->taken) free_job(j);
     }
-    if (j->mem) {
-      ENG_TRY(e, hipFreeAsync(j->mem, e->q), "hipFreeAsync");
-      j->mem = nullptr;
-      e->used -= (int64_t)j->bytes;
-    }
-    if (j->taken) free_job(j);
+    e->active.swap(keep);
   }
-  e->active.swap(keep);
   if (!e->queued.empty()) {  // job inputs come from work on the context's stream
     km_ctx* c = e->ctx;
     ENG_TRY(e, hipEventRecord(c->enter, c->stream), "hipEventRecord");
@@ -373,7 +410,7 @@ km_status rebuild(km_engine* e) {
   }
   // admission in submission order while the workspace fits
   std::vector<Job*> admitted;
-  while (!e->queued.empty()) {
+  while (!e->queued.empty() && e->active.size() + admitted.size() < kDoneCap) {
     Job* j = e->queued.front();
     if (e->budget > 0 && e->used + (int64_t)j->bytes > e->budget) break;
     e->queued.pop_front();
@@ -391,6 +428,7 @@ km_status rebuild(km_engine* e) {
     j->state = kActive;
     admitted.push_back(j);
   }
+  if (!drain && admitted.empty()) return KM_OK;
   std::vector<Job*> all = e->active;
   all.insert(all.end(), admitted.begin(), admitted.end());
   size_assignment(all, e->share);
@@ -484,17 +522,12 @@ km_status rebuild(km_engine* e) {
   km_status st = upload(e, pk);
   if (st != KM_OK) return st;
 
-  // done-flag buffers
-  if ((size_t)e->n_it > e->done_cap) {
-    if (e->hdone) (void)hipHostFree(e->hdone);
-    if (e->ddone) (void)hipFree(e->ddone);
-    e->hdone = nullptr;
-    e->ddone = nullptr;
-    size_t cap = std::max<size_t>(e->n_it * 2, 64);
-    ENG_TRY(e, hipHostMalloc((void**)&e->hdone, km_engine::kSlots * cap * sizeof(int), hipHostMallocDefault),
+  // done-flag buffers (allocated once, for kDoneCap jobs)
+  if (!e->hdone) {
+    ENG_TRY(e, hipHostMalloc((void**)&e->hdone, km_engine::kSlots * kDoneCap * sizeof(int), hipHostMallocDefault),
             "hipHostMalloc");
-    ENG_TRY(e, hipMalloc((void**)&e->ddone, cap * sizeof(int)), "hipMalloc");
-    e->done_cap = cap;
+    ENG_TRY(e, hipMalloc((void**)&e->ddone, kDoneCap * sizeof(int)), "hipMalloc");
+    e->done_cap = kDoneCap;
   }
 
   // ---- prologue of the admitted jobs ----
@@ -527,6 +560,10 @@ km_status rebuild(km_engine* e) {
   e->active = all;
 
   // ---- iteration graphs ----
+  for (hipGraphExec_t& g : e->gexec) {   // may still be in flight: destroyed at the next drain
+    if (g) e->old_graphs.push_back(g);
+    g = nullptr;
+  }
   if (e->graphs && e->n_it > 0) {
     for (int p = 0; p < km_engine::kSlots; ++p) {
       hipGraph_t g = nullptr;
@@ -540,17 +577,24 @@ km_status rebuild(km_engine* e) {
       if (ee != hipSuccess) return hip_fail(e->ctx, ee, "hipGraphInstantiate");
     }
   }
-  e->change = false;
+  if (drain) {
+    e->change = false;
+    ++e->drains;
+  } else {
+    ++e->appends;
+  }
+  e->rebuild_ms += now_ms() - t_in;
   return KM_OK;
 }
 
-// Results of the iteration in slot p: start the finishing copies of newly
-// finished jobs.
-km_status harvest(km_engine* e, int p) {
+// Results of the iteration in slot p (whose tables held the first n jobs):
+// start the finishing copies of newly finished jobs.
+km_status harvest(km_engine* e, std::pair<int, int> it) {
+  const int p = it.first;
   ENG_TRY(e, hipEventSynchronize(e->poll_ev[p]), "hipEventSynchronize");
   const int* f = e->hdone + (size_t)p * e->done_cap;
   int done_in_tables = 0;
-  for (int i = 0; i < e->n_it; ++i) {
+  for (int i = 0; i < it.second; ++i) {
     Job* j = e->active[i];
     if (f[i] && !j->done_dev) {
       j->done_dev = true;
@@ -568,15 +612,26 @@ km_status harvest(km_engine* e, int p) {
     }
     if (j->done_dev) ++done_in_tables;
   }
+  for (int i = it.second; i < e->n_it; ++i) done_in_tables += e->active[i]->done_dev ? 1 : 0;
   const int live = e->n_it - done_in_tables;
-  bool admit = false;
-  if (!e->queued.empty()) {
+  // a queued job that fits only once finished jobs are freed needs a drain
+  bool admit_after_free = false;
+  if (!e->queued.empty() && e->budget > 0 &&
+      e->used + (int64_t)e->queued.front()->bytes > e->budget) {
     int64_t freed = 0;
     for (Job* j : e->active) if (j->done_dev) freed += (int64_t)j->bytes;
-    admit = e->budget <= 0 || e->used - freed + (int64_t)e->queued.front()->bytes <= e->budget;
+    admit_after_free = e->used - freed + (int64_t)e->queued.front()->bytes <= e->budget;
   }
-  if (live == 0 || admit || (done_in_tables > 0 && done_in_tables * 4 >= e->n_it)) e->change = true;
+  if (live == 0 || admit_after_free || (done_in_tables > 0 && done_in_tables * 4 >= e->n_it) ||
+      (!e->queued.empty() && (size_t)e->n_it >= kDoneCap))
+    e->change = true;
   return KM_OK;
+}
+
+// A queued job can join without a drain.
+bool can_append(const km_engine* e) {
+  if (e->queued.empty() || (size_t)e->active.size() >= kDoneCap) return false;
+  return e->budget <= 0 || e->used + (int64_t)e->queued.front()->bytes <= e->budget;
 }
 
 void collect(km_engine* e) {
@@ -637,6 +692,8 @@ km_status km_engine_create(km_ctx* c, int32_t m_max, double tol, const km_opts* 
   bool ok = hipStreamCreateWithFlags(&e->q, hipStreamNonBlocking) == hipSuccess;
   for (int k = 0; k < km_engine::kSlots && ok; ++k)
     ok = hipEventCreateWithFlags(&e->poll_ev[k], hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; k < 2 && ok; ++k)
+    ok = hipEventCreateWithFlags(&e->tab_ev[k], hipEventDisableTiming) == hipSuccess;
   if (ok) {  // order the engine after work already on the context's stream
     ok = hipEventRecord(c->enter, c->stream) == hipSuccess && hipStreamWaitEvent(e->q, c->enter, 0) == hipSuccess;
   }
@@ -663,7 +720,11 @@ void km_engine_destroy(km_engine* e) {
     if (j->mem) (void)hipFree(j->mem);
     free_job(j);
   }
-  if (e->dtab) (void)hipFree(e->dtab);
+  for (int k = 0; k < 2; ++k) {
+    if (e->dbuf[k]) (void)hipFree(e->dbuf[k]);
+    if (e->stage[k]) (void)hipHostFree(e->stage[k]);
+    if (e->tab_ev[k]) (void)hipEventDestroy(e->tab_ev[k]);
+  }
   if (e->ddone) (void)hipFree(e->ddone);
   if (e->hdone) (void)hipHostFree(e->hdone);
   for (hipEvent_t v : e->poll_ev) if (v) (void)hipEventDestroy(v);
@@ -740,7 +801,10 @@ km_status km_engine_step(km_engine* e, int32_t wait, int32_t* n_active, int32_t*
       if (s != KM_OK) return s;
       e->inflight.pop_front();
     }
-    s = rebuild(e);
+    s = rebuild(e, true);
+    if (s != KM_OK) return s;
+  } else if (can_append(e)) {
+    s = rebuild(e, false);
     if (s != KM_OK) return s;
   }
   bool live = false;
@@ -752,13 +816,13 @@ km_status km_engine_step(km_engine* e, int32_t wait, int32_t* n_active, int32_t*
     if (e->graphs) ENG_TRY(e, hipGraphLaunch(e->gexec[p], e->q), "hipGraphLaunch");
     else if ((s = enqueue_iteration(e, p)) != KM_OK) return s;
     ENG_TRY(e, hipEventRecord(e->poll_ev[p], e->q), "hipEventRecord");
-    e->inflight.push_back(p);
+    e->inflight.push_back({p, e->n_it});
     ++e->iterations;
     progressed = true;
   }
   // collect completed iterations without waiting
   while (!e->inflight.empty() && !e->change) {
-    const hipError_t qe = hipEventQuery(e->poll_ev[e->inflight.front()]);
+    const hipError_t qe = hipEventQuery(e->poll_ev[e->inflight.front().first]);
     if (qe == hipErrorNotReady) {
       clear_pending_error();
       break;
