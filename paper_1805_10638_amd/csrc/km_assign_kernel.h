@@ -201,68 +201,99 @@ struct Tile {
   }
 };
 
-// MFMAs of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk) against
-// the SB sample blocks of this wave; accumulators start at -||c||^2/2.
-// bf16: x.hi + x.lo per slice (and x_lo.hi for float32 rows, XLO).
-template <int KS, int SB, bool GBF, bool XLO, int LB, typename XV>
-__device__ __forceinline__ void tile_mfma(const float* Cs, const uint16_t* Cbs, const float* ncs,
-                                          int tt, int g, int r16, const XV& xv,
-                                          const i16x8 (&xbv)[SB][Tile<KS, GBF, LB>::NB],
-                                          const i16x8 (&xlv)[SB][XLO ? Tile<KS, GBF, LB>::NB : 1],
-                                          f32x4 (&acc)[SB]) {
+// A operand of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk): this
+// lane's centroid row r16, lane group g's dimensions, and the tile's
+// -||c||^2/2 start values.  The tile loop loads the next tile's operand while
+// the current tile's MFMAs run, so the LDS latency is not paid per tile.
+template <int KS, bool GBF, int LB>
+struct AOp {
+  static constexpr int NB = Tile<KS, GBF, LB>::NB;
+  f32x4 n4;
+  i16x8 ah[GBF ? NB : 1], al[GBF ? NB : 1];  // bf16 hi and lo halves
+  float av[GBF ? 1 : KS];                     // float32 row
+};
+
+template <int KS, bool GBF, int LB>
+__device__ __forceinline__ void load_aop(const float* Cs, const uint16_t* Cbs, const float* ncs, int tt,
+                                         int g, int r16, AOp<KS, GBF, LB>& o) {
   using T = Tile<KS, GBF, LB>;
-  const f32x4 n4 = *(const f32x4*)(ncs + tt + 4 * g);
-#pragma unroll
-  for (int s = 0; s < SB; ++s) acc[s] = n4;
+  o.n4 = *(const f32x4*)(ncs + tt + 4 * g);
   if constexpr (GBF) {
-    i16x8 ah[T::NB], al[T::NB];
     const uint16_t* cr = Cbs + (tt + r16) * T::LDB + g * KS;
 #pragma unroll
     for (int q = 0; q < T::NB; ++q) {
-      ah[q] = *(const i16x8*)(cr + 8 * q);
-      al[q] = *(const i16x8*)(cr + T::DP + 8 * q);
-    }
-#pragma unroll
-    for (int q = 0; q < T::NB; ++q) {
-#pragma unroll
-      for (int s = 0; s < SB; ++s)
-        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            __builtin_bit_cast(bf16x8, ah[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
-#pragma unroll
-      for (int s = 0; s < SB; ++s)
-        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            __builtin_bit_cast(bf16x8, al[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
-      if constexpr (XLO) {
-#pragma unroll
-        for (int s = 0; s < SB; ++s)
-          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8, ah[q]), __builtin_bit_cast(bf16x8, xlv[s][q]), acc[s], 0, 0, 0);
-      }
+      o.ah[q] = *(const i16x8*)(cr + 8 * q);
+      o.al[q] = *(const i16x8*)(cr + T::DP + 8 * q);
     }
   } else {
-    float av[KS];
     const float* cr = Cs + (tt + r16) * T::LD + g * KS;
     if constexpr (KS % 4 == 0) {
 #pragma unroll
       for (int q = 0; q < KS; q += 4) {
         const float4 v = *(const float4*)(cr + q);
-        av[q] = v.x; av[q + 1] = v.y; av[q + 2] = v.z; av[q + 3] = v.w;
+        o.av[q] = v.x; o.av[q + 1] = v.y; o.av[q + 2] = v.z; o.av[q + 3] = v.w;
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < KS; ++q) av[q] = cr[q];
+      for (int q = 0; q < KS; ++q) o.av[q] = cr[q];
     }
+  }
+}
+
+// MFMAs of one tile against the SB sample blocks of this wave; accumulators
+// start at -||c||^2/2.  bf16: x.hi + x.lo per slice (and x_lo.hi for float32
+// rows, XLO).
+template <int KS, int SB, bool GBF, bool XLO, int LB, typename XV>
+__device__ __forceinline__ void tile_mfma(const AOp<KS, GBF, LB>& o, const XV& xv,
+                                          const i16x8 (&xbv)[SB][Tile<KS, GBF, LB>::NB],
+                                          const i16x8 (&xlv)[SB][XLO ? Tile<KS, GBF, LB>::NB : 1],
+                                          f32x4 (&acc)[SB]) {
+  using T = Tile<KS, GBF, LB>;
+#pragma unroll
+  for (int s = 0; s < SB; ++s) acc[s] = o.n4;
+  if constexpr (GBF) {
+#pragma unroll
+    for (int q = 0; q < T::NB; ++q) {
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf16x8, o.ah[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf16x8, o.al[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+      if constexpr (XLO) {
+#pragma unroll
+        for (int s = 0; s < SB; ++s)
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, o.ah[q]), __builtin_bit_cast(bf16x8, xlv[s][q]), acc[s], 0, 0, 0);
+      }
+    }
+  } else {
 #pragma unroll
     for (int q = 0; q < KS; ++q)
 #pragma unroll
       for (int s = 0; s < SB; ++s)
-        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], xv[s][q], acc[s], 0, 0, 0);
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.av[q], xv[s][q], acc[s], 0, 0, 0);
   }
 }
 
 // bfloat16 bits -> float32 of element q of a lane's bf16 chunk
 __device__ __forceinline__ float bf_elem(const i16x8& v, int e) {
   return bf16_to_f32((uint16_t)v[e]);
+}
+
+// Waves per SIMD the register allocation must leave room for: 16-wave
+// workgroups need 4; small float32 tiles run best at 4 (latency hiding);
+// wide tiles (float32 rows on the bf16 GEMM, 8 sample blocks, d > 128 in
+// bf16, more than 64 dims x blocks in float32) get the whole register file;
+// the rest run 2 waves per SIMD.
+template <int KS, int SB, int W, bool XBF, bool GBF>
+constexpr int assign_wpe() {
+  if (W >= 16) return 4;
+  if (!GBF) return (KS * SB <= 16 && SB <= 2) ? 4 : (KS * SB > 64 ? 1 : 2);
+  if (!XBF || KS >= 48 || SB >= 8) return 1;
+  return 2;
 }
 
 // KS: padded dims per lane group; SB: 16-sample blocks per wave; W: waves
@@ -338,39 +369,85 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   const float cb = GBF ? cmax * 1.008f : cmax;
 
   // Stage centroid rows [c0, c0 + rows) into LDS (zero padding beyond d and K).
+  // When every vector of a row is real (d = dp), each thread issues
+  // kStageBatch 16-byte loads before it writes any of them, so a chunk costs
+  // a few L2 round trips instead of one per vector (2 where registers are
+  // short: float32 rows on the bf16 GEMM at 256 dims, 4-wave-per-SIMD tiles,
+  // and float32 tiles up to 64 dims, whose centroids are mostly resident and
+  // which would otherwise lose a wave per SIMD).  Other widths take one
+  // vector at a time with per-element bounds.
+  constexpr int kWpe = assign_wpe<KS, SB, W, XBF, GBF>();
+  constexpr bool kShortRegs = (GBF && !XBF && KS >= 64) || kWpe >= 4 || (!GBF && KS <= 16);
+  constexpr int kStageBatch = kShortRegs ? 2 : 8;
   auto stage = [&](int c0, int rows) {
     if constexpr (GBF) {
-      const bool v8 = (d % 8) == 0;
       const int64_t KD = (int64_t)K * d;
       constexpr int V = DP / 8;   // 8-element vectors per half row
-      for (int e = tid; e < rows * 2 * V; e += NT) {
-        const int rr = e / (2 * V), rem = e - rr * (2 * V);
-        const int half = rem >= V ? 1 : 0, c8 = (rem - half * V) * 8, j = c0 + rr;
-        const uint16_t* src = a.Cb + half * KD + (int64_t)j * d;
-        i16x8 v;
-        if (v8 && j < K && c8 < d) {
-          v = *(const i16x8*)(src + c8);
-        } else {
+      const int total = rows * 2 * V;
+      if (d == DP) {
+        for (int e0 = tid; e0 < total; e0 += kStageBatch * NT) {
+          i16x8 v[kStageBatch];
 #pragma unroll
-          for (int q = 0; q < 8; ++q)
-            v[q] = (j < K && c8 + q < d) ? (short)src[c8 + q] : (short)0;
+          for (int b = 0; b < kStageBatch; ++b) {
+            const int e = e0 + b * NT;
+            const int rr = e / (2 * V), rem = e - rr * (2 * V);
+            const int half = rem >= V ? 1 : 0, c8 = (rem - half * V) * 8, j = c0 + rr;
+            v[b] = (e < total && j < K) ? *(const i16x8*)(a.Cb + half * KD + (int64_t)j * d + c8)
+                                        : i16x8{0, 0, 0, 0, 0, 0, 0, 0};
+          }
+#pragma unroll
+          for (int b = 0; b < kStageBatch; ++b) {
+            const int e = e0 + b * NT;
+            if (e < total) {
+              const int rr = e / (2 * V), rem = e - rr * (2 * V);
+              const int half = rem >= V ? 1 : 0, c8 = (rem - half * V) * 8;
+              *(i16x8*)(Cbs + rr * LDB + half * DP + c8) = v[b];
+            }
+          }
         }
-        *(i16x8*)(Cbs + rr * LDB + half * DP + c8) = v;
+      } else {
+        for (int e = tid; e < total; e += NT) {
+          const int rr = e / (2 * V), rem = e - rr * (2 * V);
+          const int half = rem >= V ? 1 : 0, c8 = (rem - half * V) * 8, j = c0 + rr;
+          const uint16_t* src = a.Cb + half * KD + (int64_t)j * d;
+          i16x8 v;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = (j < K && c8 + q < d) ? (short)src[c8 + q] : (short)0;
+          *(i16x8*)(Cbs + rr * LDB + half * DP + c8) = v;
+        }
       }
     } else {
-      const bool v4 = (d % 4) == 0;
-      for (int e = tid; e < rows * (DP / 4); e += NT) {
-        const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
-        float4 v;
-        if (v4 && j < K && c4 < d) {
-          v = *(const float4*)(a.C + (int64_t)j * d + c4);
-        } else {
-          v.x = (j < K && c4 + 0 < d) ? a.C[(int64_t)j * d + c4 + 0] : 0.f;
-          v.y = (j < K && c4 + 1 < d) ? a.C[(int64_t)j * d + c4 + 1] : 0.f;
-          v.z = (j < K && c4 + 2 < d) ? a.C[(int64_t)j * d + c4 + 2] : 0.f;
-          v.w = (j < K && c4 + 3 < d) ? a.C[(int64_t)j * d + c4 + 3] : 0.f;
+      const int total = rows * (DP / 4);
+      if (d == DP) {
+        for (int e0 = tid; e0 < total; e0 += kStageBatch * NT) {
+          float4 v[kStageBatch];
+#pragma unroll
+          for (int b = 0; b < kStageBatch; ++b) {
+            const int e = e0 + b * NT;
+            const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
+            v[b] = (e < total && j < K) ? *(const float4*)(a.C + (int64_t)j * d + c4)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int b = 0; b < kStageBatch; ++b) {
+            const int e = e0 + b * NT;
+            if (e < total) {
+              const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4;
+              *(float4*)(Cs + rr * LD + c4) = v[b];
+            }
+          }
         }
-        *(float4*)(Cs + rr * LD + c4) = v;
+      } else {
+        for (int e = tid; e < total; e += NT) {
+          const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
+          const float* src = a.C + (int64_t)j * d;
+          float4 v;
+          v.x = (j < K && c4 + 0 < d) ? src[c4 + 0] : 0.f;
+          v.y = (j < K && c4 + 1 < d) ? src[c4 + 1] : 0.f;
+          v.z = (j < K && c4 + 2 < d) ? src[c4 + 2] : 0.f;
+          v.w = (j < K && c4 + 3 < d) ? src[c4 + 3] : 0.f;
+          *(float4*)(Cs + rr * LD + c4) = v;
+        }
       }
     }
     for (int rr = tid; rr < rows; rr += NT) {
@@ -403,6 +480,10 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   // are exact as bf16; float32 rows on the bf16 GEMM keep hi and lo (XLO)
   constexpr bool KF = !GBF;
   constexpr bool XLO = GBF && !XBF;
+  using AO = AOp<KS, GBF, LB>;
+  // float32 rows on the bf16 GEMM at 256 dims and float32 tiles beyond 128
+  // dims have no registers for a second operand buffer (it would spill)
+  constexpr bool kPairOps = !(XLO && KS >= 64) && !(!GBF && KS >= 48);
 
   for (int64_t grp = bx; grp < groups; grp += gx) {
     // Sample rows of this wave, kept in registers.
@@ -469,9 +550,13 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
         stage(c0, rows);
         __syncthreads();
       }
-      for (int tt = 0; tt < rows; tt += 16) {
+      // Tiles in pairs with two operand buffers: the loads of tile t + 1 are
+      // issued (and pinned there by a scheduling barrier) before the MFMAs of
+      // tile t.  The index of a load past the chunk's last tile is clamped to
+      // a tile of the chunk; that operand is then not used.
+      auto step = [&](const AO& op, int tt) {
         f32x4 acc[SB];
-        tile_mfma<KS, SB, GBF, XLO, LB>(Cs, Cbs, ncs, tt, g, r16, xv, xbv, xlv, acc);
+        tile_mfma<KS, SB, GBF, XLO, LB>(op, xv, xbv, xlv, acc);
         const int jb = c0 + tt;
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
@@ -487,6 +572,25 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
             best[s] = gt ? v : best[s];
             bidx[s] = gt ? (jb + r) : bidx[s];
           }
+        }
+      };
+      AO opa;
+      if constexpr (kPairOps) {
+        AO opb;
+        load_aop<KS, GBF, LB>(Cs, Cbs, ncs, 0, g, r16, opa);
+        for (int tt = 0; tt < rows; tt += 32) {
+          load_aop<KS, GBF, LB>(Cs, Cbs, ncs, tt + 16 < rows ? tt + 16 : tt, g, r16, opb);
+          __builtin_amdgcn_sched_barrier(0);
+          step(opa, tt);
+          if (tt + 16 >= rows) break;
+          load_aop<KS, GBF, LB>(Cs, Cbs, ncs, tt + 32 < rows ? tt + 32 : tt + 16, g, r16, opa);
+          __builtin_amdgcn_sched_barrier(0);
+          step(opb, tt + 16);
+        }
+      } else {
+        for (int tt = 0; tt < rows; tt += 16) {
+          load_aop<KS, GBF, LB>(Cs, Cbs, ncs, tt, g, r16, opa);
+          step(opa, tt);
         }
       }
     }
@@ -653,8 +757,9 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
 #pragma unroll
           for (int u = 0; u < QT; ++u) acc[u] = 0.0;
           if (v4) {
-            for (int k = 0; k < d; k += 4) {
-              const float4 c4 = *(const float4*)(cr + k);
+            // RB loads of the centroid row in flight per step (dimensions
+            // are still added in order)
+            auto dims4 = [&](const float4& c4, int k) {
 #pragma unroll
               for (int u = 0; u < QT; ++u) {
                 if (u < total) {
@@ -665,7 +770,17 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
                   df = (double)x4.w - (double)c4.w; acc[u] = fma(df, df, acc[u]);
                 }
               }
+            };
+            constexpr int RB = kShortRegs ? 1 : 8;
+            int k = 0;
+            for (; k + 4 * RB <= d; k += 4 * RB) {
+              float4 c4[RB];
+#pragma unroll
+              for (int b = 0; b < RB; ++b) c4[b] = *(const float4*)(cr + k + 4 * b);
+#pragma unroll
+              for (int b = 0; b < RB; ++b) dims4(c4[b], k + 4 * b);
             }
+            for (; k < d; k += 4) dims4(*(const float4*)(cr + k), k);
           } else {
             for (int k = 0; k < d; ++k) {
               const double c = (double)cr[k];
@@ -743,19 +858,6 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     for (int w = 1; w < W; ++w) e += dred[w];
     a.e_part[bx] = e;
   }
-}
-
-// Waves per SIMD the register allocation must leave room for: 16-wave
-// workgroups need 4; small float32 tiles run best at 4 (latency hiding);
-// wide tiles (float32 rows on the bf16 GEMM, 8 sample blocks, d > 128 in
-// bf16, more than 64 dims x blocks in float32) get the whole register file;
-// the rest run 2 waves per SIMD.
-template <int KS, int SB, int W, bool XBF, bool GBF>
-constexpr int assign_wpe() {
-  if (W >= 16) return 4;
-  if (!GBF) return (KS * SB <= 16 && SB <= 2) ? 4 : (KS * SB > 64 ? 1 : 2);
-  if (!XBF || KS >= 48 || SB >= 8) return 1;
-  return 2;
 }
 
 template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
