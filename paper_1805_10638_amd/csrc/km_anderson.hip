@@ -24,17 +24,26 @@ constexpr int kSmallLs = 12;   // systems up to this size are solved in register
 // (zero for dropped columns) to th[0..mt) and returns the number of columns
 // used (0 when the factorisation fails).
 __device__ int ls_solve_group(const CombineArgs& a, int s_new, int len_new, int mt, double ridge,
-                              double* th, double* newrow, double* bvec, double* Lm, double* sc, int* cols,
-                              int* misc) {
+                              double* th, double* newrow, double* bvec, double* Lm, double* sc, double* diag,
+                              int* cols, int* misc) {
   const int cap = a.cap;
   const int tid = threadIdx.x;
   // fixed-order sums of the per-workgroup partials: new Gram row and rhs
   for (int q = tid; q < len_new; q += blockDim.x) {
     const int sl = (s_new - q + cap) % cap;
     double ga = 0.0, gb = 0.0;
-    for (int w = 0; w < a.n_dots; ++w) {
-      ga += a.dots[(int64_t)w * 2 * cap + sl];
-      gb += a.dots[(int64_t)w * 2 * cap + cap + sl];
+    for (int w0 = 0; w0 < a.n_dots; w0 += 8) {   // partials in order, 16 loads in flight
+      double va[8], vb[8];
+#pragma unroll
+      for (int q8 = 0; q8 < 8; ++q8) {
+        const bool ok = w0 + q8 < a.n_dots;
+        va[q8] = ok ? a.dots[(int64_t)(w0 + q8) * 2 * cap + sl] : 0.0;
+        vb[q8] = ok ? a.dots[(int64_t)(w0 + q8) * 2 * cap + cap + sl] : 0.0;
+      }
+#pragma unroll
+      for (int q8 = 0; q8 < 8; ++q8) {
+        if (w0 + q8 < a.n_dots) { ga += va[q8]; gb += vb[q8]; }
+      }
     }
     newrow[q] = ga;
     bvec[q] = gb;
@@ -46,10 +55,12 @@ __device__ int ls_solve_group(const CombineArgs& a, int s_new, int len_new, int 
     const int sq = (s_new - q + cap) % cap, sr = (s_new - r + cap) % cap;
     return a.gram[sq * cap + sr];
   };
+  for (int q = tid; q < mt; q += blockDim.x) diag[q] = gram(q, q);   // loaded in parallel
+  __syncthreads();
   if (tid == 0) {
     int n = 0;
     for (int q = 0; q < mt; ++q) {
-      const double nrm = sqrt(q == 0 ? newrow[0] : gram(q, q));
+      const double nrm = sqrt(diag[q]);
       if (nrm > 0.0) { cols[n] = q; sc[n] = nrm; ++n; }
     }
     misc[0] = n;
@@ -177,12 +188,16 @@ __device__ __forceinline__ float put_centroid(float* C, uint16_t* Cb, int64_t KD
 
 __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
   Ctl* c = a.ctl;
-  __shared__ double th[kMaxM], newrow[kMaxM], bvec[kMaxM], sc[kMaxM];
+  __shared__ double th[kMaxM], newrow[kMaxM], bvec[kMaxM], sc[kMaxM], diag[kMaxM];
   __shared__ double Lm[kMaxM * kMaxM];
   __shared__ int cols[kMaxM], misc[2];
   int mt = 0, head = 0;
   const int cap = a.cap;
   if (a.gated) {
+    if (a.done_out && bx == 0 && threadIdx.x == 0) {   // the host polls this slot
+      *(volatile int*)a.done_out = c->done;
+      __threadfence_system();
+    }
     if (c->done) return;
     const int t = c->t;
     if (cap > 0) {
@@ -190,7 +205,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
       const int len_new = t < cap ? t : cap;
       int m = c->m < t ? c->m : t;
       if (m > len_new) m = len_new;
-      const int used = ls_solve_group(a, s_new, len_new, m, c->ridge, th, newrow, bvec, Lm, sc, cols, misc);
+      const int used = ls_solve_group(a, s_new, len_new, m, c->ridge, th, newrow, bvec, Lm, sc, diag, cols, misc);
       if (bx == 0) {
         for (int q = threadIdx.x; q < len_new; q += blockDim.x) {
           const int sl = (s_new - q + cap) % cap;
@@ -228,9 +243,16 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
     const int64_t e = (int64_t)j * d + k;
     const double g = a.G_last[e];
     double v = g;
-    for (int q = 0; q < mt; ++q) {
-      const int sl = (head - q + cap) % cap;
-      v -= th[q] * a.ring_dG[(int64_t)sl * KD + e];
+    for (int q0 = 0; q0 < mt; q0 += 4) {   // history columns in order, 4 loads in flight
+      double r[4];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int sl = (head - (q0 + q4) + cap) % cap;
+        r[q4] = q0 + q4 < mt ? a.ring_dG[(int64_t)sl * KD + e] : 0.0;
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+        if (q0 + q4 < mt) v -= th[q0 + q4] * r[q4];
     }
     put_centroid(a.C_cand, a.Cb_cand, KD, e, v, &n_c, &e_c);
     put_centroid(a.C_fb, a.Cb_fb, KD, e, g, &n_f, &e_f);

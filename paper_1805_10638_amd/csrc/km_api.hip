@@ -188,7 +188,7 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   AssignArgs a{};
   a.X = X; a.N = N; a.d = d; a.K = K; a.C = C; a.nc = c->w.nc_tmp;
   a.Cb = gbf ? c->w.Cb_tmp : nullptr; a.delta = gbf ? c->w.del_tmp : nullptr;
-  a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->w.e_part; a.ctl = c->w.ctl;
+  a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->w.e_part; a.flags = c->w.flags; a.ctl = c->w.ctl;
   a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
   HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
@@ -280,7 +280,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   AssignArgs a{};
   a.X = X; a.N = N; a.d = d; a.K = K; a.C = c->w.C_tmp; a.nc = c->w.nc_tmp;
   a.Cb = gbf ? c->w.Cb_tmp : nullptr; a.delta = gbf ? c->w.del_tmp : nullptr;
-  a.lab = c->w.labels; a.lab_prev = nullptr; a.e_part = c->w.e_part; a.ctl = c->w.ctl;
+  a.lab = c->w.labels; a.lab_prev = nullptr; a.e_part = c->w.e_part; a.flags = c->w.flags; a.ctl = c->w.ctl;
   a.xbf16 = xbf; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xbf, d, K);
   UpdateArgs u{};
@@ -338,15 +338,19 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   CtlArgs k2 = k1;
   k2.e_part = c->w.e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
 
+  // The combine kernel, last of the iteration, writes the done flag into
+  // pinned slot p (no copy node).
+  int* done_dev = nullptr;
+  HIP_TRY(c, hipHostGetDevicePointer((void**)&done_dev, c->done_host, 0), "hipHostGetDevicePointer");
   auto enqueue_rest = [&](int p) -> km_status {
+    CombineArgs cp = ci;
+    cp.done_out = done_dev + p;
     HIP_TRY(c, launch_controller(k1, q), "controller");
     HIP_TRY(c, launch_assign(af, kRoleFallback, q), "assignment");
     HIP_TRY(c, launch_controller(k2, q), "controller");
     HIP_TRY(c, launch_update_sums(u, q), "update");
     HIP_TRY(c, launch_finalize(fi, q), "finalize");
-    HIP_TRY(c, launch_combine(ci, q), "combine");
-    HIP_TRY(c, hipMemcpyAsync(&c->done_host[p], &c->w.ctl->done, sizeof(int), hipMemcpyDeviceToHost, q),
-            "poll copy");
+    HIP_TRY(c, launch_combine(cp, q), "combine");
     return KM_OK;
   };
 
@@ -396,7 +400,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
         }
         it_ms.push_back(ms);
       }
-      if (c->done_host[pp]) finished = true;
+      if (((volatile int*)c->done_host)[pp]) finished = true;
     }
     ++launched;
   }

@@ -82,7 +82,7 @@ int64_t assign_resident(const KernelPick& p, int64_t N, double frac) {
 }
 
 hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s) {
-  if (a.N <= 0 || a.K <= 0 || a.d <= 0 || a.d > kMaxD || a.K > kMaxK) return hipErrorInvalidValue;
+  if (a.N <= 0 || a.K <= 0 || a.d <= 0 || a.d > kMaxD || a.K > kMaxK || !a.flags) return hipErrorInvalidValue;
   const KernelPick p = assign_pick(a);
   if (!p.fn) return hipErrorInvalidValue;
   const int grid = assign_grid(a);

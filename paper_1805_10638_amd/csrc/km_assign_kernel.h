@@ -111,37 +111,6 @@ __device__ __forceinline__ int wave_argmin(double bd, int bj, double* dist) {
   return bj;
 }
 
-// Centroids from global memory, the sample staged in LDS (xrow, zero-padded
-// to DP): float64 differences over the d real dimensions.
-template <int DP>
-__device__ __forceinline__ int exact_argmin(const float* xrow, int d, const float* C, int K, int lane,
-                                            double* dist) {
-  double bd = __builtin_inf();
-  int bj = -1;
-  const bool v4 = (d % 4) == 0;
-  for (int j = lane; j < K; j += kWave) {
-    const float* cr = C + (int64_t)j * d;
-    double s = 0.0;
-    if (v4) {
-      for (int k = 0; k < d; k += 4) {
-        const float4 x4 = *(const float4*)(xrow + k);
-        const float4 c4 = *(const float4*)(cr + k);
-        double df = (double)x4.x - (double)c4.x; s = fma(df, df, s);
-        df = (double)x4.y - (double)c4.y; s = fma(df, df, s);
-        df = (double)x4.z - (double)c4.z; s = fma(df, df, s);
-        df = (double)x4.w - (double)c4.w; s = fma(df, df, s);
-      }
-    } else {
-      for (int k = 0; k < d; ++k) {
-        const double df = (double)xrow[k] - (double)cr[k];
-        s = fma(df, df, s);
-      }
-    }
-    if (s < bd) { bd = s; bj = j; }
-  }
-  return wave_argmin(bd, bj, dist);
-}
-
 // Centroids resident in LDS (row stride ld, zero-padded to DP) and the
 // sample staged in LDS (xrow, zero-padded to DP).
 template <int DP>
@@ -173,15 +142,15 @@ __device__ __forceinline__ int exact_argmin_lds(const float* xrow, const float* 
   return wave_argmin(bd, bj, dist);
 }
 
-// Workgroup scratch after the centroid chunk and its norms (bytes): maxima
-// (32 floats), energy partials (16 doubles), re-check queue counters (3 ints,
-// padded), per-wave re-check winners (kQueue x 16 ints and doubles).  Staged
-// rows follow: kQueue queued rows and one row per wave for immediate
-// re-checks ((kQueue + 16) x DP floats).
-constexpr int kQueue = 4;
-constexpr int kAssignScratch = 128 + 128 + 128 + kQueue * 16 * 4 + kQueue * 16 * 8;
+// LDS layout.  HEAD: workgroup scratch (maxima: 32 floats; energy partials:
+// 16 doubles; flagged-row counts: 16 ints, padded) and one staged row per wave
+// for immediate re-checks (16 x DP floats).  AREA: the centroid chunk and its
+// -||c||^2/2 values during the row groups; after the last row group the
+// deferred re-check reuses it for RX sample rows (float64), per-wave
+// reduction slots and float32 centroid rows.
+constexpr int kAssignScratch = 128 + 128 + 128;
 
-// LB: bytes of LDS a workgroup may use (centroid chunk, norms, scratch).
+// LB: bytes of LDS a workgroup may use for the centroid chunk.
 template <int KS, bool GBF, int LB>
 struct Tile {
   static constexpr int DP = 4 * KS;                    // padded dimension
@@ -189,16 +158,23 @@ struct Tile {
   static constexpr int LD = DP + 4;                    // f32 LDS row stride (floats)
   static constexpr int LDB = 2 * DP + 8;               // bf16 LDS row stride: hi[DP], lo[DP], pad
   static constexpr int ROW_BYTES = GBF ? LDB * 2 : LD * 4;
+  static constexpr int HEAD = kAssignScratch + 16 * DP * 4;
+  static constexpr int RX = DP <= 128 ? 16 : 8;        // rows per deferred re-check batch
+  static constexpr int DEF_FIXED = RX * DP * 8 + RX * 16 * 16;
+  static constexpr int DEF_MIN = DEF_FIXED + 16 * LD * 4;
   // centroid rows per LDS chunk (multiple of 16) for a given K
   static __host__ __device__ int chunk_rows(int K) {
     const int kpad = (K + 15) & ~15;
-    int c = ((LB - (kQueue + 16) * DP * 4 - kAssignScratch) / (ROW_BYTES + 4)) & ~15;
+    int c = ((LB - HEAD) / (ROW_BYTES + 4)) & ~15;
     return c < kpad ? c : kpad;
   }
-  static __host__ __device__ size_t lds_bytes(int K) {
-    const int c = chunk_rows(K);
-    return (size_t)c * ROW_BYTES + (size_t)c * 4 + kAssignScratch + (size_t)(kQueue + 16) * DP * 4;
+  static __host__ __device__ size_t area_bytes(int K) {
+    const size_t c = (size_t)chunk_rows(K) * (ROW_BYTES + 4);
+    return c > (size_t)DEF_MIN ? c : (size_t)DEF_MIN;
   }
+  static __host__ __device__ size_t lds_bytes(int K) { return HEAD + area_bytes(K); }
+  // float32 centroid rows per chunk of the deferred re-check (at least 16)
+  static __host__ __device__ int def_rows(int K) { return (int)((area_bytes(K) - DEF_FIXED) / (LD * 4)); }
 };
 
 // A operand of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk): this
@@ -242,7 +218,10 @@ __device__ __forceinline__ void load_aop(const float* Cs, const uint16_t* Cbs, c
 
 // MFMAs of one tile against the SB sample blocks of this wave; accumulators
 // start at -||c||^2/2.  bf16: x.hi + x.lo per slice (and x_lo.hi for float32
-// rows, XLO).
+// rows, XLO).  A scheduling barrier after every group of SB independent MFMAs
+// keeps the blocks in round-robin order, so that an MFMA never waits on the
+// accumulator written just before it (the compiler otherwise pairs dependent
+// MFMAs and pads them with wait states).
 template <int KS, int SB, bool GBF, bool XLO, int LB, typename XV>
 __device__ __forceinline__ void tile_mfma(const AOp<KS, GBF, LB>& o, const XV& xv,
                                           const i16x8 (&xbv)[SB][Tile<KS, GBF, LB>::NB],
@@ -258,23 +237,28 @@ __device__ __forceinline__ void tile_mfma(const AOp<KS, GBF, LB>& o, const XV& x
       for (int s = 0; s < SB; ++s)
         acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
             __builtin_bit_cast(bf16x8, o.ah[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int s = 0; s < SB; ++s)
         acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
             __builtin_bit_cast(bf16x8, o.al[q]), __builtin_bit_cast(bf16x8, xbv[s][q]), acc[s], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
       if constexpr (XLO) {
 #pragma unroll
         for (int s = 0; s < SB; ++s)
           acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
               __builtin_bit_cast(bf16x8, o.ah[q]), __builtin_bit_cast(bf16x8, xlv[s][q]), acc[s], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < KS; ++q)
+    for (int q = 0; q < KS; ++q) {
 #pragma unroll
       for (int s = 0; s < SB; ++s)
         acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.av[q], xv[s][q], acc[s], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -331,19 +315,17 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r16 = lane & 15;
 
-  // LDS: centroid tile, -||c||^2/2 per row, small reduction scratch.
+  // LDS (layout at Tile): scratch, per-wave rows, centroid chunk + norms.
   const int kchunk = T::chunk_rows(K);
   const bool resident = kchunk >= Kpad;
-  float* Cs = (float*)smem_raw;                                  // kchunk x LD (f32 path)
-  uint16_t* Cbs = (uint16_t*)smem_raw;                           // kchunk x LDB (bf16 path)
-  float* ncs = (float*)(smem_raw + (size_t)kchunk * T::ROW_BYTES);
-  float* fred = ncs + kchunk;                                // 2 W floats (W <= 16)
-  double* dred = (double*)(fred + 32);                       // W doubles
-  int* qcnt = (int*)(fred + 64);                             // 3 rotating queue counters
-  int* qj = qcnt + 32;                                       // kQueue rows x 16 waves
-  double* qd = (double*)(qj + kQueue * 16);                  // kQueue rows x 16 waves
-  float* qx = (float*)(qd + kQueue * 16);                    // (kQueue + 16) staged rows x DP
-  if (tid < 3) qcnt[tid] = 0;
+  float* fred = (float*)smem_raw;                            // 2 x 16 floats
+  double* dred = (double*)(smem_raw + 128);                  // W doubles
+  int* wcnt = (int*)(smem_raw + 256);                        // W flagged-row counts
+  float* xrows = (float*)(smem_raw + kAssignScratch);        // 16 x DP floats
+  unsigned char* area = smem_raw + T::HEAD;
+  float* Cs = (float*)area;                                  // kchunk x LD (f32 path)
+  uint16_t* Cbs = (uint16_t*)area;                           // kchunk x LDB (bf16 path)
+  float* ncs = (float*)(area + (size_t)kchunk * T::ROW_BYTES);
 
   // max_j ||c_j||^2 and max_j r_j over the real centroids
   float mx = 0.f, mdel = 0.f;
@@ -379,6 +361,41 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   constexpr int kWpe = assign_wpe<KS, SB, W, XBF, GBF>();
   constexpr bool kShortRegs = (GBF && !XBF && KS >= 64) || kWpe >= 4 || (!GBF && KS <= 16);
   constexpr int kStageBatch = kShortRegs ? 2 : 8;
+  // float32 rows [c0, c0 + rows) of C into dst (row stride LD, zero beyond d)
+  auto stage_f32 = [&](float* dst, int c0, int rows) {
+    const int total = rows * (DP / 4);
+    if (d == DP) {
+      for (int e0 = tid; e0 < total; e0 += kStageBatch * NT) {
+        float4 v[kStageBatch];
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) {
+          const int e = e0 + b * NT;
+          const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
+          v[b] = (e < total && j < K) ? *(const float4*)(a.C + (int64_t)j * d + c4)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) {
+          const int e = e0 + b * NT;
+          if (e < total) {
+            const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4;
+            *(float4*)(dst + rr * LD + c4) = v[b];
+          }
+        }
+      }
+    } else {
+      for (int e = tid; e < total; e += NT) {
+        const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
+        const float* src = a.C + (int64_t)j * d;
+        float4 v;
+        v.x = (j < K && c4 + 0 < d) ? src[c4 + 0] : 0.f;
+        v.y = (j < K && c4 + 1 < d) ? src[c4 + 1] : 0.f;
+        v.z = (j < K && c4 + 2 < d) ? src[c4 + 2] : 0.f;
+        v.w = (j < K && c4 + 3 < d) ? src[c4 + 3] : 0.f;
+        *(float4*)(dst + rr * LD + c4) = v;
+      }
+    }
+  };
   auto stage = [&](int c0, int rows) {
     if constexpr (GBF) {
       const int64_t KD = (int64_t)K * d;
@@ -417,38 +434,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
         }
       }
     } else {
-      const int total = rows * (DP / 4);
-      if (d == DP) {
-        for (int e0 = tid; e0 < total; e0 += kStageBatch * NT) {
-          float4 v[kStageBatch];
-#pragma unroll
-          for (int b = 0; b < kStageBatch; ++b) {
-            const int e = e0 + b * NT;
-            const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
-            v[b] = (e < total && j < K) ? *(const float4*)(a.C + (int64_t)j * d + c4)
-                                        : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-#pragma unroll
-          for (int b = 0; b < kStageBatch; ++b) {
-            const int e = e0 + b * NT;
-            if (e < total) {
-              const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4;
-              *(float4*)(Cs + rr * LD + c4) = v[b];
-            }
-          }
-        }
-      } else {
-        for (int e = tid; e < total; e += NT) {
-          const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
-          const float* src = a.C + (int64_t)j * d;
-          float4 v;
-          v.x = (j < K && c4 + 0 < d) ? src[c4 + 0] : 0.f;
-          v.y = (j < K && c4 + 1 < d) ? src[c4 + 1] : 0.f;
-          v.z = (j < K && c4 + 2 < d) ? src[c4 + 2] : 0.f;
-          v.w = (j < K && c4 + 3 < d) ? src[c4 + 3] : 0.f;
-          *(float4*)(Cs + rr * LD + c4) = v;
-        }
-      }
+      stage_f32(Cs, c0, rows);
     }
     for (int rr = tid; rr < rows; rr += NT) {
       const int j = c0 + rr;
@@ -459,17 +445,17 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     stage(0, Kpad);
     __syncthreads();
   }
-  // Re-check queue: kQueue rows per row group shared by the waves (slots by
-  // LDS atomics; a row's result does not depend on its slot), and one row
-  // per wave for immediate re-checks once the queue is full.  Row group n
-  // counts on qcnt[n % 3]: the counter of group n + 1 is cleared before the
-  // first barrier of group n, after every wave has read the one of n - 2.
-  // With float32 centroids resident in LDS a single wave re-checks a row
-  // quickly and the queue's barrier per row group would cost more.
-  constexpr int QT = kQueue;
-  float* xrow = qx + (QT + wave) * DP;             // this wave's immediate row
-  const bool use_queue = GBF || !resident;         // uniform per launch
-  int rot = 0;
+  // Flagged rows.  With float32 centroids resident in LDS a wave re-checks a
+  // row at once from the LDS copy (xrow: its staged row).  Otherwise each
+  // wave appends the rows it flags to its own list, and after the last row
+  // group the workgroup re-checks all of them together (below), so the
+  // centroids are read once per batch of rows rather than once per row.
+  // The p-th row a wave flags is stored in the slot of the p-th row it owns
+  // (its rows of row groups bx, bx + gx, ...), so every list fits in N ints
+  // and its order is fixed.
+  float* xrow = xrows + wave * DP;
+  const bool defer = GBF || !resident;             // uniform per launch
+  int nfl = 0;                                     // rows this wave has listed
 
   const int64_t group_rows = 16 * SB * W;
   const int64_t groups = (a.N + group_rows - 1) / group_rows;
@@ -596,7 +582,8 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
 
     // Epilogue: combine the 4 lane groups, flag near ties, exact energy terms.
-    int bi_s[SB], u_s[SB];
+    int bi_s[SB];
+    bool fl_s[SB];
     double term_s[SB];
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
@@ -690,144 +677,39 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
         term = p;
       }
 
-      // Flagged rows: queue them for the workgroup re-check below, or (queue
-      // full) re-check them now with this wave alone.  The row is spread over
-      // lanes r16 == f of the 4 lane groups.
-      int u_mine = -1;
       unsigned long long fm = __ballot(flag) & 0xFFFFull;
       n_flag += (unsigned)__popcll(fm);
-      while (fm) {
-        const int f = __ffsll((long long)fm) - 1;
-        fm &= fm - 1;
-        int slot = QT;
-        if (use_queue) {
-          if (lane == 0) slot = atomicAdd(&qcnt[rot], 1);
-          slot = __shfl(slot, 0, kWave);
+      if (defer) {
+        if (flag && g == 0) {
+          const int pos = nfl + __popcll(fm & ((1ull << r16) - 1ull));
+          const int64_t own = (bx + (int64_t)(pos / (16 * SB)) * gx) * group_rows + wave * (16 * SB) +
+                              pos % (16 * SB);
+          a.flags[own] = (int)i;
         }
-        if (slot < QT) {
-          float* dst = qx + slot * DP;
+        nfl += __popcll(fm);
+      } else {
+        // immediate: the row is spread over lanes r16 == f of the 4 lane groups
+        while (fm) {
+          const int f = __ffsll((long long)fm) - 1;
+          fm &= fm - 1;
           if (r16 == f) {
 #pragma unroll
-            for (int q = 0; q < KS; ++q) dst[g * KS + q] = xe[q];
-            u_mine = slot;
+            for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xe[q];
           }
-          continue;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          double dist;
+          const int j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (j >= 0 && r16 == f) { bi = j; term = dist; }
         }
-        if (r16 == f) {
-#pragma unroll
-          for (int q = 0; q < KS; ++q) xrow[g * KS + q] = xe[q];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double dist;
-        int j;
-        if (!GBF && resident) j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist);
-        else j = exact_argmin<DP>(xrow, d, a.C, K, lane, &dist);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (j >= 0 && r16 == f) { bi = j; term = dist; }
       }
       bi_s[s] = bi;
       term_s[s] = term;
-      u_s[s] = u_mine;
-    }
-
-    // Workgroup re-check of the queued rows: every thread takes centroids
-    // tid, tid + NT, ... and scores each against all queued rows (float64
-    // direct differences, dimensions in order); per queued row the lowest
-    // distance wins, ties to the lowest index (waves in order).  The barrier
-    // also publishes the queue; it is taken by every wave of every group.
-    if (use_queue) {
-      if (tid == 0) qcnt[rot == 2 ? 0 : rot + 1] = 0;
-      __syncthreads();
-      int total = qcnt[rot];
-      total = total < QT ? total : QT;
-      rot = rot == 2 ? 0 : rot + 1;
-      if (total > 0) {
-        double bd[QT];
-        int bj[QT];
-#pragma unroll
-        for (int u = 0; u < QT; ++u) { bd[u] = __builtin_inf(); bj[u] = -1; }
-        const bool v4 = (d % 4) == 0;
-        for (int j = tid; j < K; j += NT) {
-          const float* cr = (!GBF && resident) ? Cs + j * LD : a.C + (int64_t)j * d;
-          double acc[QT];
-#pragma unroll
-          for (int u = 0; u < QT; ++u) acc[u] = 0.0;
-          if (v4) {
-            // RB loads of the centroid row in flight per step (dimensions
-            // are still added in order)
-            auto dims4 = [&](const float4& c4, int k) {
-#pragma unroll
-              for (int u = 0; u < QT; ++u) {
-                if (u < total) {
-                  const float4 x4 = *(const float4*)(qx + u * DP + k);
-                  double df = (double)x4.x - (double)c4.x; acc[u] = fma(df, df, acc[u]);
-                  df = (double)x4.y - (double)c4.y; acc[u] = fma(df, df, acc[u]);
-                  df = (double)x4.z - (double)c4.z; acc[u] = fma(df, df, acc[u]);
-                  df = (double)x4.w - (double)c4.w; acc[u] = fma(df, df, acc[u]);
-                }
-              }
-            };
-            constexpr int RB = kShortRegs ? 1 : 8;
-            int k = 0;
-            for (; k + 4 * RB <= d; k += 4 * RB) {
-              float4 c4[RB];
-#pragma unroll
-              for (int b = 0; b < RB; ++b) c4[b] = *(const float4*)(cr + k + 4 * b);
-#pragma unroll
-              for (int b = 0; b < RB; ++b) dims4(c4[b], k + 4 * b);
-            }
-            for (; k < d; k += 4) dims4(*(const float4*)(cr + k), k);
-          } else {
-            for (int k = 0; k < d; ++k) {
-              const double c = (double)cr[k];
-#pragma unroll
-              for (int u = 0; u < QT; ++u) {
-                if (u < total) {
-                  const double df = (double)qx[u * DP + k] - c;
-                  acc[u] = fma(df, df, acc[u]);
-                }
-              }
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < QT; ++u)
-            if (acc[u] < bd[u]) { bd[u] = acc[u]; bj[u] = j; }
-        }
-#pragma unroll
-        for (int u = 0; u < QT; ++u) {
-          if (u < total) {
-            double dist;
-            const int j = wave_argmin(bd[u], bj[u], &dist);
-            if (lane == 0) { qd[u * 16 + wave] = dist; qj[u * 16 + wave] = j; }
-          }
-        }
-        __syncthreads();
-        if (tid < total) {
-          double bdist = qd[tid * 16];
-          int bjj = qj[tid * 16];
-          for (int w = 1; w < W; ++w) {
-            const double od = qd[tid * 16 + w];
-            const int oj = qj[tid * 16 + w];
-            const bool take = (od < bdist) || (od == bdist && (unsigned)oj < (unsigned)bjj);
-            bdist = take ? od : bdist;
-            bjj = take ? oj : bjj;
-          }
-          qd[tid * 16] = bdist;
-          qj[tid * 16] = bjj;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < SB; ++s) {
-          if (u_s[s] >= 0) {
-            const int j = qj[u_s[s] * 16];
-            if (j >= 0) { bi_s[s] = j; term_s[s] = qd[u_s[s] * 16]; }
-          }
-        }
-      }
+      fl_s[s] = defer && flag;
     }
 
     double e_lane = 0.0;
@@ -835,15 +717,134 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     for (int s = 0; s < SB; ++s) {
       const int64_t i = row0 + 16 * s + r16;
       const bool valid = i < a.N;
+      const bool mine = valid && g == 0 && !fl_s[s];   // deferred rows are written later
       bool ch = false;
-      if (valid && g == 0) {
+      if (mine) {
         rho[i] = bi_s[s];
         ch = (prev != nullptr) && (prev[i] != bi_s[s]);
       }
       n_changed += (unsigned)__popcll(__ballot(ch));
-      e_lane += (valid && g == 0) ? term_s[s] : 0.0;
+      e_lane += mine ? term_s[s] : 0.0;
     }
     e_wave += wave_sum(e_lane);
+  }
+
+  // Deferred re-check of the listed rows: float64 direct differences to all
+  // K centroids (dimensions in order), the lowest distance wins, ties to the
+  // lowest index.  Rows go in batches of RX (staged as float64), centroids in
+  // chunks of def_rows(K) float32 rows.  Thread t scores centroid slots
+  // t % S, t % S + S, ... of a chunk against rows rg, rg + G, ... of the
+  // batch (rg = t / S, G = NT / S >= 2; S is a multiple of 64, so a wave
+  // shares its rows and reduces them with shuffles).  The energy terms of the
+  // batch are added in row order by thread 0.
+  double e_def = 0.0;
+  if (defer) {
+    if (lane == 0) wcnt[wave] = nfl;
+    __syncthreads();
+    int R = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) R += wcnt[w];
+    // rows per batch: the layout's RX, or 8 where registers are short
+    constexpr int RX = kShortRegs && T::RX > 8 ? 8 : T::RX;
+    constexpr int MR = RX / 2;
+    double* xb = (double*)area;                          // RX x DP
+    double* redd = (double*)(area + RX * DP * 8);        // RX x 16 waves
+    int* redj = (int*)(redd + RX * 16);                  // RX x 16 waves
+    int* rowidx = redj + RX * 16;                        // RX
+    double* rowdist = (double*)(rowidx + RX);            // RX
+    float* cc = (float*)(area + T::DEF_FIXED);           // def_rows(K) x LD
+    const int crows = T::def_rows(K);
+    const int want = crows < NT / 2 ? crows : NT / 2;
+    int S = 64;
+    while (S < want) S <<= 1;
+    const int G = NT / S;
+    const int cs = tid % S, rg = tid / S;
+    for (int b0 = 0; b0 < R; b0 += RX) {
+      const int rb = (R - b0) < RX ? (R - b0) : RX;
+      if (tid < rb) {
+        int r = b0 + tid, w = 0;
+        while (r >= wcnt[w]) { r -= wcnt[w]; ++w; }
+        const int64_t own = (bx + (int64_t)(r / (16 * SB)) * gx) * group_rows + w * (16 * SB) + r % (16 * SB);
+        rowidx[tid] = a.flags[own];
+      }
+      __syncthreads();
+      for (int e = tid; e < RX * DP; e += NT) {
+        const int u = e / DP, k = e - u * DP;
+        double v = 0.0;
+        if (u < rb && k < d) v = (double)ld_x(a.X, (int64_t)rowidx[u] * d + k, XBF);
+        xb[e] = v;
+      }
+      double bd[MR];
+      int bj[MR];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) { bd[m] = __builtin_inf(); bj[m] = -1; }
+      for (int c0 = 0; c0 < K; c0 += crows) {
+        const int rows = (K - c0) < crows ? (K - c0) : crows;
+        __syncthreads();
+        stage_f32(cc, c0, rows);
+        __syncthreads();
+        for (int jj = cs; jj < rows; jj += S) {
+          const float* cr = cc + jj * LD;
+          const int j = c0 + jj;
+#pragma unroll
+          for (int m0 = 0; m0 < MR; m0 += 4) {
+            if (rg + G * m0 >= rb) break;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < DP; k += 4) {
+              const float4 c4 = *(const float4*)(cr + k);
+              const double cx = c4.x, cy = c4.y, cz = c4.z, cw = c4.w;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int u = rg + G * (m0 + r);
+                if (u < rb) {
+                  const double* xr = xb + u * DP + k;
+                  double df = xr[0] - cx; acc[r] = fma(df, df, acc[r]);
+                  df = xr[1] - cy; acc[r] = fma(df, df, acc[r]);
+                  df = xr[2] - cz; acc[r] = fma(df, df, acc[r]);
+                  df = xr[3] - cw; acc[r] = fma(df, df, acc[r]);
+                }
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (acc[r] < bd[m0 + r]) { bd[m0 + r] = acc[r]; bj[m0 + r] = j; }
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int u = rg + G * m;
+        if (u < rb) {
+          double dist;
+          const int j = wave_argmin(bd[m], bj[m], &dist);
+          if (lane == 0) { redd[u * 16 + wave] = dist; redj[u * 16 + wave] = j; }
+        }
+      }
+      __syncthreads();
+      bool ch = false;
+      if (tid < rb) {
+        const int w0 = (tid % G) * (S / 64), w1 = w0 + S / 64;
+        double bdist = redd[tid * 16 + w0];
+        int bjj = redj[tid * 16 + w0];
+        for (int w = w0 + 1; w < w1; ++w) {
+          const double od = redd[tid * 16 + w];
+          const int oj = redj[tid * 16 + w];
+          const bool take = (od < bdist) || (od == bdist && (unsigned)oj < (unsigned)bjj);
+          bdist = take ? od : bdist;
+          bjj = take ? oj : bjj;
+        }
+        const int i = rowidx[tid];
+        const int jl = bjj >= 0 ? bjj : 0;
+        rho[i] = jl;
+        ch = (prev != nullptr) && (prev[i] != jl);
+        rowdist[tid] = bdist;
+      }
+      if (wave == 0) n_changed += (unsigned)__popcll(__ballot(ch));
+      __syncthreads();
+      if (tid == 0)
+        for (int u = 0; u < rb; ++u) e_def += rowdist[u];
+      __syncthreads();
+    }
   }
 
   if (lane == 0) {
@@ -856,7 +857,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     double e = dred[0];
 #pragma unroll
     for (int w = 1; w < W; ++w) e += dred[w];
-    a.e_part[bx] = e;
+    a.e_part[bx] = e + e_def;
   }
 }
 

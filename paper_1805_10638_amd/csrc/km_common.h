@@ -10,7 +10,7 @@ constexpr int kWave = 64;
 constexpr int kMaxK = 4096;          // labels per LDS histogram row in the rank kernel
 constexpr int kMaxD = 256;           // register-resident sample rows in the assignment
 constexpr int kMaxM = 64;            // Anderson history bound
-constexpr int kRankRows = 4096;      // rows per block of the counting sort
+constexpr int kRankRows = 1024;      // rows per block of the counting sort
 constexpr int kSegRows = 512;        // rows per work item of the segmented sum
 constexpr int kTraceRec = 80;        // doubles per trace record
 

@@ -46,27 +46,8 @@ __device__ __forceinline__ void ctl_finish(Ctl* c, int status, bool fb, double* 
   if (rec) rec[11] = stop;
 }
 
-// red: 256 doubles of LDS.  Must be called by all 256 threads of the group.
-__device__ inline void controller_stage(Ctl* c, const double* e_part, int n_part, int stage,
-                                 const CtlTrace& tr, double* red) {
-  const int tid = threadIdx.x;
-  const bool need = (stage == 1) || c->reject;
-  double v = 0.0;
-  if (need)
-    for (int i = tid; i < n_part; i += 256) v += e_part[i];
-  red[tid] = v;
-  const int t_next = c->t + (stage == 1 ? 1 : 0);
-  if (stage == 1 && tr.trace_C) {
-    const int64_t kd = (int64_t)tr.K * tr.d;
-    for (int64_t e = tid; e < kd; e += 256) tr.trace_C[(int64_t)t_next * kd + e] = tr.C_cand[e];
-  }
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  if (tid != 0) return;
-  const double E = red[0];
+// Decisions of one stage on the energy E of the pass (thread 0 only).
+__device__ inline void controller_decide(Ctl* c, double E, int stage, int t_next, const CtlTrace& tr) {
   double* rec = tr.trace_rec ? tr.trace_rec + (int64_t)t_next * kTraceRec : nullptr;
 
   if (stage == 1) {
@@ -140,6 +121,47 @@ __device__ inline void controller_stage(Ctl* c, const double* e_part, int n_part
   c->E1 = Ea;
   c->cnt_changed[0] = 0;
   c->cnt_flagged[0] = 0;
+}
+
+// red: 256 doubles of LDS.  Must be called by all 256 threads of the group.
+// The control block is copied into LDS (one 8-byte word per thread), updated
+// there by thread 0 and copied back, so that the decision logic does not
+// wait on a global round trip per field.
+__device__ inline void controller_stage(Ctl* cg, const double* e_part, int n_part, int stage,
+                                        const CtlTrace& tr, double* red) {
+  __shared__ Ctl lc;
+  static_assert(sizeof(Ctl) % 8 == 0, "the control block is copied in 8-byte words");
+  constexpr int kWords = (int)(sizeof(Ctl) / 8);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kWords; i += 256) ((unsigned long long*)&lc)[i] = ((const unsigned long long*)cg)[i];
+  __syncthreads();
+  Ctl* c = &lc;
+  const bool need = (stage == 1) || c->reject;
+  double v = 0.0;
+  if (need) {   // partials tid, tid + 256, ... in order, four loads in flight
+    for (int i0 = tid; i0 < n_part; i0 += 4 * 256) {
+      double q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = i0 + u * 256 < n_part ? e_part[i0 + u * 256] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u * 256 < n_part) v += q[u];
+    }
+  }
+  red[tid] = v;
+  const int t_next = c->t + (stage == 1 ? 1 : 0);
+  if (stage == 1 && tr.trace_C) {
+    const int64_t kd = (int64_t)tr.K * tr.d;
+    for (int64_t e = tid; e < kd; e += 256) tr.trace_C[(int64_t)t_next * kd + e] = tr.C_cand[e];
+  }
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) controller_decide(c, red[0], stage, t_next, tr);
+  __syncthreads();
+  for (int i = tid; i < kWords; i += 256) ((unsigned long long*)cg)[i] = ((const unsigned long long*)&lc)[i];
 }
 
 }  // namespace km

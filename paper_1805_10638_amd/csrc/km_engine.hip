@@ -233,7 +233,7 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   AssignArgs a{};
   a.X = s.X; a.N = s.N; a.d = s.d; a.K = s.K; a.C = w.C_tmp; a.nc = w.nc_tmp;
   a.Cb = gbf ? w.Cb_tmp : nullptr; a.delta = gbf ? w.del_tmp : nullptr;
-  a.lab = w.labels; a.lab_prev = nullptr; a.e_part = w.e_part; a.ctl = w.ctl;
+  a.lab = w.labels; a.lab_prev = nullptr; a.e_part = w.e_part; a.flags = w.flags; a.ctl = w.ctl;
   a.xbf16 = j->xbf; a.gemm_bf16 = gbf; a.shape = 0; a.role = kRolePlain;
   r.plain = a;
   r.cand = a;

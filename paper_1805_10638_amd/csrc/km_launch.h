@@ -21,6 +21,7 @@ struct AssignArgs {
   int* lab;               // label buffers: 3 x N (solver roles) or N (plain role)
   const int* lab_prev;    // plain role: labels to count changes against, or null
   double* e_part;         // per-workgroup energy partials of this pass
+  int* flags;             // N ints: per-wave lists of flagged rows (deferred re-check)
   Ctl* ctl;
   int xbf16;              // X stored as bfloat16
   int gemm_bf16;          // distance GEMM in bfloat16
@@ -134,6 +135,7 @@ struct CombineArgs {
   int K, d, cap;
   float* C_cand; float* nc_cand; uint16_t* Cb_cand; float* delta_cand;
   float* C_fb; float* nc_fb; uint16_t* Cb_fb; float* delta_fb;
+  int* done_out;          // nullable: pinned host slot that receives ctl->done (solver iterations)
 };
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s);
 int combine_grid(int K);

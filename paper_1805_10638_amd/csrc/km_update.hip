@@ -216,47 +216,65 @@ __device__ __forceinline__ void segsum_body(const UpdateArgs& u, int bx) {
   const int k0 = col * 4;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const bool vec = (d % 4) == 0 && k0 + 4 <= d;
-  constexpr int kPf = 8;   // perm indices fetched ahead of the row loads
-  int pidx[kPf];
-  int64_t pbase = p0 + rg;
-#pragma unroll
-  for (int q = 0; q < kPf; ++q) {
-    const int64_t pp = pbase + (int64_t)q * rpp;
-    pidx[q] = pp < p1 ? u.perm[pp] : 0;
-  }
-  for (int64_t p = pbase; p < p1; p += rpp) {
-    const int64_t i = pidx[0];
-#pragma unroll
-    for (int q = 0; q < kPf - 1; ++q) pidx[q] = pidx[q + 1];
-    {
-      const int64_t pp = p + (int64_t)kPf * rpp;
-      pidx[kPf - 1] = pp < p1 ? u.perm[pp] : 0;
-    }
+  // Rows p, p + rpp, ... of the item, four per step: the four row loads are
+  // issued together and the permutation entries of the next step are fetched
+  // meanwhile; the rows are still added in order.
+  constexpr int kU = 4;
+  auto row4 = [&](int64_t i, bool ok, double (&v)[4]) {
+    v[0] = v[1] = v[2] = v[3] = 0.0;
+    if (!ok) return;
     if (XBF) {   // uniform per workgroup
       const uint16_t* xr = (const uint16_t*)u.X + i * d;
       if (vec) {
-        const uint2 v = *(const uint2*)(xr + k0);
-        acc[0] += (double)__uint_as_float(v.x << 16);
-        acc[1] += (double)__uint_as_float(v.x & 0xFFFF0000u);
-        acc[2] += (double)__uint_as_float(v.y << 16);
-        acc[3] += (double)__uint_as_float(v.y & 0xFFFF0000u);
+        const uint2 t = *(const uint2*)(xr + k0);
+        v[0] = (double)__uint_as_float(t.x << 16);
+        v[1] = (double)__uint_as_float(t.x & 0xFFFF0000u);
+        v[2] = (double)__uint_as_float(t.y << 16);
+        v[3] = (double)__uint_as_float(t.y & 0xFFFF0000u);
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (k0 + e < d) acc[e] += (double)__uint_as_float(((uint32_t)xr[k0 + e]) << 16);
+          if (k0 + e < d) v[e] = (double)__uint_as_float(((uint32_t)xr[k0 + e]) << 16);
       }
     } else {
       const float* xr = (const float*)u.X + i * d;
       if (vec) {
-        const float4 v = *(const float4*)(xr + k0);
-        acc[0] += (double)v.x;
-        acc[1] += (double)v.y;
-        acc[2] += (double)v.z;
-        acc[3] += (double)v.w;
+        const float4 t = *(const float4*)(xr + k0);
+        v[0] = (double)t.x;
+        v[1] = (double)t.y;
+        v[2] = (double)t.z;
+        v[3] = (double)t.w;
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (k0 + e < d) acc[e] += (double)xr[k0 + e];
+          if (k0 + e < d) v[e] = (double)xr[k0 + e];
+      }
+    }
+  };
+  const int64_t pbase = p0 + rg;
+  int nxt[kU];
+#pragma unroll
+  for (int q = 0; q < kU; ++q) {
+    const int64_t pp = pbase + (int64_t)q * rpp;
+    nxt[q] = pp < p1 ? u.perm[pp] : 0;
+  }
+  for (int64_t p = pbase; p < p1; p += (int64_t)kU * rpp) {
+    int cur[kU];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) cur[q] = nxt[q];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) {
+      const int64_t pp = p + (int64_t)(kU + q) * rpp;
+      nxt[q] = pp < p1 ? u.perm[pp] : 0;
+    }
+    double v[kU][4];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) row4(cur[q], p + (int64_t)q * rpp < p1, v[q]);
+#pragma unroll
+    for (int q = 0; q < kU; ++q) {
+      if (p + (int64_t)q * rpp < p1) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += v[q][e];
       }
     }
   }
@@ -361,8 +379,17 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs& f, int bx, int
     const int n = f.counts[j];
     const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
     const int k = (int)(e - (int64_t)j * d);
+    // item partials in order, eight loads in flight
     double sum = 0.0;
-    for (int it = i0; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
+    int it = i0;
+    for (; it + 8 <= i1; it += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = f.partial[(int64_t)(it + q) * d + k];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sum += v[q];
+    }
+    for (; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
     if (f.mode == kFinG) {
       f.C_out[e] = (float)(n > 0 ? sum / (double)n : (double)f.C_in[e]);
       continue;

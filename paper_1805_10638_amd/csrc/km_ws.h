@@ -27,6 +27,7 @@ struct Ws {
   int* labels = nullptr;        // 3 x N
   int* lrank = nullptr;         // N
   int* perm = nullptr;          // N
+  int* flags = nullptr;         // N (flagged rows of an assignment pass)
   int* blockcount = nullptr;    // nblk x K
   int* counts = nullptr;        // K
   int* seg_start = nullptr;     // K + 1
@@ -70,6 +71,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const size_t o_lab = take(3 * N * 4);
   const size_t o_lr = take(N * 4);
   const size_t o_perm = take(N * 4);
+  const size_t o_flags = take(N * 4);
   const size_t o_bc = take((size_t)nblk * s.K * 4);
   const size_t o_cnt = take((size_t)s.K * 4);
   const size_t o_ss = take((size_t)(s.K + 1) * 4);
@@ -102,6 +104,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
     w->labels = (int*)(b + o_lab);
     w->lrank = (int*)(b + o_lr);
     w->perm = (int*)(b + o_perm);
+    w->flags = (int*)(b + o_flags);
     w->blockcount = (int*)(b + o_bc);
     w->counts = (int*)(b + o_cnt);
     w->seg_start = (int*)(b + o_ss);
