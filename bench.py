@@ -30,7 +30,7 @@ WORKLOAD = dict(N=1_000_000, d=32, K=256, m_max=10, tol=1e-6, max_iter=500)
 # WRITE_SIZE, each scaled by its reading for a plain copy of known size
 # (profiles/assign_f32_N1M_d32_K256_traffic.md).  Set to None when the kernel
 # changes until it is measured again.
-TRAFFIC_BYTES_PER_LAUNCH = 136249831
+TRAFFIC_BYTES_PER_LAUNCH = 136252676
 
 
 def parse():
@@ -41,13 +41,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time budget of the oracle baseline sample")
-    ap.add_argument("--workload", choices=["plain", "precision", "batched", "served", "studies"],
+    ap.add_argument("--workload", choices=["plain", "precision", "batched", "served", "studies", "update"],
                     default="plain",
                     help="plain: N=1e6 d=32 K=256 float32 (default line); precision: "
                          "N=4e6 d=128 K=1024 bfloat16-stored X, float32 vs bfloat16 GEMM; batched: "
                          "512 uneven instances in one engine vs one at a time; served: Poisson arrivals "
                          "(200 jobs/s) through the continuous-batching engine vs a FIFO loop; studies: fixed vs "
-                         "dynamic m and Lloyd vs Anderson on synthetic mixtures")
+                         "dynamic m and Lloyd vs Anderson on synthetic mixtures; update: the update step "
+                         "against the HBM roofline at N=1e7 d=16 K=256 and N=1e6 d=32 K=256")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of instances")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
@@ -120,6 +121,9 @@ def main():
         return
     if args.workload == "studies":
         studies_workload(args, km, synth, torch)
+        return
+    if args.workload == "update":
+        update_workload(args, km, synth, torch)
         return
 
     w = WORKLOAD
@@ -215,6 +219,42 @@ def main():
 
 
 BF16_MFMA_PEAK_TFLOPS = 2516.6   # MI355X dense bf16 matrix peak
+
+
+def update_workload(args, km, synth, torch):
+    """The update step (Eq. (4): counting sort by label, float64 segmented sums,
+    means) against the HBM roofline.  kmeans_g at N=1e7, d=16, K=256 (X is
+    640 MB, more than the 256 MB last-level cache) and at N=1e6, d=32, K=256,
+    each applied repeatedly at the centroids of one Lloyd step from a seeded
+    random-sample start; device time of the update from HIP events.
+    Algorithmic bytes per update: N*d*4 (X read once) + 16*N (labels, ranks,
+    permutation) + 8*K*d (float64 sums)."""
+    res = {}
+    reps = max(3, args.steps)
+    for N, d, K in ((10_000_000, 16, 256), (1_000_000, 32, 256)):
+        X, C0 = synth.device_instance(N, d, K, seed=0)
+        ctx = km.Context(0)
+        ctx.set_timing(True)
+        _, C, _, _ = km.kmeans_g(X, C0, ctx=ctx)
+        upd, asg = [], []
+        for _ in range(reps):
+            _, _, _, st = km.kmeans_g(X, C, ctx=ctx)
+            upd.append(st.update_ms)
+            asg.append(st.assign_ms)
+        u_ms = statistics.median(upd)
+        nbytes = N * d * 4 + 16 * N + 8 * K * d
+        gbs = nbytes / (u_ms / 1e3) / 1e9
+        res[f"N{N}_d{d}_K{K}"] = {"update_ms": u_ms, "assign_ms": statistics.median(asg),
+                                  "algorithmic_bytes": nbytes, "achieved_GBs": gbs,
+                                  "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS, "reps": reps}
+        del X, C0, C, ctx
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "update step: algorithmic bytes per second vs HBM peak", "unit": "GB/s",
+                      "data": "synthetic", "dtype": "f64 sums of f32 rows",
+                      "config": {"workload": "kmeans_g on gaussian mixtures (centres N(0,25I), std U[0.5,2], "
+                                             "Dirichlet(1) weights), random-sample init, one Lloyd step, then "
+                                             "repeated G at those centroids"},
+                      "results": res}), flush=True)
 
 
 def precision_workload(args, km, synth, torch):

@@ -81,7 +81,8 @@ const char *km_last_error(const km_ctx *ctx);
 int km_version(void);
 
 /* Record HIP events around every assignment-kernel launch of kmeans_solve
- * (1) or not (0, default).  Results appear in km_solve_stats.assign_ms. */
+ * (1) or not (0, default).  Results appear in km_solve_stats.assign_ms, and
+ * for kmeans_g in km_g_stats.assign_ms / update_ms. */
 km_status km_set_timing(km_ctx *ctx, int enable);
 
 /* Tile shape of the assignment kernel for later calls on this context whose
@@ -101,6 +102,9 @@ typedef struct {
   int64_t changed;         /* rows whose label differs from rho_prev (0 if rho_prev NULL) */
   int64_t flagged_rows;    /* rows re-checked with float64 differences */
   int32_t empty_clusters;  /* clusters with no sample (centroid kept, reading R9) */
+  float assign_ms;         /* device time of the assignment kernel, -1 unless timing is on */
+  float update_ms;         /* device time of the update step (counting sort, segmented
+                              sums, means), -1 unless timing is on */
 } km_g_stats;
 
 /*

@@ -34,7 +34,7 @@ class KMError(RuntimeError):
 
 class _GStats(ct.Structure):
     _fields_ = [("changed", ct.c_int64), ("flagged_rows", ct.c_int64),
-                ("empty_clusters", ct.c_int32)]
+                ("empty_clusters", ct.c_int32), ("assign_ms", ct.c_float), ("update_ms", ct.c_float)]
 
 
 class _Opts(ct.Structure):
@@ -87,6 +87,8 @@ class GStats:
     changed: int
     flagged_rows: int
     empty_clusters: int
+    assign_ms: float = -1.0   # device times from HIP events when Context.set_timing(True)
+    update_ms: float = -1.0
 
 
 @dataclass
@@ -289,7 +291,8 @@ def kmeans_g(X: torch.Tensor, C: torch.Tensor, prec="f32", rho_prev: torch.Tenso
                           ct.c_void_p(rho.data_ptr()), ct.c_void_p(C_out.data_ptr()),
                           ct.byref(E), ct.byref(gs))
     ctx._check(st, "kmeans_g")
-    return rho, C_out, E.value, GStats(gs.changed, gs.flagged_rows, gs.empty_clusters)
+    return rho, C_out, E.value, GStats(gs.changed, gs.flagged_rows, gs.empty_clusters, gs.assign_ms,
+                                       gs.update_ms)
 
 
 def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float = 1e-6,

@@ -191,9 +191,12 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->w.e_part; a.flags = c->w.flags; a.ctl = c->w.ctl;
   a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[0], st_), "hipEventRecord");
   HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[0], st_), "hipEventRecord");
   const int grid = assign_grid(a);
   HIP_TRY(c, launch_reduce_energy(c->w.e_part, grid, c->w.e_out, st_), "energy");
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[1], st_), "hipEventRecord");
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
   u.lab = rho; u.lab_from_ctl = 0; u.lrank = c->w.lrank; u.blockcount = c->w.blockcount;
@@ -207,6 +210,7 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
   f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
   HIP_TRY(c, launch_finalize(f, st_), "finalize");
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[1], st_), "hipEventRecord");
   HIP_TRY(c, hipMemcpyAsync(c->scal_host, c->w.e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
   HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
   HIP_TRY(c, hipStreamSynchronize(st_), "hipStreamSynchronize");
@@ -215,6 +219,14 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
     st->changed = rho_prev ? (int64_t)c->ctl_host->cnt_changed[0] : 0;
     st->flagged_rows = (int64_t)c->ctl_host->cnt_flagged[0];
     st->empty_clusters = c->ctl_host->empty;
+    st->assign_ms = st->update_ms = -1.f;
+    if (c->timing) {
+      if (hipEventElapsedTime(&st->assign_ms, c->ta[0], c->tb[0]) != hipSuccess ||
+          hipEventElapsedTime(&st->update_ms, c->ta[1], c->tb[1]) != hipSuccess) {
+        clear_pending_error();
+        st->assign_ms = st->update_ms = -1.f;
+      }
+    }
   }
   if (!isfinite(*E)) return fail(c, KM_ENONFINITE, "energy is not finite");
   return KM_OK;

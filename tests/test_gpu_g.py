@@ -211,8 +211,9 @@ def test_solve_bf16_gemm_matches_f32():
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_g_many_flags_streamed_centroids(prec):
     """Large common offset with K too large for LDS residency: most rows are
-    flagged, so the workgroup re-check queue fills and overflows into the
-    per-wave path; every label must still be the exact argmin."""
+    flagged, so every workgroup re-checks many batches of listed rows against
+    several staged centroid chunks; every label must still be the exact
+    argmin."""
     km = _lib()
     rng = np.random.default_rng(11)
     # bf16 keeps the offset small enough that the noise is not rounded away
@@ -224,3 +225,22 @@ def test_g_many_flags_streamed_centroids(prec):
     r = check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
     assert st.flagged_rows > 1000
     assert r["mismatch"] <= r["near_ties"]
+
+
+def test_g_phase_timing():
+    """With timing on, kmeans_g reports positive device times for the
+    assignment and the update; with timing off both are -1; results are the
+    same either way."""
+    km = _lib()
+    X = _mixture(50000, 16, 64, seed=21)
+    C = synth.init_centroids(X, 64, seed=2)
+    Xt, Ct = x_tensor(X), dev(C)
+    ctx = km.Context(0)
+    r0 = km.kmeans_g(Xt, Ct, ctx=ctx)
+    assert r0[3].assign_ms == -1.0 and r0[3].update_ms == -1.0
+    ctx.set_timing(True)
+    r1 = km.kmeans_g(Xt, Ct, ctx=ctx)
+    ctx.set_timing(False)
+    assert r1[3].assign_ms > 0.0 and r1[3].update_ms > 0.0
+    assert np.array_equal(r0[0].cpu().numpy(), r1[0].cpu().numpy())
+    assert np.array_equal(r0[1].cpu().numpy().view(np.uint32), r1[1].cpu().numpy().view(np.uint32))
