@@ -143,12 +143,13 @@ __device__ __forceinline__ int exact_argmin_lds(const float* xrow, const float* 
 }
 
 // LDS layout.  HEAD: workgroup scratch (maxima: 32 floats; energy partials:
-// 16 doubles; flagged-row counts: 16 ints, padded) and one staged row per wave
+// 16 doubles; flagged-row list lengths: 2 x 16 ints; re-checked counts: 16
+// ints, padded) and one staged row per wave
 // for immediate re-checks (16 x DP floats).  AREA: the centroid chunk and its
 // -||c||^2/2 values during the row groups; after the last row group the
 // deferred re-check reuses it for RX sample rows (float64), per-wave
 // reduction slots and float32 centroid rows.
-constexpr int kAssignScratch = 128 + 128 + 128;
+constexpr int kAssignScratch = 128 + 128 + 128 + 128;
 
 // LB: bytes of LDS a workgroup may use for the centroid chunk.
 template <int KS, bool GBF, int LB>
@@ -268,14 +269,20 @@ __device__ __forceinline__ float bf_elem(const i16x8& v, int e) {
 }
 
 // Waves per SIMD the register allocation must leave room for: 16-wave
-// workgroups need 4; small float32 tiles run best at 4 (latency hiding);
+// workgroups need 4; small float32 tiles run best at 4 (latency hiding),
+// float32 tiles up to 32 dims x blocks at 3 (VGPRs come in blocks of 8, so
+// 169 of them would already leave room for only 2);
 // wide tiles (float32 rows on the bf16 GEMM, 8 sample blocks, d > 128 in
 // bf16, more than 64 dims x blocks in float32) get the whole register file;
 // the rest run 2 waves per SIMD.
 template <int KS, int SB, int W, bool XBF, bool GBF>
 constexpr int assign_wpe() {
   if (W >= 16) return 4;
-  if (!GBF) return (KS * SB <= 16 && SB <= 2) ? 4 : (KS * SB > 64 ? 1 : 2);
+  if (!GBF) {
+    if (KS * SB <= 16 && SB <= 2) return 4;
+    if (KS * SB <= 32 && KS <= 16) return 3;   // fits 168 VGPRs: 3 waves per SIMD
+    return KS * SB > 64 ? 1 : 2;
+  }
   if (!XBF || KS >= 48 || SB >= 8) return 1;
   return 2;
 }
@@ -320,12 +327,15 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   const bool resident = kchunk >= Kpad;
   float* fred = (float*)smem_raw;                            // 2 x 16 floats
   double* dred = (double*)(smem_raw + 128);                  // W doubles
-  int* wcnt = (int*)(smem_raw + 256);                        // W flagged-row counts
+  int* wcnt = (int*)(smem_raw + 256);                        // 2 x 16 list lengths
+  int* pw = (int*)(smem_raw + 384);                          // 16 re-checked counts
   float* xrows = (float*)(smem_raw + kAssignScratch);        // 16 x DP floats
   unsigned char* area = smem_raw + T::HEAD;
   float* Cs = (float*)area;                                  // kchunk x LD (f32 path)
   uint16_t* Cbs = (uint16_t*)area;                           // kchunk x LDB (bf16 path)
   float* ncs = (float*)(area + (size_t)kchunk * T::ROW_BYTES);
+
+  if (tid < 16) pw[tid] = 0;   // published by the barrier below
 
   // max_j ||c_j||^2 and max_j r_j over the real centroids
   float mx = 0.f, mdel = 0.f;
@@ -447,9 +457,11 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   }
   // Flagged rows.  With float32 centroids resident in LDS a wave re-checks a
   // row at once from the LDS copy (xrow: its staged row).  Otherwise each
-  // wave appends the rows it flags to its own list, and after the last row
-  // group the workgroup re-checks all of them together (below), so the
-  // centroids are read once per batch of rows rather than once per row.
+  // wave appends the rows it flags to its own list, and the workgroup
+  // re-checks them together in batches (recheck_batches below): at the end
+  // of every row group when a full batch is pending and the centroids are
+  // streamed, and after the last row group; the centroids are read once per
+  // batch of rows rather than once per row.
   // The p-th row a wave flags is stored in the slot of the p-th row it owns
   // (its rows of row groups bx, bx + gx, ...), so every list fits in N ints
   // and its order is fixed.
@@ -471,6 +483,138 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   // dims have no registers for a second operand buffer (it would spill)
   constexpr bool kPairOps = !(XLO && KS >= 64) && !(!GBF && KS >= 48);
 
+  // Re-check of the listed rows: float64 direct differences to all K
+  // centroids (dimensions in order), the lowest distance wins, ties to the
+  // lowest index.  Rows go in batches of RX (staged as float64), centroids in
+  // chunks of def_rows(K) float32 rows.  Thread t scores centroid slots
+  // t % S, t % S + S, ... of a chunk against rows rg, rg + G, ... of the
+  // batch (rg = t / S, G = NT / S >= 2; S is a multiple of 64, so a wave
+  // shares its rows and reduces them with shuffles).  The energy terms of the
+  // batch are added in row order by thread 0.  Called by all threads after a
+  // barrier that published the waves' list lengths wc; pw[w] counts the rows
+  // of wave w's list already re-checked, and batches take pending rows with
+  // the waves in order, so the batches depend on the data only.  Without
+  // final only full batches run.
+  double e_def = 0.0;
+  // rows per batch: the layout's RX, or 8 where registers are short
+  constexpr int RX = kShortRegs && T::RX > 8 ? 8 : T::RX;
+  constexpr int MR = RX / 2;
+  constexpr bool kInterleave = GBF && !(XLO && KS >= 64);
+  auto recheck_batches = [&](const int* wc, bool final) {
+    double* xb = (double*)area;                          // RX x DP
+    double* redd = (double*)(area + RX * DP * 8);        // RX x 16 waves
+    int* redj = (int*)(redd + RX * 16);                  // RX x 16 waves
+    int* rowidx = redj + RX * 16;                        // RX
+    double* rowdist = (double*)(rowidx + RX);            // RX
+    float* cc = (float*)(area + T::DEF_FIXED);           // def_rows(K) x LD
+    const int crows = T::def_rows(K);
+    const int want = crows < NT / 2 ? crows : NT / 2;
+    int S = 64;
+    while (S < want) S <<= 1;
+    const int G = NT / S;
+    const int cs = tid % S, rg = tid / S;
+    int pending = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) pending += wc[w] - pw[w];
+    while (pending >= RX || (final && pending > 0)) {
+      const int rb = pending < RX ? pending : RX;
+      if (tid < rb) {   // the tid-th pending row, waves in order
+        int r = tid, w = 0;
+        while (r >= wc[w] - pw[w]) { r -= wc[w] - pw[w]; ++w; }
+        const int q = pw[w] + r;
+        const int64_t own = (bx + (int64_t)(q / (16 * SB)) * gx) * group_rows + w * (16 * SB) + q % (16 * SB);
+        rowidx[tid] = a.flags[own];
+      }
+      __syncthreads();
+      for (int e = tid; e < RX * DP; e += NT) {
+        const int u = e / DP, k = e - u * DP;
+        double v = 0.0;
+        if (u < rb && k < d) v = (double)ld_x(a.X, (int64_t)rowidx[u] * d + k, XBF);
+        xb[e] = v;
+      }
+      double bd[MR];
+      int bj[MR];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) { bd[m] = __builtin_inf(); bj[m] = -1; }
+      for (int c0 = 0; c0 < K; c0 += crows) {
+        const int rows = (K - c0) < crows ? (K - c0) : crows;
+        __syncthreads();
+        stage_f32(cc, c0, rows);
+        __syncthreads();
+        for (int jj = cs; jj < rows; jj += S) {
+          const float* cr = cc + jj * LD;
+          const int j = c0 + jj;
+#pragma unroll
+          for (int m0 = 0; m0 < MR; m0 += 4) {
+            if (rg + G * m0 >= rb) break;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < DP; k += 4) {
+              const float4 c4 = *(const float4*)(cr + k);
+              const double cx = c4.x, cy = c4.y, cz = c4.z, cw = c4.w;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int u = rg + G * (m0 + r);
+                if (u < rb) {
+                  const double* xr = xb + u * DP + k;
+                  double df = xr[0] - cx; acc[r] = fma(df, df, acc[r]);
+                  df = xr[1] - cy; acc[r] = fma(df, df, acc[r]);
+                  df = xr[2] - cz; acc[r] = fma(df, df, acc[r]);
+                  df = xr[3] - cw; acc[r] = fma(df, df, acc[r]);
+                }
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (acc[r] < bd[m0 + r]) { bd[m0 + r] = acc[r]; bj[m0 + r] = j; }
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int u = rg + G * m;
+        if (u < rb) {
+          double dist;
+          const int j = wave_argmin(bd[m], bj[m], &dist);
+          if (lane == 0) { redd[u * 16 + wave] = dist; redj[u * 16 + wave] = j; }
+        }
+      }
+      __syncthreads();
+      bool ch = false;
+      if (tid < rb) {
+        const int w0 = (tid % G) * (S / 64), w1 = w0 + S / 64;
+        double bdist = redd[tid * 16 + w0];
+        int bjj = redj[tid * 16 + w0];
+        for (int w = w0 + 1; w < w1; ++w) {
+          const double od = redd[tid * 16 + w];
+          const int oj = redj[tid * 16 + w];
+          const bool take = (od < bdist) || (od == bdist && (unsigned)oj < (unsigned)bjj);
+          bdist = take ? od : bdist;
+          bjj = take ? oj : bjj;
+        }
+        const int i = rowidx[tid];
+        const int jl = bjj >= 0 ? bjj : 0;
+        rho[i] = jl;
+        ch = (prev != nullptr) && (prev[i] != jl);
+        rowdist[tid] = bdist;
+      }
+      if (wave == 0) n_changed += (unsigned)__popcll(__ballot(ch));
+      __syncthreads();
+      if (tid == 0) {
+        for (int u = 0; u < rb; ++u) e_def += rowdist[u];
+        int c = rb;   // consume the batch from the waves' pending ranges
+        for (int w = 0; w < W && c > 0; ++w) {
+          const int av = wc[w] - pw[w];
+          const int take = av < c ? av : c;
+          pw[w] += take;
+          c -= take;
+        }
+      }
+      __syncthreads();
+      pending -= rb;
+    }
+  };
+
+  int nb = 0;   // row-group boundaries passed (selects the wc buffer)
   for (int64_t grp = bx; grp < groups; grp += gx) {
     // Sample rows of this wave, kept in registers.
     const int64_t row0 = grp * group_rows + (int64_t)wave * (16 * SB);
@@ -727,124 +871,24 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       e_lane += mine ? term_s[s] : 0.0;
     }
     e_wave += wave_sum(e_lane);
+    // With streamed centroids the chunk area is free here: re-check full
+    // batches now, so that the re-check overlaps other workgroups' MFMA work
+    // instead of piling up after the last row group (bf16 GEMM kernels; in
+    // the float32 kernels the extra live registers of this call would spill).
+    if (kInterleave && defer && !resident) {
+      int* wc = wcnt + (nb & 1) * 16;   // two buffers: a slow wave may still read the previous one
+      if (lane == 0) wc[wave] = nfl;
+      __syncthreads();
+      recheck_batches(wc, false);
+      ++nb;
+    }
   }
 
-  // Deferred re-check of the listed rows: float64 direct differences to all
-  // K centroids (dimensions in order), the lowest distance wins, ties to the
-  // lowest index.  Rows go in batches of RX (staged as float64), centroids in
-  // chunks of def_rows(K) float32 rows.  Thread t scores centroid slots
-  // t % S, t % S + S, ... of a chunk against rows rg, rg + G, ... of the
-  // batch (rg = t / S, G = NT / S >= 2; S is a multiple of 64, so a wave
-  // shares its rows and reduces them with shuffles).  The energy terms of the
-  // batch are added in row order by thread 0.
-  double e_def = 0.0;
-  if (defer) {
-    if (lane == 0) wcnt[wave] = nfl;
+  if (defer) {   // the remaining listed rows
+    int* wc = wcnt + (nb & 1) * 16;
+    if (lane == 0) wc[wave] = nfl;
     __syncthreads();
-    int R = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) R += wcnt[w];
-    // rows per batch: the layout's RX, or 8 where registers are short
-    constexpr int RX = kShortRegs && T::RX > 8 ? 8 : T::RX;
-    constexpr int MR = RX / 2;
-    double* xb = (double*)area;                          // RX x DP
-    double* redd = (double*)(area + RX * DP * 8);        // RX x 16 waves
-    int* redj = (int*)(redd + RX * 16);                  // RX x 16 waves
-    int* rowidx = redj + RX * 16;                        // RX
-    double* rowdist = (double*)(rowidx + RX);            // RX
-    float* cc = (float*)(area + T::DEF_FIXED);           // def_rows(K) x LD
-    const int crows = T::def_rows(K);
-    const int want = crows < NT / 2 ? crows : NT / 2;
-    int S = 64;
-    while (S < want) S <<= 1;
-    const int G = NT / S;
-    const int cs = tid % S, rg = tid / S;
-    for (int b0 = 0; b0 < R; b0 += RX) {
-      const int rb = (R - b0) < RX ? (R - b0) : RX;
-      if (tid < rb) {
-        int r = b0 + tid, w = 0;
-        while (r >= wcnt[w]) { r -= wcnt[w]; ++w; }
-        const int64_t own = (bx + (int64_t)(r / (16 * SB)) * gx) * group_rows + w * (16 * SB) + r % (16 * SB);
-        rowidx[tid] = a.flags[own];
-      }
-      __syncthreads();
-      for (int e = tid; e < RX * DP; e += NT) {
-        const int u = e / DP, k = e - u * DP;
-        double v = 0.0;
-        if (u < rb && k < d) v = (double)ld_x(a.X, (int64_t)rowidx[u] * d + k, XBF);
-        xb[e] = v;
-      }
-      double bd[MR];
-      int bj[MR];
-#pragma unroll
-      for (int m = 0; m < MR; ++m) { bd[m] = __builtin_inf(); bj[m] = -1; }
-      for (int c0 = 0; c0 < K; c0 += crows) {
-        const int rows = (K - c0) < crows ? (K - c0) : crows;
-        __syncthreads();
-        stage_f32(cc, c0, rows);
-        __syncthreads();
-        for (int jj = cs; jj < rows; jj += S) {
-          const float* cr = cc + jj * LD;
-          const int j = c0 + jj;
-#pragma unroll
-          for (int m0 = 0; m0 < MR; m0 += 4) {
-            if (rg + G * m0 >= rb) break;
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int k = 0; k < DP; k += 4) {
-              const float4 c4 = *(const float4*)(cr + k);
-              const double cx = c4.x, cy = c4.y, cz = c4.z, cw = c4.w;
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int u = rg + G * (m0 + r);
-                if (u < rb) {
-                  const double* xr = xb + u * DP + k;
-                  double df = xr[0] - cx; acc[r] = fma(df, df, acc[r]);
-                  df = xr[1] - cy; acc[r] = fma(df, df, acc[r]);
-                  df = xr[2] - cz; acc[r] = fma(df, df, acc[r]);
-                  df = xr[3] - cw; acc[r] = fma(df, df, acc[r]);
-                }
-              }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (acc[r] < bd[m0 + r]) { bd[m0 + r] = acc[r]; bj[m0 + r] = j; }
-          }
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < MR; ++m) {
-        const int u = rg + G * m;
-        if (u < rb) {
-          double dist;
-          const int j = wave_argmin(bd[m], bj[m], &dist);
-          if (lane == 0) { redd[u * 16 + wave] = dist; redj[u * 16 + wave] = j; }
-        }
-      }
-      __syncthreads();
-      bool ch = false;
-      if (tid < rb) {
-        const int w0 = (tid % G) * (S / 64), w1 = w0 + S / 64;
-        double bdist = redd[tid * 16 + w0];
-        int bjj = redj[tid * 16 + w0];
-        for (int w = w0 + 1; w < w1; ++w) {
-          const double od = redd[tid * 16 + w];
-          const int oj = redj[tid * 16 + w];
-          const bool take = (od < bdist) || (od == bdist && (unsigned)oj < (unsigned)bjj);
-          bdist = take ? od : bdist;
-          bjj = take ? oj : bjj;
-        }
-        const int i = rowidx[tid];
-        const int jl = bjj >= 0 ? bjj : 0;
-        rho[i] = jl;
-        ch = (prev != nullptr) && (prev[i] != jl);
-        rowdist[tid] = bdist;
-      }
-      if (wave == 0) n_changed += (unsigned)__popcll(__ballot(ch));
-      __syncthreads();
-      if (tid == 0)
-        for (int u = 0; u < rb; ++u) e_def += rowdist[u];
-      __syncthreads();
-    }
+    recheck_batches(wc, true);
   }
 
   if (lane == 0) {

@@ -72,7 +72,8 @@ struct UpdateArgs {
   int gated;              // 1: skip when ctl->done
 };
 int update_max_items(int64_t N, int K);
-int update_rank_blocks(int64_t N);
+// blockcount entries a workspace for (N, K) must hold: enough for any K' <= K
+size_t update_blockcount_ints(int64_t N, int K);
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s);
 // workgroups of update kernel `which` (0 rank, 1 scan, 2 scatter, 3 segsum)
 int update_grid(const UpdateArgs& u, int which);

@@ -29,17 +29,16 @@ __device__ __forceinline__ const int* labels_of(const UpdateArgs& u) {
 }
 
 // ---------------------------------------------------------------------------
-// 1. ranks within blocks of kRankRows rows
+// 1. ranks within blocks of rank_rows(K) rows
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void rank_body(const UpdateArgs& u, int bx) {
-  if (u.gated && u.ctl->done) return;
-  __shared__ int cnt[4][kMaxK];
+template <int RR>
+__device__ __forceinline__ void rank_rows_body(const UpdateArgs& u, int bx, int (&cnt)[4][kMaxK]) {
   const int* L = labels_of(u);
   const int K = u.K;
-  const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
+  const int nblk = (int)((u.N + RR - 1) / RR);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  constexpr int kChunks = kRankRows / 256;   // 64-row chunks per wave
-  const int64_t base = (int64_t)bx * kRankRows + (int64_t)w * (kChunks * 64);
+  constexpr int kChunks = RR / 256;   // 64-row chunks per wave
+  const int64_t base = (int64_t)bx * RR + (int64_t)w * (kChunks * 64);
   int labs[kChunks], rk[kChunks];
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
@@ -90,6 +89,13 @@ __device__ __forceinline__ void rank_body(const UpdateArgs& u, int bx) {
   }
 }
 
+__device__ __forceinline__ void rank_body(const UpdateArgs& u, int bx) {
+  if (u.gated && u.ctl->done) return;
+  __shared__ int cnt[4][kMaxK];
+  if (rank_rows(u.K) == kRankRowsLargeK) rank_rows_body<kRankRowsLargeK>(u, bx, cnt);
+  else rank_rows_body<kRankRowsSmallK>(u, bx, cnt);
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup-wide exclusive scan of one int per thread (256 threads).
 // ---------------------------------------------------------------------------
@@ -110,7 +116,7 @@ __device__ __forceinline__ void scan_body(const UpdateArgs& u, int bx) {
   __shared__ int wsum[4];
   __shared__ int carry;
   const int j = bx;
-  const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
+  const int nblk = update_rank_blocks(u.N, u.K);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int* row = u.blockcount + (int64_t)j * nblk;
   if (tid == 0) carry = 0;
@@ -184,10 +190,10 @@ __device__ __forceinline__ void scatter_body(const UpdateArgs& u, int bx) {
   const int* L = labels_of(u);
   const int64_t i = (int64_t)bx * 256 + threadIdx.x;
   if (i >= u.N) return;
-  const int nblk = (int)((u.N + kRankRows - 1) / kRankRows);
+  const int nblk = update_rank_blocks(u.N, u.K);
   int lab = L[i];
   if (lab < 0 || lab >= u.K) lab = 0;
-  const int64_t b = i / kRankRows;
+  const int64_t b = i / rank_rows(u.K);
   const int64_t pos = (int64_t)u.seg_start[lab] + u.blockcount[(int64_t)lab * nblk + b] + u.lrank[i];
   if (pos >= 0 && pos < u.N) u.perm[pos] = (int)i;
 }
@@ -289,7 +295,12 @@ __device__ __forceinline__ void segsum_body(const UpdateArgs& u, int bx) {
   }
 }
 
-int update_rank_blocks(int64_t N) { return (int)((N + kRankRows - 1) / kRankRows); }
+size_t update_blockcount_ints(int64_t N, int K) {
+  const int ks = K < kRankSplitK ? K : kRankSplitK;
+  const size_t a = (size_t)update_rank_blocks(N, ks) * ks;
+  const size_t b = (size_t)update_rank_blocks(N, K) * K;
+  return a > b ? a : b;
+}
 int update_max_items(int64_t N, int K) { return (int)((N + kSegRows - 1) / kSegRows) + K; }
 
 __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) { rank_body(u, blockIdx.x); }
@@ -320,7 +331,7 @@ __global__ __launch_bounds__(256) void k_segsum_batch(BatchRef<UpdateArgs> t) {
 
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
   if (u.K > kMaxK || u.d > kMaxD) return hipErrorInvalidValue;
-  const int nblk = update_rank_blocks(u.N);
+  const int nblk = update_rank_blocks(u.N, u.K);
   clear_pending_error();
   hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(256), 0, s, u);
   hipLaunchKernelGGL(k_scan, dim3(u.K), dim3(256), 0, s, u);
@@ -343,7 +354,7 @@ hipError_t launch_update_sums_batch(const UpdateBatch& ub, hipStream_t s) {
 
 int update_grid(const UpdateArgs& u, int which) {
   switch (which) {
-    case 0: return update_rank_blocks(u.N);
+    case 0: return update_rank_blocks(u.N, u.K);
     case 1: return u.K;
     case 2: return (int)((u.N + 255) / 256);
     case 3: return u.max_items;

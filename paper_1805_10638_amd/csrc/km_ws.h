@@ -63,7 +63,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const int64_t KD = (int64_t)s.K * s.d;
   const int64_t grid = N / 64 + 1;   // upper bound of an assignment grid
   const int max_items = update_max_items(N, s.K);
-  const int nblk = update_rank_blocks(N);
+  const int nblk = update_rank_blocks(N, s.K);
   const int fin_grid = finalize_grid(KD);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += ws_up(bytes); return o; };
@@ -72,7 +72,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const size_t o_lr = take(N * 4);
   const size_t o_perm = take(N * 4);
   const size_t o_flags = take(N * 4);
-  const size_t o_bc = take((size_t)nblk * s.K * 4);
+  const size_t o_bc = take(update_blockcount_ints(N, s.K) * 4);
   const size_t o_cnt = take((size_t)s.K * 4);
   const size_t o_ss = take((size_t)(s.K + 1) * 4);
   const size_t o_is = take((size_t)(s.K + 1) * 4);
