@@ -115,21 +115,32 @@ __device__ __forceinline__ void scan_body(const UpdateArgs& u, int bx) {
   if (u.gated && u.ctl->done) return;
   __shared__ int wsum[4];
   __shared__ int carry;
+  constexpr int V = 8;   // consecutive block counts per thread and pass
   const int j = bx;
   const int nblk = update_rank_blocks(u.N, u.K);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int* row = u.blockcount + (int64_t)j * nblk;
   if (tid == 0) carry = 0;
   __syncthreads();
-  for (int b0 = 0; b0 < nblk; b0 += 256) {
-    const int b = b0 + tid;
-    const int v = (b < nblk) ? row[b] : 0;
-    const int inc = wave_incl_scan(v, lane);
+  for (int b0 = 0; b0 < nblk; b0 += 256 * V) {
+    const int bb = b0 + tid * V;
+    int v[V], loc = 0;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      v[q] = (bb + q < nblk) ? row[bb + q] : 0;
+      loc += v[q];
+    }
+    const int inc = wave_incl_scan(loc, lane);
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
     int before = carry;
     for (int q = 0; q < w; ++q) before += wsum[q];
-    if (b < nblk) row[b] = before + inc - v;
+    int run = before + inc - loc;   // exclusive prefix of this thread's first entry
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      if (bb + q < nblk) row[bb + q] = run;
+      run += v[q];
+    }
     __syncthreads();
     if (tid == 255) carry = before + inc;
     __syncthreads();
@@ -144,6 +155,7 @@ __device__ __forceinline__ void offsets_body(const UpdateArgs& u) {
   if (u.gated && u.ctl->done) return;
   __shared__ int wc[16], wi[16];
   __shared__ int empty_sh;
+  __shared__ int ist[kMaxK + 1];   // item starts, for the item list below
   const int K = u.K;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int per = (K + 1023) / 1024;
@@ -168,17 +180,23 @@ __device__ __forceinline__ void offsets_body(const UpdateArgs& u) {
     const int ni = (c + kSegRows - 1) / kSegRows;
     u.seg_start[j] = cbase;
     u.item_start[j] = ibase;
-    for (int q = 0; q < ni; ++q)
-      if (ibase + q < u.max_items) u.item_cluster[ibase + q] = j;
+    ist[j] = ibase;
     cbase += c;
     ibase += ni;
   }
+  if (tid == 1023) ist[K] = ibase;
   __syncthreads();
   if (tid == 1023) {
     u.seg_start[K] = cbase;
     u.item_start[K] = ibase;
     u.ctl->total_items = ibase < u.max_items ? ibase : u.max_items;
     u.ctl->empty = empty_sh;
+  }
+  // item list: wave w writes the items of clusters w, w + 16, ... with
+  // consecutive lanes on consecutive items (coalesced stores)
+  for (int j = w; j < K; j += 16) {
+    const int i1 = ist[j + 1] < u.max_items ? ist[j + 1] : u.max_items;
+    for (int q = ist[j] + lane; q < i1; q += 64) u.item_cluster[q] = j;
   }
 }
 
