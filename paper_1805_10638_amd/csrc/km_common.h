@@ -10,15 +10,20 @@ constexpr int kWave = 64;
 constexpr int kMaxK = 4096;          // labels per LDS histogram row in the rank kernel
 constexpr int kMaxD = 256;           // register-resident sample rows in the assignment
 constexpr int kMaxM = 64;            // Anderson history bound
-// Rows per block of the counting sort: 1024 up to 512 clusters, 4096 beyond
-// (each block clears and writes a K-entry histogram, so large K wants fewer
-// blocks).
-constexpr int kRankRowsSmallK = 1024;
-constexpr int kRankRowsLargeK = 4096;
+// Rows per block of the counting sort: 4096 for more than 512 clusters (each
+// block clears and writes a K-entry histogram, so large K wants fewer blocks)
+// or at least 4M rows (longer runs of consecutive permutation entries per
+// cluster, so the scatter's stores coalesce), else 1024 (enough blocks to
+// fill the device).
+constexpr int kRankRowsSmall = 1024;
+constexpr int kRankRowsLarge = 4096;
 constexpr int kRankSplitK = 512;
-__host__ __device__ inline int rank_rows(int K) { return K > kRankSplitK ? kRankRowsLargeK : kRankRowsSmallK; }
+constexpr int64_t kRankSplitN = 4 << 20;
+__host__ __device__ inline int rank_rows(int64_t N, int K) {
+  return (K > kRankSplitK || N >= kRankSplitN) ? kRankRowsLarge : kRankRowsSmall;
+}
 __host__ __device__ inline int update_rank_blocks(int64_t N, int K) {
-  const int rr = rank_rows(K);
+  const int rr = rank_rows(N, K);
   return (int)((N + rr - 1) / rr);
 }
 constexpr int kSegRows = 512;        // rows per work item of the segmented sum

@@ -29,7 +29,7 @@ __device__ __forceinline__ const int* labels_of(const UpdateArgs& u) {
 }
 
 // ---------------------------------------------------------------------------
-// 1. ranks within blocks of rank_rows(K) rows
+// 1. ranks within blocks of rank_rows(N, K) rows
 // ---------------------------------------------------------------------------
 template <int RR>
 __device__ __forceinline__ void rank_rows_body(const UpdateArgs& u, int bx, int (&cnt)[4][kMaxK]) {
@@ -92,8 +92,8 @@ __device__ __forceinline__ void rank_rows_body(const UpdateArgs& u, int bx, int 
 __device__ __forceinline__ void rank_body(const UpdateArgs& u, int bx) {
   if (u.gated && u.ctl->done) return;
   __shared__ int cnt[4][kMaxK];
-  if (rank_rows(u.K) == kRankRowsLargeK) rank_rows_body<kRankRowsLargeK>(u, bx, cnt);
-  else rank_rows_body<kRankRowsSmallK>(u, bx, cnt);
+  if (rank_rows(u.N, u.K) == kRankRowsLarge) rank_rows_body<kRankRowsLarge>(u, bx, cnt);
+  else rank_rows_body<kRankRowsSmall>(u, bx, cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -211,7 +211,7 @@ __device__ __forceinline__ void scatter_body(const UpdateArgs& u, int bx) {
   const int nblk = update_rank_blocks(u.N, u.K);
   int lab = L[i];
   if (lab < 0 || lab >= u.K) lab = 0;
-  const int64_t b = i / rank_rows(u.K);
+  const int64_t b = i / rank_rows(u.N, u.K);
   const int64_t pos = (int64_t)u.seg_start[lab] + u.blockcount[(int64_t)lab * nblk + b] + u.lrank[i];
   if (pos >= 0 && pos < u.N) u.perm[pos] = (int)i;
 }
@@ -314,9 +314,13 @@ __device__ __forceinline__ void segsum_body(const UpdateArgs& u, int bx) {
 }
 
 size_t update_blockcount_ints(int64_t N, int K) {
+  // largest nblk(N', K') * K' over N' <= N, K' <= K: small blocks at the
+  // largest N' below the row split and K' = min(K, split), or large blocks at
+  // N and K
   const int ks = K < kRankSplitK ? K : kRankSplitK;
-  const size_t a = (size_t)update_rank_blocks(N, ks) * ks;
-  const size_t b = (size_t)update_rank_blocks(N, K) * K;
+  const int64_t ns = N < kRankSplitN ? N : kRankSplitN - 1;
+  const size_t a = (size_t)((ns + kRankRowsSmall - 1) / kRankRowsSmall) * ks;
+  const size_t b = (size_t)((N + kRankRowsLarge - 1) / kRankRowsLarge) * K;
   return a > b ? a : b;
 }
 int update_max_items(int64_t N, int K) { return (int)((N + kSegRows - 1) / kSegRows) + K; }
