@@ -1,6 +1,8 @@
 """GPU parity of one application of G (assignment + update, energy) against
 the FP64 oracle, through the C ABI."""
 
+import math
+
 import numpy as np
 import pytest
 
@@ -244,3 +246,64 @@ def test_g_phase_timing():
     assert r1[3].assign_ms > 0.0 and r1[3].update_ms > 0.0
     assert np.array_equal(r0[0].cpu().numpy(), r1[0].cpu().numpy())
     assert np.array_equal(r0[1].cpu().numpy().view(np.uint32), r1[1].cpu().numpy().view(np.uint32))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_g_max_sizes(prec):
+    """Largest supported width and cluster count (d = 256, K = 4096): the
+    widest register tile and centroids streamed through LDS in many chunks,
+    with the deferred re-check over several chunk rounds.  Labels of sampled
+    rows, the energy and all centroids against the oracle."""
+    km = _lib()
+    X = _mixture(8192, 256, 4096, seed=31)
+    if prec == "bf16":
+        X = synth.to_bf16_bits(X)
+    C = synth.init_centroids(X, 4096, seed=4)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C), prec=prec)
+    rows = np.random.default_rng(2).choice(X.shape[0], 400, replace=False)
+    check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E, rows=rows)
+
+
+def test_g_served_large_shape_bf16():
+    """The served large-job shape (d = 96, K = 2048, bfloat16 rows and GEMM)
+    at N = 30,000: sampled labels, energy and centroids against the oracle."""
+    km = _lib()
+    X = synth.to_bf16_bits(_mixture(30000, 96, 2048, seed=33))
+    C = synth.init_centroids(X, 2048, seed=5)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C), prec="bf16")
+    rows = np.random.default_rng(3).choice(X.shape[0], 1000, replace=False)
+    check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E, rows=rows)
+
+
+def test_g_full_size_precision_sampled():
+    """N = 4,000,000, d = 128, K = 1024, bfloat16 rows and GEMM (the precision
+    benchmark's data and launch configuration): labels of 3000 sampled rows
+    against the oracle (outside its near ties), the energy against the
+    oracle's energy of the GPU labels (summed over row chunks), and the
+    centroids of 24 sampled clusters against the oracle's means of their
+    GPU-labelled members."""
+    km = _lib()
+    N, d, K = 4_000_000, 128, 1024
+    Xb, _ = synth.precision(rep=0, n=N, d=d, k=K)
+    C = synth.init_centroids(Xb, K, 1)
+    C64 = C.astype(np.float64)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(Xb), dev(C), prec="bf16")
+    rho = rho.cpu().numpy().astype(np.int64)
+    Cn = Cn.cpu().numpy()
+    rng = np.random.default_rng(4)
+    rows = rng.choice(N, 3000, replace=False)
+    a = ko.assign(x_values(Xb[rows]), C64)
+    bad = np.flatnonzero((a.rho != rho[rows]) & ~a.near_tie)
+    assert bad.size == 0, f"{bad.size} sampled label mismatches outside near ties"
+    step = 500_000
+    Eo = math.fsum(ko.energy(x_values(Xb[s:s + step]), rho[s:s + step], C64) for s in range(0, N, step))
+    assert abs(E - Eo) <= 1e-6 * Eo, (E, Eo)
+    for j in rng.choice(K, 24, replace=False):
+        members = np.flatnonzero(rho == j)
+        if members.size == 0:
+            assert np.array_equal(Cn[j], C[j])
+            continue
+        Xm = x_values(Xb[members])
+        Cj, _ = ko.update(Xm, np.zeros(members.size, dtype=np.int64), C64[j:j + 1])
+        err = np.linalg.norm(Cn[j].astype(np.float64) - Cj[0]) / max(np.linalg.norm(Cj[0]), 1.0)
+        assert err <= 1e-5, (j, err)
