@@ -222,13 +222,15 @@ BF16_MFMA_PEAK_TFLOPS = 2516.6   # MI355X dense bf16 matrix peak
 
 
 def update_workload(args, km, synth, torch):
-    """The update step (Eq. (4): counting sort by label, float64 segmented sums,
-    means) against the HBM roofline.  kmeans_g at N=1e7, d=16, K=256 (X is
-    640 MB, more than the 256 MB last-level cache) and at N=1e6, d=32, K=256,
-    each applied repeatedly at the centroids of one Lloyd step from a seeded
-    random-sample start; device time of the update from HIP events.
-    Algorithmic bytes per update: N*d*4 (X read once) + 16*N (labels, ranks,
-    permutation) + 8*K*d (float64 sums)."""
+    """The update step (Eq. (4): cluster sums and sizes, means) against the
+    HBM roofline.  kmeans_g at N=1e7, d=16, K=256 (X is 640 MB, more than the
+    256 MB last-level cache) and at N=1e6, d=32, K=256, each applied
+    repeatedly at the centroids of one Lloyd step from a seeded random-sample
+    start; device time of the update from HIP events (both shapes take the
+    fixed-point sums; the one pass over X that bounds |x| is computed once per
+    X and is not part of the update).
+    Algorithmic bytes per update, the least any update moves: N*d*4 (X read
+    once) + 4*N (labels read once) + 4*K*d (float32 means written)."""
     res = {}
     reps = max(3, args.steps)
     for N, d, K in ((10_000_000, 16, 256), (1_000_000, 32, 256)):
@@ -242,7 +244,7 @@ def update_workload(args, km, synth, torch):
             upd.append(st.update_ms)
             asg.append(st.assign_ms)
         u_ms = statistics.median(upd)
-        nbytes = N * d * 4 + 16 * N + 8 * K * d
+        nbytes = N * d * 4 + 4 * N + 4 * K * d
         gbs = nbytes / (u_ms / 1e3) / 1e9
         res[f"N{N}_d{d}_K{K}"] = {"update_ms": u_ms, "assign_ms": statistics.median(asg),
                                   "algorithmic_bytes": nbytes, "achieved_GBs": gbs,
@@ -250,7 +252,7 @@ def update_workload(args, km, synth, torch):
         del X, C0, C, ctx
         torch.cuda.empty_cache()
     print(json.dumps({"metric": "update step: algorithmic bytes per second vs HBM peak", "unit": "GB/s",
-                      "data": "synthetic", "dtype": "f64 sums of f32 rows",
+                      "data": "synthetic", "dtype": "i64 fixed-point sums of f32 rows",
                       "config": {"workload": "kmeans_g on gaussian mixtures (centres N(0,25I), std U[0.5,2], "
                                              "Dirichlet(1) weights), random-sample init, one Lloyd step, then "
                                              "repeated G at those centroids"},

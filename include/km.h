@@ -103,8 +103,9 @@ typedef struct {
   int64_t flagged_rows;    /* rows re-checked with float64 differences */
   int32_t empty_clusters;  /* clusters with no sample (centroid kept, reading R9) */
   float assign_ms;         /* device time of the assignment kernel, -1 unless timing is on */
-  float update_ms;         /* device time of the update step (counting sort, segmented
-                              sums, means), -1 unless timing is on */
+  float update_ms;         /* device time of the update step (cluster sums and sizes,
+                              means), -1 unless timing is on; the one pass over X that
+                              bounds |x| for the fixed-point sums is not included */
 } km_g_stats;
 
 /*
@@ -112,6 +113,11 @@ typedef struct {
  *   rho   = Assignment-Step(X, C)            (Sec. 1, Eq. (3); lowest index on ties)
  *   C_out = Update-Step(X, rho)              (Sec. 1, Eq. (4)); an empty cluster keeps C_j
  *   *E    = sum_i ||x_i - c_{rho_i}||^2      (Sec. 1, Eq. (1)), energy of the INPUT C
+ * Cluster sums: when K*d + K <= 10240, int64 fixed-point sums of the
+ * coordinates rounded to multiples of 2^-e, 2^e the largest power of two with
+ * N * max|x| * 2^e < 2^62 (each mean within N * max|x| * 2^-61 of the exact
+ * mean of the float32 values); otherwise float64 sums in a fixed order.  Both
+ * are bitwise reproducible; kmeans_solve and the engine use the same sums.
  * Arguments:
  *   X [N x d] (xt), C [K x d] float32, rho_prev [N] int32 or NULL (only used
  *   to count changed labels), rho [N] int32 out, C_out [K x d] float32 out

@@ -191,18 +191,22 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->w.e_part; a.flags = c->w.flags; a.ctl = c->w.ctl;
   a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[0], st_), "hipEventRecord");
-  HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[0], st_), "hipEventRecord");
-  const int grid = assign_grid(a);
-  HIP_TRY(c, launch_reduce_energy(c->w.e_part, grid, c->w.e_out, st_), "energy");
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[1], st_), "hipEventRecord");
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
   u.lab = rho; u.lab_from_ctl = 0; u.lrank = c->w.lrank; u.blockcount = c->w.blockcount;
   u.counts = c->w.counts; u.seg_start = c->w.seg_start; u.item_start = c->w.item_start;
   u.item_cluster = c->w.item_cluster; u.perm = c->w.perm; u.partial = c->w.partial;
   u.max_items = update_max_items(N, K); u.ctl = c->w.ctl; u.gated = 0;
+  u.fx = fx_ok(K, d); u.xbound = c->w.xbound; u.fxpart = c->w.fxpart;
+  // bound of |x| for the fixed-point sums: part of preparing X, outside the
+  // phase times (a solve computes it once)
+  HIP_TRY(c, launch_xbound(u, st_), "bound of |x|");
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[0], st_), "hipEventRecord");
+  HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[0], st_), "hipEventRecord");
+  const int grid = assign_grid(a);
+  HIP_TRY(c, launch_reduce_energy(c->w.e_part, grid, c->w.e_out, st_), "energy");
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[1], st_), "hipEventRecord");
   HIP_TRY(c, launch_update_sums(u, st_), "update");
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = 0; f.partial = c->w.partial; f.item_start = c->w.item_start;
@@ -301,6 +305,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   u.counts = c->w.counts; u.seg_start = c->w.seg_start; u.item_start = c->w.item_start;
   u.item_cluster = c->w.item_cluster; u.perm = c->w.perm; u.partial = c->w.partial;
   u.max_items = update_max_items(N, K); u.ctl = c->w.ctl; u.gated = 1;
+  u.fx = fx_ok(K, d); u.xbound = c->w.xbound; u.fxpart = c->w.fxpart;
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = cap; f.partial = c->w.partial; f.item_start = c->w.item_start;
   f.counts = c->w.counts; f.C_in = c->w.C_tmp; f.C_out = nullptr;
@@ -320,6 +325,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   HIP_TRY(c, launch_prep(c->w.C_tmp, K, d, c->w.nc_tmp, gbf ? c->w.Cb_tmp : nullptr,
                          gbf ? c->w.del_tmp : nullptr, q), "prep");
   HIP_TRY(c, launch_assign(a, kRolePlain, q), "assignment");
+  HIP_TRY(c, launch_xbound(u, q), "bound of |x|");
   HIP_TRY(c, launch_update_sums(u, q), "update");
   HIP_TRY(c, launch_finalize(f, q), "finalize");
   HIP_TRY(c, launch_combine(cb, q), "combine");

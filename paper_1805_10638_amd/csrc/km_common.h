@@ -29,6 +29,27 @@ __host__ __device__ inline int update_rank_blocks(int64_t N, int K) {
 constexpr int kSegRows = 512;        // rows per work item of the segmented sum
 constexpr int kTraceRec = 80;        // doubles per trace record
 
+// Fixed-point update: the cluster sums and sizes of a contiguous row range
+// are K*d + K int64 accumulators in LDS (integer addition is associative, so
+// the result does not depend on the order of the LDS atomics).  Used when
+// they fit in kFxMaxL entries (80 KB); larger K*d takes the counting sort.
+constexpr int kFxThreads = 1024;
+constexpr int kFxMaxL = 10240;
+constexpr int kFxMaxBlocks = 512;    // two workgroups per compute unit
+constexpr int kFxMinRows = 4096;     // rows per workgroup before the grid grows
+constexpr int kXBoundSlots = 256;    // per-workgroup maxima of |x|
+__host__ __device__ inline bool fx_ok(int K, int d) { return (int64_t)K * d + K <= kFxMaxL; }
+__host__ __device__ inline int fx_blocks(int64_t N) {
+  const int64_t p = N / kFxMinRows;
+  return p < 1 ? 1 : (p > kFxMaxBlocks ? kFxMaxBlocks : (int)p);
+}
+// int64 entries of the per-workgroup partials a workspace for (N, K, d) holds
+// (enough for any shape it fits: fewer rows, clusters or K*d)
+__host__ __device__ inline int64_t fx_part_entries(int64_t N, int K, int d) {
+  const int64_t L = (int64_t)K * d + K;
+  return (int64_t)fx_blocks(N) * (L < kFxMaxL ? L : kFxMaxL);
+}
+
 // Roles of an assignment launch.
 enum Role : int {
   kRolePlain = 0,      // stand-alone G(C): explicit label pointers, no gating

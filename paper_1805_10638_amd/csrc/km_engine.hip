@@ -110,8 +110,8 @@ struct km_engine {
     size_t lds = 0;
   };
   std::vector<Bucket> it_buckets;
-  size_t o_k1 = 0, o_k2 = 0, o_u = 0, o_upre[4] = {}, o_fi = 0, o_fpre = 0, o_cb = 0, o_cpre = 0, o_ctls = 0;
-  int ublocks[4] = {}, fblocks = 0, cblocks = 0, n_it = 0;
+  size_t o_k1 = 0, o_k2 = 0, o_u = 0, o_upre[kUpdateKinds] = {}, o_fi = 0, o_fpre = 0, o_cb = 0, o_cpre = 0, o_ctls = 0;
+  int ublocks[kUpdateKinds] = {}, fblocks = 0, cblocks = 0, n_it = 0;
 
   // Up to kSlots iterations in flight, each with its slot of done flags
   // (pinned), its poll event and its graph.
@@ -249,6 +249,7 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   u.counts = w.counts; u.seg_start = w.seg_start; u.item_start = w.item_start;
   u.item_cluster = w.item_cluster; u.perm = w.perm; u.partial = w.partial;
   u.max_items = update_max_items(s.N, s.K); u.ctl = w.ctl; u.gated = 1;
+  u.fx = fx_ok(s.K, s.d); u.xbound = w.xbound; u.fxpart = w.fxpart;
   r.u = u;
 
   FinalizeArgs f{};
@@ -350,7 +351,7 @@ km_status enqueue_iteration(km_engine* e, int p) {
   ENG_TRY(e, launch_controller_batch(dptr<CtlArgs>(e, e->o_k2), e->n_it, q), "batched controller");
   UpdateBatch ub;
   ub.tab = dptr<UpdateArgs>(e, e->o_u);
-  for (int k = 0; k < 4; ++k) { ub.prefix[k] = dptr<int>(e, e->o_upre[k]); ub.blocks[k] = e->ublocks[k]; }
+  for (int k = 0; k < kUpdateKinds; ++k) { ub.prefix[k] = dptr<int>(e, e->o_upre[k]); ub.blocks[k] = e->ublocks[k]; }
   ub.n = e->n_it;
   ENG_TRY(e, launch_update_sums_batch(ub, q), "batched update");
   ENG_TRY(e, launch_finalize_batch(dptr<FinalizeArgs>(e, e->o_fi), dptr<int>(e, e->o_fpre), e->n_it, e->fblocks, q),
@@ -442,7 +443,7 @@ km_status rebuild(km_engine* e, bool drain) {
   std::vector<PrepArgs> prep;
   std::vector<int> prep_sz;
   std::vector<UpdateArgs> pu;
-  std::vector<int> pusz[4];
+  std::vector<int> pusz[kUpdateKinds];
   std::vector<FinalizeArgs> pf;
   std::vector<int> pfsz;
   std::vector<CombineArgs> pc;
@@ -453,13 +454,13 @@ km_status rebuild(km_engine* e, bool drain) {
     prep_sz.push_back(prep_grid(j->spec.K));
     add_bucket(pb, j->pick, aa[i].plain, nullptr, j->assign_blocks);
     pu.push_back(aa[i].u);
-    for (int k = 0; k < 4; ++k) pusz[k].push_back(update_grid(aa[i].u, k));
+    for (int k = 0; k < kUpdateKinds; ++k) pusz[k].push_back(update_grid(aa[i].u, k));
     pf.push_back(aa[i].f_init);
     pfsz.push_back(finalize_grid((int64_t)j->spec.K * j->spec.d));
     pc.push_back(aa[i].c0);
     pcsz.push_back(combine_grid(j->spec.K));
   }
-  int prep_blocks = 0, pub[4] = {}, pfb = 0, pcb = 0;
+  int prep_blocks = 0, pub[kUpdateKinds] = {}, pfb = 0, pcb = 0;
   const size_t o_prep = pk.add(prep), o_prep_pre = pk.add(prefix_of(prep_sz, &prep_blocks));
   std::vector<size_t> o_pb, o_pb_pre;
   std::vector<int> pb_blocks;
@@ -470,8 +471,8 @@ km_status rebuild(km_engine* e, bool drain) {
     pb_blocks.push_back(t);
   }
   const size_t o_pu = pk.add(pu);
-  size_t o_pupre[4];
-  for (int k = 0; k < 4; ++k) o_pupre[k] = pk.add(prefix_of(pusz[k], &pub[k]));
+  size_t o_pupre[kUpdateKinds];
+  for (int k = 0; k < kUpdateKinds; ++k) o_pupre[k] = pk.add(prefix_of(pusz[k], &pub[k]));
   const size_t o_pf = pk.add(pf), o_pfpre = pk.add(prefix_of(pfsz, &pfb));
   const size_t o_pc = pk.add(pc), o_pcpre = pk.add(prefix_of(pcsz, &pcb));
 
@@ -479,7 +480,7 @@ km_status rebuild(km_engine* e, bool drain) {
   std::vector<HostBucket> ib;
   std::vector<CtlArgs> k1, k2;
   std::vector<UpdateArgs> iu;
-  std::vector<int> iusz[4];
+  std::vector<int> iusz[kUpdateKinds];
   std::vector<FinalizeArgs> fi;
   std::vector<int> fisz;
   std::vector<CombineArgs> ci;
@@ -491,7 +492,7 @@ km_status rebuild(km_engine* e, bool drain) {
     k1.push_back(r.k1);
     k2.push_back(r.k2);
     iu.push_back(r.u);
-    for (int k = 0; k < 4; ++k) iusz[k].push_back(update_grid(r.u, k));
+    for (int k = 0; k < kUpdateKinds; ++k) iusz[k].push_back(update_grid(r.u, k));
     fi.push_back(r.f_iter);
     fisz.push_back(finalize_grid((int64_t)j->spec.K * j->spec.d));
     ci.push_back(r.c1);
@@ -512,7 +513,7 @@ km_status rebuild(km_engine* e, bool drain) {
   e->o_k1 = pk.add(k1);
   e->o_k2 = pk.add(k2);
   e->o_u = pk.add(iu);
-  for (int k = 0; k < 4; ++k) e->o_upre[k] = pk.add(prefix_of(iusz[k], &e->ublocks[k]));
+  for (int k = 0; k < kUpdateKinds; ++k) e->o_upre[k] = pk.add(prefix_of(iusz[k], &e->ublocks[k]));
   e->o_fi = pk.add(fi);
   e->o_fpre = pk.add(prefix_of(fisz, &e->fblocks));
   e->o_cb = pk.add(ci);
@@ -546,8 +547,9 @@ km_status rebuild(km_engine* e, bool drain) {
                                      (int)pb[b].a.size(), pb_blocks[b], pb[b].lds, q), "batched assignment");
     UpdateBatch ub;
     ub.tab = dptr<UpdateArgs>(e, o_pu);
-    for (int k = 0; k < 4; ++k) { ub.prefix[k] = dptr<int>(e, o_pupre[k]); ub.blocks[k] = pub[k]; }
+    for (int k = 0; k < kUpdateKinds; ++k) { ub.prefix[k] = dptr<int>(e, o_pupre[k]); ub.blocks[k] = pub[k]; }
     ub.n = na;
+    ENG_TRY(e, launch_xbound_batch(ub, q), "batched bound of |x|");
     ENG_TRY(e, launch_update_sums_batch(ub, q), "batched update");
     ENG_TRY(e, launch_finalize_batch(dptr<FinalizeArgs>(e, o_pf), dptr<int>(e, o_pfpre), na, pfb, q),
             "batched finalize");

@@ -70,23 +70,33 @@ struct UpdateArgs {
   int max_items;
   Ctl* ctl;
   int gated;              // 1: skip when ctl->done
+  int fx;                 // 1: fixed-point sums (fx_ok(K, d)) instead of the counting sort
+  unsigned* xbound;       // kXBoundSlots per-workgroup maxima of the |x| bit patterns
+  unsigned long long* fxpart;  // fx_blocks(N) x (K*d + K) int64 partials
 };
 int update_max_items(int64_t N, int K);
 // blockcount entries a workspace for (N, K) must hold: enough for any K' <= K
 size_t update_blockcount_ints(int64_t N, int K);
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s);
-// workgroups of update kernel `which` (0 rank, 1 scan, 2 scatter, 3 segsum)
+// Bound of |x| over X for the fixed-point sums (u.fx only): once per X, before
+// the first update with it.
+hipError_t launch_xbound(const UpdateArgs& u, hipStream_t s);
+// workgroups of update kernel `which` (0 rank, 1 scan, 2 scatter, 3 segsum,
+// 4 fixed-point sums, 5 their reduction, 6 the |x| bound); 0 where the
+// instance takes the other path
+constexpr int kUpdateKinds = 7;
 int update_grid(const UpdateArgs& u, int which);
 // Batched update: tab (device) one UpdateArgs per instance; prefix[w]
 // (device, n + 1 entries) the cumulative workgroups of kernel w; blocks[w]
 // the launch size.  The offsets kernel runs one workgroup per instance.
 struct UpdateBatch {
   const UpdateArgs* tab;
-  const int* prefix[4];
-  int blocks[4];
+  const int* prefix[kUpdateKinds];
+  int blocks[kUpdateKinds];
   int n;
 };
 hipError_t launch_update_sums_batch(const UpdateBatch& ub, hipStream_t s);
+hipError_t launch_xbound_batch(const UpdateBatch& ub, hipStream_t s);
 
 // Finalisation of the means and, in the solver, the residual/history push.
 enum FinMode : int { kFinG = 0, kFinInit = 1, kFinIter = 2 };

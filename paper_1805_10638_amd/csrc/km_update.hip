@@ -323,6 +323,221 @@ size_t update_blockcount_ints(int64_t N, int K) {
   const size_t b = (size_t)((N + kRankRowsLarge - 1) / kRankRowsLarge) * K;
   return a > b ? a : b;
 }
+// ---------------------------------------------------------------------------
+// Fixed-point sums (fx_ok(K, d)): X is read once, in row order
+// ---------------------------------------------------------------------------
+// Each workgroup adds the rows of one contiguous range into K*d + K int64
+// accumulators in LDS (sums of the scaled, rounded coordinates, then the
+// cluster sizes); a second kernel adds the per-workgroup partials and converts
+// the sums back.  Integer addition is associative, so the order of the LDS
+// atomics does not change the result: runs are bitwise reproducible, and the
+// sums do not depend on how the rows are split between workgroups.
+//
+// Scale: 2^e with n * max|x| * 2^e < 2^62, so no partial sum of at most n
+// scaled values overflows; e is the largest such integer up to the powers of
+// two that bound n and max|x|, so 2^-e <= n * max|x| * 2^-60.  Each
+// coordinate is rounded to the nearest multiple of 2^-e; a cluster mean then
+// differs from the exact mean of the float32 values by at most
+// 2^-(e+1) <= n * max|x| * 2^-61 (about 4e-12 max|x| at n = 1e7), far below
+// float32 rounding of the centroids.
+
+__device__ __forceinline__ unsigned wave_umax(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+  return v;
+}
+
+// Per-workgroup maxima of |x| over X, as float32 bit patterns (non-negative
+// floats order like their bits; NaN lies above infinity).  bfloat16 bits are
+// the high half of the float32 pattern.
+__device__ __forceinline__ void xbound_body(const UpdateArgs& u, int bx) {
+  __shared__ unsigned wm[4];
+  const int tid = threadIdx.x;
+  const int64_t n = u.N * u.d;
+  const int64_t stride = (int64_t)kXBoundSlots * 256;
+  const uint4* x4 = (const uint4*)u.X;     // X starts on a 16-byte boundary
+  unsigned m = 0;
+  if (u.xbf16) {
+    const uint16_t* x = (const uint16_t*)u.X;
+    const int64_t n8 = n / 8;
+    for (int64_t q = (int64_t)bx * 256 + tid; q < n8; q += stride) {
+      const uint4 v = x4[q];
+      const unsigned a = max(v.x & 0x7fff7fffu, v.y & 0x7fff7fffu), b = max(v.z & 0x7fff7fffu, v.w & 0x7fff7fffu);
+      m = max(m, max(max(a >> 16, a & 0xffffu), max(b >> 16, b & 0xffffu)));
+    }
+    for (int64_t i = n8 * 8 + (int64_t)bx * 256 + tid; i < n; i += stride) m = max(m, (unsigned)(x[i] & 0x7fffu));
+    m <<= 16;
+  } else {
+    const unsigned* x = (const unsigned*)u.X;
+    const int64_t n4 = n / 4;
+    for (int64_t q = (int64_t)bx * 256 + tid; q < n4; q += stride) {
+      const uint4 v = x4[q];
+      m = max(m, max(max(v.x & 0x7fffffffu, v.y & 0x7fffffffu), max(v.z & 0x7fffffffu, v.w & 0x7fffffffu)));
+    }
+    for (int64_t i = n4 * 4 + (int64_t)bx * 256 + tid; i < n; i += stride) m = max(m, x[i] & 0x7fffffffu);
+  }
+  m = wave_umax(m);
+  if ((tid & 63) == 0) wm[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) u.xbound[bx] = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+}
+
+// e for the bound pattern `bits` and n rows; 0 for all-zero or non-finite X
+// (non-finite data makes the energy non-finite, which the caller reports).
+__device__ __forceinline__ int fx_exponent(unsigned bits, int64_t n) {
+  if (bits == 0u || bits >= 0x7f800000u) return 0;
+  const int E = (int)(bits >> 23);
+  const int eb = E == 0 ? -126 : E - 126;                 // max|x| < 2^eb
+  const int ln = 64 - __clzll((unsigned long long)n);     // n < 2^ln
+  return 62 - eb - ln;
+}
+
+// The bound over all slots (every thread of a kFxThreads workgroup).
+__device__ __forceinline__ unsigned fx_bound(const UpdateArgs& u, unsigned* sh) {
+  const int tid = threadIdx.x;
+  unsigned m = tid < kXBoundSlots ? u.xbound[tid] : 0u;
+  m = wave_umax(m);
+  if ((tid & 63) == 0) sh[tid >> 6] = m;
+  __syncthreads();
+  unsigned b = 0;
+#pragma unroll
+  for (int w = 0; w < kFxThreads / 64; ++w) b = max(b, sh[w]);
+  return b;
+}
+
+// round(v * s) as a two's complement int64: v * s is exact (s a power of
+// two, v a float32); hi = floor(q / 2^32) and lo = q - hi * 2^32 in [0, 2^32)
+// are exact in float64.
+__device__ __forceinline__ unsigned long long fx_quant(float v, double s) {
+  const double q = rint((double)v * s);
+  const double hi = floor(q * 0x1p-32);
+  const double lo = fma(hi, -0x1p32, q);
+  return ((unsigned long long)(long long)(int)hi << 32) + (unsigned long long)(unsigned)lo;
+}
+
+__device__ __forceinline__ int fx_label(const int* lab, int64_t r, int K) {
+  const int j = lab[r];
+  return (j < 0 || j >= K) ? 0 : j;
+}
+
+__device__ __forceinline__ float4 fx_load4(const UpdateArgs& u, int64_t i) {
+  if (u.xbf16) {
+    const uint2 v = *(const uint2*)((const uint16_t*)u.X + i);
+    return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                       __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+  }
+  return *(const float4*)((const float*)u.X + i);
+}
+
+__device__ __forceinline__ float fx_load1(const UpdateArgs& u, int64_t i) {
+  return u.xbf16 ? __uint_as_float((unsigned)((const uint16_t*)u.X)[i] << 16) : ((const float*)u.X)[i];
+}
+
+// Workgroup bx of P: rows [bx * ceil(N/P), ...) into acc (K*d + K entries).
+__device__ __forceinline__ void fxsum_body(const UpdateArgs& u, int bx, int P, unsigned long long* acc) {
+  if (u.gated && u.ctl->done) return;
+  __shared__ unsigned bsh[kFxThreads / 64];
+  constexpr int T = kFxThreads;
+  const int tid = threadIdx.x;
+  const int d = u.d, K = u.K, KD = K * d, L = KD + K;
+  const int* lab = labels_of(u);
+  for (int i = tid; i < L; i += T) acc[i] = 0ull;
+  if (bx == 0 && tid == 0) u.ctl->empty = 0;     // the reduction adds the empty clusters
+  const double s = ldexp(1.0, fx_exponent(fx_bound(u, bsh), u.N));   // ends with a barrier
+  const int64_t rows = (u.N + P - 1) / P;
+  const int64_t r0 = (int64_t)bx * rows;
+  const int64_t r1 = r0 + rows < u.N ? r0 + rows : u.N;
+  if (r0 < r1) {
+    // consecutive threads take consecutive groups of g coordinates; (row, col)
+    // of a thread's group advances by T groups per step
+    const int g = (d & 3) == 0 ? 4 : 1;
+    const int qd = d / g;
+    const int64_t ng = (r1 - r0) * qd;
+    const int drow = T / qd, dcol = T % qd;
+    int64_t row = r0 + tid / qd;
+    int col = tid % qd;
+    int64_t q = tid;
+    if (g == 4) {
+      for (; q + T < ng; q += 2 * T) {
+        int64_t rowb = row + drow;
+        int colb = col + dcol;
+        if (colb >= qd) { colb -= qd; ++rowb; }
+        const float4 va = fx_load4(u, row * d + 4 * col), vb = fx_load4(u, rowb * d + 4 * colb);
+        const int ja = fx_label(lab, row, K), jb = fx_label(lab, rowb, K);
+        unsigned long long* a = acc + ja * d + 4 * col;
+        atomicAdd(a + 0, fx_quant(va.x, s)); atomicAdd(a + 1, fx_quant(va.y, s));
+        atomicAdd(a + 2, fx_quant(va.z, s)); atomicAdd(a + 3, fx_quant(va.w, s));
+        unsigned long long* b = acc + jb * d + 4 * colb;
+        atomicAdd(b + 0, fx_quant(vb.x, s)); atomicAdd(b + 1, fx_quant(vb.y, s));
+        atomicAdd(b + 2, fx_quant(vb.z, s)); atomicAdd(b + 3, fx_quant(vb.w, s));
+        row = rowb + drow;
+        col = colb + dcol;
+        if (col >= qd) { col -= qd; ++row; }
+      }
+      if (q < ng) {
+        const float4 va = fx_load4(u, row * d + 4 * col);
+        unsigned long long* a = acc + fx_label(lab, row, K) * d + 4 * col;
+        atomicAdd(a + 0, fx_quant(va.x, s)); atomicAdd(a + 1, fx_quant(va.y, s));
+        atomicAdd(a + 2, fx_quant(va.z, s)); atomicAdd(a + 3, fx_quant(va.w, s));
+      }
+    } else {
+      for (; q < ng; q += T) {
+        atomicAdd(acc + fx_label(lab, row, K) * d + col, fx_quant(fx_load1(u, row * d + col), s));
+        row += drow;
+        col += dcol;
+        if (col >= qd) { col -= qd; ++row; }
+      }
+    }
+    for (int64_t r = r0 + tid; r < r1; r += T) atomicAdd(acc + KD + fx_label(lab, r, K), 1ull);
+  }
+  __syncthreads();
+  unsigned long long* part = u.fxpart + (int64_t)bx * L;
+  for (int i = tid; i < L; i += T) part[i] = acc[i];
+}
+
+// 64 entries per workgroup: sums of the fx_blocks(N) partials (16 waves split
+// them), then sums * 2^-e into partial[j*d + k] (one work item per cluster),
+// sizes into counts, item_start[j] = j, and the number of empty clusters.
+__device__ __forceinline__ void fxreduce_body(const UpdateArgs& u, int bx) {
+  if (u.gated && u.ctl->done) return;
+  __shared__ unsigned long long r[kFxThreads / 64][64];
+  __shared__ unsigned bsh[kFxThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int KD = u.K * u.d, L = KD + u.K;
+  const int P = fx_blocks(u.N);
+  const double inv = ldexp(1.0, -fx_exponent(fx_bound(u, bsh), u.N));   // ends with a barrier
+  const int e = bx * 64 + lane;
+  unsigned long long t = 0;
+  if (e < L) {
+    const unsigned long long* p0 = u.fxpart + e;
+    int p = w;
+    for (; p + 48 < P; p += 64) {
+      const unsigned long long a = p0[(int64_t)p * L], b = p0[(int64_t)(p + 16) * L];
+      const unsigned long long c = p0[(int64_t)(p + 32) * L], dd = p0[(int64_t)(p + 48) * L];
+      t += (a + b) + (c + dd);
+    }
+    for (; p < P; p += 16) t += p0[(int64_t)p * L];
+  }
+  r[w][lane] = t;
+  __syncthreads();
+  if (w != 0) return;
+  t = 0;
+#pragma unroll
+  for (int i = 0; i < kFxThreads / 64; ++i) t += r[i][lane];
+  bool empty = false;
+  if (e < KD) {
+    u.partial[e] = (double)(long long)t * inv;
+  } else if (e < L) {
+    const int j = e - KD;
+    u.counts[j] = (int)t;
+    u.item_start[j] = j;
+    if (j == u.K - 1) u.item_start[u.K] = u.K;
+    empty = t == 0;
+  }
+  const unsigned long long em = __ballot(empty);
+  if (lane == 0 && em) atomicAdd(&u.ctl->empty, (int)__popcll(em));
+}
+
 int update_max_items(int64_t N, int K) { return (int)((N + kSegRows - 1) / kSegRows) + K; }
 
 __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) { rank_body(u, blockIdx.x); }
@@ -340,7 +555,8 @@ __global__ __launch_bounds__(256) void k_scan_batch(BatchRef<UpdateArgs> t) {
   scan_body(t.tab[b], blockIdx.x - t.prefix[b]);
 }
 __global__ __launch_bounds__(1024) void k_offsets_batch(BatchRef<UpdateArgs> t) {
-  offsets_body(t.tab[blockIdx.x]);   // one workgroup per instance
+  const UpdateArgs& u = t.tab[blockIdx.x];   // one workgroup per instance
+  if (!u.fx) offsets_body(u);
 }
 __global__ __launch_bounds__(256) void k_scatter_batch(BatchRef<UpdateArgs> t) {
   const int b = batch_find(t.prefix, t.n, blockIdx.x);
@@ -351,8 +567,65 @@ __global__ __launch_bounds__(256) void k_segsum_batch(BatchRef<UpdateArgs> t) {
   segsum_body(t.tab[b], blockIdx.x - t.prefix[b]);
 }
 
+__global__ __launch_bounds__(256) void k_xbound(UpdateArgs u) { xbound_body(u, blockIdx.x); }
+__global__ __launch_bounds__(kFxThreads) void k_fxsum(UpdateArgs u) {
+  extern __shared__ unsigned long long fx_acc[];
+  fxsum_body(u, blockIdx.x, gridDim.x, fx_acc);
+}
+__global__ __launch_bounds__(kFxThreads) void k_fxreduce(UpdateArgs u) { fxreduce_body(u, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_xbound_batch(BatchRef<UpdateArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  xbound_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
+__global__ __launch_bounds__(kFxThreads) void k_fxsum_batch(BatchRef<UpdateArgs> t) {
+  extern __shared__ unsigned long long fx_acc[];
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  fxsum_body(t.tab[b], blockIdx.x - t.prefix[b], t.prefix[b + 1] - t.prefix[b], fx_acc);
+}
+__global__ __launch_bounds__(kFxThreads) void k_fxreduce_batch(BatchRef<UpdateArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  fxreduce_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
+
+// Dynamic LDS of the fixed-point sums: kFxMaxL accumulators (above the
+// default 64 KB limit, so the attribute is raised once per process).
+constexpr size_t kFxLds = (size_t)kFxMaxL * 8;
+static hipError_t fx_lds_attr() {
+  static hipError_t st = [] {
+    hipError_t a = hipFuncSetAttribute((const void*)k_fxsum, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFxLds);
+    hipError_t b = hipFuncSetAttribute((const void*)k_fxsum_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kFxLds);
+    return a != hipSuccess ? a : b;
+  }();
+  return st;
+}
+
+hipError_t launch_xbound(const UpdateArgs& u, hipStream_t s) {
+  if (!u.fx) return hipSuccess;
+  clear_pending_error();
+  hipLaunchKernelGGL(k_xbound, dim3(kXBoundSlots), dim3(256), 0, s, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_xbound_batch(const UpdateBatch& ub, hipStream_t s) {
+  clear_pending_error();
+  if (ub.n <= 0 || ub.blocks[6] <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xbound_batch, dim3(ub.blocks[6]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[6], ub.n});
+  return hipGetLastError();
+}
+
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
   if (u.K > kMaxK || u.d > kMaxD) return hipErrorInvalidValue;
+  if (u.fx) {
+    if (!fx_ok(u.K, u.d)) return hipErrorInvalidValue;
+    const hipError_t a = fx_lds_attr();
+    if (a != hipSuccess) return a;
+    clear_pending_error();
+    hipLaunchKernelGGL(k_fxsum, dim3(fx_blocks(u.N)), dim3(kFxThreads), kFxLds, s, u);
+    hipLaunchKernelGGL(k_fxreduce, dim3(update_grid(u, 5)), dim3(kFxThreads), 0, s, u);
+    return hipGetLastError();
+  }
   const int nblk = update_rank_blocks(u.N, u.K);
   clear_pending_error();
   hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(256), 0, s, u);
@@ -363,23 +636,41 @@ hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Instances on the counting sort get workgroups in kernels 0-3 (and the
+// offsets kernel, one workgroup per instance, returns at once for the others);
+// fixed-point instances in kernels 4-5.
 hipError_t launch_update_sums_batch(const UpdateBatch& ub, hipStream_t s) {
   clear_pending_error();
   if (ub.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rank_batch, dim3(ub.blocks[0]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[0], ub.n});
-  hipLaunchKernelGGL(k_scan_batch, dim3(ub.blocks[1]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[1], ub.n});
-  hipLaunchKernelGGL(k_offsets_batch, dim3(ub.n), dim3(1024), 0, s, BatchRef<UpdateArgs>{ub.tab, nullptr, ub.n});
-  hipLaunchKernelGGL(k_scatter_batch, dim3(ub.blocks[2]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[2], ub.n});
-  hipLaunchKernelGGL(k_segsum_batch, dim3(ub.blocks[3]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[3], ub.n});
+  if (ub.blocks[0] > 0) {
+    hipLaunchKernelGGL(k_rank_batch, dim3(ub.blocks[0]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[0], ub.n});
+    hipLaunchKernelGGL(k_scan_batch, dim3(ub.blocks[1]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[1], ub.n});
+    hipLaunchKernelGGL(k_offsets_batch, dim3(ub.n), dim3(1024), 0, s, BatchRef<UpdateArgs>{ub.tab, nullptr, ub.n});
+    hipLaunchKernelGGL(k_scatter_batch, dim3(ub.blocks[2]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[2], ub.n});
+    hipLaunchKernelGGL(k_segsum_batch, dim3(ub.blocks[3]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[3], ub.n});
+  }
+  if (ub.blocks[4] > 0) {
+    const hipError_t a = fx_lds_attr();
+    if (a != hipSuccess) return a;
+    hipLaunchKernelGGL(k_fxsum_batch, dim3(ub.blocks[4]), dim3(kFxThreads), kFxLds, s,
+                       BatchRef<UpdateArgs>{ub.tab, ub.prefix[4], ub.n});
+    hipLaunchKernelGGL(k_fxreduce_batch, dim3(ub.blocks[5]), dim3(kFxThreads), 0, s,
+                       BatchRef<UpdateArgs>{ub.tab, ub.prefix[5], ub.n});
+  }
   return hipGetLastError();
 }
 
 int update_grid(const UpdateArgs& u, int which) {
+  if (which <= 3 && u.fx) return 0;
+  if (which >= 4 && !u.fx) return 0;
   switch (which) {
     case 0: return update_rank_blocks(u.N, u.K);
     case 1: return u.K;
     case 2: return (int)((u.N + 255) / 256);
     case 3: return u.max_items;
+    case 4: return fx_blocks(u.N);
+    case 5: return (u.K * u.d + u.K + 63) / 64;
+    case 6: return kXBoundSlots;
   }
   return 0;
 }

@@ -35,6 +35,8 @@ struct Ws {
   int* item_cluster = nullptr;  // max_items
   double* e_part = nullptr;     // 2 x (N / 64 + 1): partials of the candidate and fall-back passes
   double* partial = nullptr;    // max_items x d
+  unsigned* xbound = nullptr;   // kXBoundSlots (fixed-point update)
+  unsigned long long* fxpart = nullptr;  // fx_part_entries(N, K, d)
   double* G_last = nullptr;     // K x d
   double* F_last = nullptr;     // K x d
   double* ring_dF = nullptr;    // cap x K x d
@@ -79,6 +81,8 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const size_t o_ic = take((size_t)max_items * 4);
   const size_t o_ep = take((size_t)2 * grid * 8);
   const size_t o_pa = take((size_t)max_items * s.d * 8);
+  const size_t o_xb = take((size_t)kXBoundSlots * 4);
+  const size_t o_fx = take((size_t)fx_part_entries(N, s.K, s.d) * 8);
   const size_t o_gl = take(KD * 8);
   const size_t o_fl = take(KD * 8);
   const size_t o_rf = take((size_t)s.cap * KD * 8);
@@ -112,6 +116,8 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
     w->item_cluster = (int*)(b + o_ic);
     w->e_part = (double*)(b + o_ep);
     w->partial = (double*)(b + o_pa);
+    w->xbound = (unsigned*)(b + o_xb);
+    w->fxpart = (unsigned long long*)(b + o_fx);
     w->G_last = (double*)(b + o_gl);
     w->F_last = (double*)(b + o_fl);
     w->ring_dF = (double*)(b + o_rf);

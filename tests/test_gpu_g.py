@@ -307,3 +307,44 @@ def test_g_full_size_precision_sampled():
         Cj, _ = ko.update(Xm, np.zeros(members.size, dtype=np.int64), C64[j:j + 1])
         err = np.linalg.norm(Cn[j].astype(np.float64) - Cj[0]) / max(np.linalg.norm(Cj[0]), 1.0)
         assert err <= 1e-5, (j, err)
+
+
+def _mean_bound_check(X, C, rho, Cn):
+    """Means against the oracle's means of the GPU labels, to float32 rounding
+    plus the fixed-point bound N * max|x| * 2^-61 (with a factor 2 margin)."""
+    X64 = x_values(X)
+    Co, _ = ko.update(X64, np.asarray(rho).astype(np.int64), C.astype(np.float64))
+    tol = np.abs(Co) * 2.0**-23 + X64.shape[0] * np.abs(X64).max() * 2.0**-60
+    err = np.abs(np.asarray(Cn).astype(np.float64) - Co)
+    assert (err <= tol).all(), float((err / tol).max())
+
+
+# The fixed-point sums take K*d + K <= 10240 (80 KB of LDS accumulators);
+# larger shapes take the counting sort.  Both sides of the limit, float32 and
+# bfloat16 rows, d with and without 4-coordinate groups.
+@pytest.mark.parametrize("d,K,xt", [(16, 602, "f32"), (16, 603, "f32"), (7, 1280, "bf16"),
+                                    (7, 1281, "bf16"), (12, 100, "bf16"), (5, 64, "f32")])
+def test_update_sums_both_paths(d, K, xt):
+    km = _lib()
+    X = _mixture(20000, d, K, seed=d * K)
+    if xt == "bf16":
+        X = synth.to_bf16_bits(X)
+    C = synth.init_centroids(X, K, seed=1)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C))
+    check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
+    _mean_bound_check(X, C, rho.cpu().numpy(), Cn.cpu().numpy())
+
+
+def test_update_fixed_point_wide_range():
+    """Coordinates spanning eight decades (max |x| near 4e5, the smallest
+    dimension near 1e-3): every mean within the fixed-point bound."""
+    km = _lib()
+    rng = np.random.default_rng(5)
+    N, d, K = 30000, 8, 40
+    X = (rng.normal(size=(N, d)) * np.logspace(-3, 5, d)).astype(np.float32)
+    C = X[rng.choice(N, K, replace=False)].copy()
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C))
+    _mean_bound_check(X, C, rho.cpu().numpy(), Cn.cpu().numpy())
+    a = ko.assign(X.astype(np.float64), C.astype(np.float64))
+    mism = np.flatnonzero(a.rho != rho.cpu().numpy())
+    assert (a.near_tie[mism]).all()
