@@ -115,8 +115,9 @@ typedef struct {
  *   *E    = sum_i ||x_i - c_{rho_i}||^2      (Sec. 1, Eq. (1)), energy of the INPUT C
  * Cluster sums: when K*d + K <= 10240, int64 fixed-point sums of the
  * coordinates rounded to multiples of 2^-e, 2^e the largest power of two with
- * N * max|x| * 2^e < 2^62 (each mean within N * max|x| * 2^-61 of the exact
- * mean of the float32 values); otherwise float64 sums in a fixed order.  Both
+ * N * max|x| * 2^e < 2^62 and max|x| * 2^e < 2^51 (each mean within
+ * N * max|x| * 2^-61 of the exact mean of the float32 values, max|x| * 2^-51
+ * below 2048 rows); otherwise float64 sums in a fixed order.  Both
  * are bitwise reproducible; kmeans_solve and the engine use the same sums.
  * Arguments:
  *   X [N x d] (xt), C [K x d] float32, rho_prev [N] int32 or NULL (only used

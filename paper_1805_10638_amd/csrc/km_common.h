@@ -30,15 +30,18 @@ constexpr int kSegRows = 512;        // rows per work item of the segmented sum
 constexpr int kTraceRec = 80;        // doubles per trace record
 
 // Fixed-point update: the cluster sums and sizes of a contiguous row range
-// are K*d + K int64 accumulators in LDS (integer addition is associative, so
-// the result does not depend on the order of the LDS atomics).  Used when
-// they fit in kFxMaxL entries (80 KB); larger K*d takes the counting sort.
+// are int64 accumulators in LDS (integer addition is associative, so the
+// result does not depend on the order of the LDS atomics).  A cluster's sums
+// take fx_stride(d) entries: an odd stride puts the rows of different
+// clusters on different banks.  Used when K * fx_stride(d) + K entries fit in
+// kFxMaxL (80 KB); larger K*d takes the counting sort.
 constexpr int kFxThreads = 1024;
 constexpr int kFxMaxL = 10240;
-constexpr int kFxMaxBlocks = 512;    // two workgroups per compute unit
+constexpr int kFxMaxBlocks = 256;    // one workgroup per compute unit (fewer partials to add)
 constexpr int kFxMinRows = 4096;     // rows per workgroup before the grid grows
-constexpr int kXBoundSlots = 256;    // per-workgroup maxima of |x|
-__host__ __device__ inline bool fx_ok(int K, int d) { return (int64_t)K * d + K <= kFxMaxL; }
+constexpr int kXBoundSlots = 1024;   // per-workgroup maxima of |x| (one per thread of a fixed-point workgroup)
+__host__ __device__ inline int fx_stride(int d) { return d | 1; }
+__host__ __device__ inline bool fx_ok(int K, int d) { return (int64_t)K * fx_stride(d) + K <= kFxMaxL; }
 __host__ __device__ inline int fx_blocks(int64_t N) {
   const int64_t p = N / kFxMinRows;
   return p < 1 ? 1 : (p > kFxMaxBlocks ? kFxMaxBlocks : (int)p);

@@ -334,12 +334,20 @@ size_t update_blockcount_ints(int64_t N, int K) {
 // sums do not depend on how the rows are split between workgroups.
 //
 // Scale: 2^e with n * max|x| * 2^e < 2^62, so no partial sum of at most n
-// scaled values overflows; e is the largest such integer up to the powers of
-// two that bound n and max|x|, so 2^-e <= n * max|x| * 2^-60.  Each
-// coordinate is rounded to the nearest multiple of 2^-e; a cluster mean then
-// differs from the exact mean of the float32 values by at most
-// 2^-(e+1) <= n * max|x| * 2^-61 (about 4e-12 max|x| at n = 1e7), far below
-// float32 rounding of the centroids.
+// scaled values overflows, and max|x| * 2^e < 2^51 (below).  e is the largest
+// such integer up to the powers of two that bound n and max|x|, so for
+// n >= 2048, 2^-e <= n * max|x| * 2^-60.  Each coordinate is rounded to the
+// nearest multiple of 2^-e; a cluster mean then differs from the exact mean
+// of the float32 values by at most 2^-(e+1) <= n * max|x| * 2^-61 (about
+// 4e-12 max|x| at n = 1e7; max|x| * 2^-51 for smaller n), far below float32
+// rounding of the centroids.
+//
+// Rounding: with |v * 2^e| < 2^51, t = fma(v, 2^e, 1.5 * 2^52) lies in
+// [2^52, 2^53), where float64 spacing is 1, so t is v * 2^e rounded to the
+// nearest integer q, and the bit pattern of t is q + bits(1.5 * 2^52).  The
+// accumulators add bit patterns (modulo 2^64); each workgroup subtracts
+// (rows of cluster j) * bits(1.5 * 2^52) from the sums of cluster j when it
+// writes its partials, which leaves the exact integer sums.
 
 __device__ __forceinline__ unsigned wave_umax(unsigned v) {
 #pragma unroll
@@ -350,31 +358,39 @@ __device__ __forceinline__ unsigned wave_umax(unsigned v) {
 // Per-workgroup maxima of |x| over X, as float32 bit patterns (non-negative
 // floats order like their bits; NaN lies above infinity).  bfloat16 bits are
 // the high half of the float32 pattern.
+// largest |x| pattern of a 16-byte word: 4 float32, or 8 bfloat16 (16-bit result)
+__device__ __forceinline__ unsigned xb_half(unsigned w) {
+  w &= 0x7fff7fffu;
+  return max(w >> 16, w & 0xffffu);
+}
+__device__ __forceinline__ unsigned xb_word(uint4 v, bool bf) {
+  if (bf) return max(max(xb_half(v.x), xb_half(v.y)), max(xb_half(v.z), xb_half(v.w)));
+  return max(max(v.x & 0x7fffffffu, v.y & 0x7fffffffu), max(v.z & 0x7fffffffu, v.w & 0x7fffffffu));
+}
+
 __device__ __forceinline__ void xbound_body(const UpdateArgs& u, int bx) {
   __shared__ unsigned wm[4];
   const int tid = threadIdx.x;
   const int64_t n = u.N * u.d;
   const int64_t stride = (int64_t)kXBoundSlots * 256;
   const uint4* x4 = (const uint4*)u.X;     // X starts on a 16-byte boundary
+  const bool bf = u.xbf16 != 0;
+  const int es = bf ? 8 : 4;               // elements per 16-byte word
+  const int64_t nw = n / es;
   unsigned m = 0;
-  if (u.xbf16) {
+  int64_t q = (int64_t)bx * 256 + tid;
+  for (; q + 3 * stride < nw; q += 4 * stride) {   // four loads in flight
+    const uint4 a = x4[q], b = x4[q + stride], c = x4[q + 2 * stride], e = x4[q + 3 * stride];
+    m = max(m, max(max(xb_word(a, bf), xb_word(b, bf)), max(xb_word(c, bf), xb_word(e, bf))));
+  }
+  for (; q < nw; q += stride) m = max(m, xb_word(x4[q], bf));
+  if (bf) {
     const uint16_t* x = (const uint16_t*)u.X;
-    const int64_t n8 = n / 8;
-    for (int64_t q = (int64_t)bx * 256 + tid; q < n8; q += stride) {
-      const uint4 v = x4[q];
-      const unsigned a = max(v.x & 0x7fff7fffu, v.y & 0x7fff7fffu), b = max(v.z & 0x7fff7fffu, v.w & 0x7fff7fffu);
-      m = max(m, max(max(a >> 16, a & 0xffffu), max(b >> 16, b & 0xffffu)));
-    }
-    for (int64_t i = n8 * 8 + (int64_t)bx * 256 + tid; i < n; i += stride) m = max(m, (unsigned)(x[i] & 0x7fffu));
+    for (int64_t i = nw * es + (int64_t)bx * 256 + tid; i < n; i += stride) m = max(m, (unsigned)(x[i] & 0x7fffu));
     m <<= 16;
   } else {
     const unsigned* x = (const unsigned*)u.X;
-    const int64_t n4 = n / 4;
-    for (int64_t q = (int64_t)bx * 256 + tid; q < n4; q += stride) {
-      const uint4 v = x4[q];
-      m = max(m, max(max(v.x & 0x7fffffffu, v.y & 0x7fffffffu), max(v.z & 0x7fffffffu, v.w & 0x7fffffffu)));
-    }
-    for (int64_t i = n4 * 4 + (int64_t)bx * 256 + tid; i < n; i += stride) m = max(m, x[i] & 0x7fffffffu);
+    for (int64_t i = nw * es + (int64_t)bx * 256 + tid; i < n; i += stride) m = max(m, x[i] & 0x7fffffffu);
   }
   m = wave_umax(m);
   if ((tid & 63) == 0) wm[tid >> 6] = m;
@@ -389,8 +405,12 @@ __device__ __forceinline__ int fx_exponent(unsigned bits, int64_t n) {
   const int E = (int)(bits >> 23);
   const int eb = E == 0 ? -126 : E - 126;                 // max|x| < 2^eb
   const int ln = 64 - __clzll((unsigned long long)n);     // n < 2^ln
-  return 62 - eb - ln;
+  const int e = 62 - eb - ln;
+  return e < 51 - eb ? e : 51 - eb;
 }
+
+constexpr double kFxMagic = 0x1.8p52;                      // 1.5 * 2^52
+constexpr unsigned long long kFxMagicBits = 0x4338000000000000ull;
 
 // The bound over all slots (every thread of a kFxThreads workgroup).
 __device__ __forceinline__ unsigned fx_bound(const UpdateArgs& u, unsigned* sh) {
@@ -405,14 +425,9 @@ __device__ __forceinline__ unsigned fx_bound(const UpdateArgs& u, unsigned* sh) 
   return b;
 }
 
-// round(v * s) as a two's complement int64: v * s is exact (s a power of
-// two, v a float32); hi = floor(q / 2^32) and lo = q - hi * 2^32 in [0, 2^32)
-// are exact in float64.
+// round(v * s) + bits(1.5 * 2^52), |v * s| < 2^51 (see above)
 __device__ __forceinline__ unsigned long long fx_quant(float v, double s) {
-  const double q = rint((double)v * s);
-  const double hi = floor(q * 0x1p-32);
-  const double lo = fma(hi, -0x1p32, q);
-  return ((unsigned long long)(long long)(int)hi << 32) + (unsigned long long)(unsigned)lo;
+  return (unsigned long long)__double_as_longlong(fma((double)v, s, kFxMagic));
 }
 
 __device__ __forceinline__ int fx_label(const int* lab, int64_t r, int K) {
@@ -433,66 +448,82 @@ __device__ __forceinline__ float fx_load1(const UpdateArgs& u, int64_t i) {
   return u.xbf16 ? __uint_as_float((unsigned)((const uint16_t*)u.X)[i] << 16) : ((const float*)u.X)[i];
 }
 
-// Workgroup bx of P: rows [bx * ceil(N/P), ...) into acc (K*d + K entries).
+// Workgroup bx of P.  The workgroups sweep X together: step t of workgroup
+// bx takes the T coordinate groups starting at group (t * P + bx) * T.  Any
+// split of the rows gives the same integer sums.  The lane that holds
+// coordinate group 0 of a row also adds the row to its cluster's size, so the
+// labels are read once.
 __device__ __forceinline__ void fxsum_body(const UpdateArgs& u, int bx, int P, unsigned long long* acc) {
   if (u.gated && u.ctl->done) return;
   __shared__ unsigned bsh[kFxThreads / 64];
   constexpr int T = kFxThreads;
   const int tid = threadIdx.x;
   const int d = u.d, K = u.K, KD = K * d, L = KD + K;
+  const int S = fx_stride(d), KS = K * S;   // LDS: sums of cluster j at j*S, sizes at KS
   const int* lab = labels_of(u);
-  for (int i = tid; i < L; i += T) acc[i] = 0ull;
+  for (int i = tid; i < KS + K; i += T) acc[i] = 0ull;
   if (bx == 0 && tid == 0) u.ctl->empty = 0;     // the reduction adds the empty clusters
   const double s = ldexp(1.0, fx_exponent(fx_bound(u, bsh), u.N));   // ends with a barrier
-  const int64_t rows = (u.N + P - 1) / P;
-  const int64_t r0 = (int64_t)bx * rows;
-  const int64_t r1 = r0 + rows < u.N ? r0 + rows : u.N;
-  if (r0 < r1) {
-    // consecutive threads take consecutive groups of g coordinates; (row, col)
-    // of a thread's group advances by T groups per step
-    const int g = (d & 3) == 0 ? 4 : 1;
-    const int qd = d / g;
-    const int64_t ng = (r1 - r0) * qd;
-    const int drow = T / qd, dcol = T % qd;
-    int64_t row = r0 + tid / qd;
-    int col = tid % qd;
-    int64_t q = tid;
-    if (g == 4) {
-      for (; q + T < ng; q += 2 * T) {
-        int64_t rowb = row + drow;
-        int colb = col + dcol;
-        if (colb >= qd) { colb -= qd; ++rowb; }
-        const float4 va = fx_load4(u, row * d + 4 * col), vb = fx_load4(u, rowb * d + 4 * colb);
-        const int ja = fx_label(lab, row, K), jb = fx_label(lab, rowb, K);
-        unsigned long long* a = acc + ja * d + 4 * col;
-        atomicAdd(a + 0, fx_quant(va.x, s)); atomicAdd(a + 1, fx_quant(va.y, s));
-        atomicAdd(a + 2, fx_quant(va.z, s)); atomicAdd(a + 3, fx_quant(va.w, s));
-        unsigned long long* b = acc + jb * d + 4 * colb;
-        atomicAdd(b + 0, fx_quant(vb.x, s)); atomicAdd(b + 1, fx_quant(vb.y, s));
-        atomicAdd(b + 2, fx_quant(vb.z, s)); atomicAdd(b + 3, fx_quant(vb.w, s));
-        row = rowb + drow;
-        col = colb + dcol;
-        if (col >= qd) { col -= qd; ++row; }
-      }
-      if (q < ng) {
-        const float4 va = fx_load4(u, row * d + 4 * col);
-        unsigned long long* a = acc + fx_label(lab, row, K) * d + 4 * col;
-        atomicAdd(a + 0, fx_quant(va.x, s)); atomicAdd(a + 1, fx_quant(va.y, s));
-        atomicAdd(a + 2, fx_quant(va.z, s)); atomicAdd(a + 3, fx_quant(va.w, s));
-      }
-    } else {
-      for (; q < ng; q += T) {
-        atomicAdd(acc + fx_label(lab, row, K) * d + col, fx_quant(fx_load1(u, row * d + col), s));
-        row += drow;
-        col += dcol;
-        if (col >= qd) { col -= qd; ++row; }
-      }
+  // consecutive threads take consecutive groups of g coordinates; (row, col)
+  // of a thread's group advances by P * T groups per step
+  const int g = (d & 3) == 0 ? 4 : 1;
+  const int qd = d / g;
+  const int64_t ng = u.N * qd;
+  const int64_t stride = (int64_t)P * T;
+  const int64_t g0 = (int64_t)bx * T + tid;
+  const int64_t drow = stride / qd;
+  const int dcol = (int)(stride % qd);
+  int64_t row = g0 / qd;
+  int col = (int)(g0 % qd);
+  int64_t q = g0;
+  if (g == 4) {
+    for (; q + stride < ng; q += 2 * stride) {
+      int64_t rowb = row + drow;
+      int colb = col + dcol;
+      if (colb >= qd) { colb -= qd; ++rowb; }
+      const float4 va = fx_load4(u, row * d + 4 * col), vb = fx_load4(u, rowb * d + 4 * colb);
+      const int ja = fx_label(lab, row, K), jb = fx_label(lab, rowb, K);
+      unsigned long long* a = acc + ja * S + 4 * col;
+      atomicAdd(a + 0, fx_quant(va.x, s)); atomicAdd(a + 1, fx_quant(va.y, s));
+      atomicAdd(a + 2, fx_quant(va.z, s)); atomicAdd(a + 3, fx_quant(va.w, s));
+      if (col == 0) atomicAdd(acc + KS + ja, 1ull);
+      unsigned long long* b = acc + jb * S + 4 * colb;
+      atomicAdd(b + 0, fx_quant(vb.x, s)); atomicAdd(b + 1, fx_quant(vb.y, s));
+      atomicAdd(b + 2, fx_quant(vb.z, s)); atomicAdd(b + 3, fx_quant(vb.w, s));
+      if (colb == 0) atomicAdd(acc + KS + jb, 1ull);
+      row = rowb + drow;
+      col = colb + dcol;
+      if (col >= qd) { col -= qd; ++row; }
     }
-    for (int64_t r = r0 + tid; r < r1; r += T) atomicAdd(acc + KD + fx_label(lab, r, K), 1ull);
+    if (q < ng) {
+      const float4 va = fx_load4(u, row * d + 4 * col);
+      const int ja = fx_label(lab, row, K);
+      unsigned long long* a = acc + ja * S + 4 * col;
+      atomicAdd(a + 0, fx_quant(va.x, s)); atomicAdd(a + 1, fx_quant(va.y, s));
+      atomicAdd(a + 2, fx_quant(va.z, s)); atomicAdd(a + 3, fx_quant(va.w, s));
+      if (col == 0) atomicAdd(acc + KS + ja, 1ull);
+    }
+  } else {
+    for (; q < ng; q += stride) {
+      const int j = fx_label(lab, row, K);
+      atomicAdd(acc + j * S + col, fx_quant(fx_load1(u, row * d + col), s));
+      if (col == 0) atomicAdd(acc + KS + j, 1ull);   // the row's size, once per row
+      row += drow;
+      col += dcol;
+      if (col >= qd) { col -= qd; ++row; }
+    }
   }
   __syncthreads();
+  // partials dense: sums (K x d) then sizes (K)
   unsigned long long* part = u.fxpart + (int64_t)bx * L;
-  for (int i = tid; i < L; i += T) part[i] = acc[i];
+  for (int i = tid; i < L; i += T) {
+    if (i < KD) {
+      const int j = (int)((unsigned)i / (unsigned)d), k = i - j * d;
+      part[i] = acc[j * S + k] - acc[KS + j] * kFxMagicBits;
+    } else {
+      part[i] = acc[KS + i - KD];
+    }
+  }
 }
 
 // 64 entries per workgroup: sums of the fx_blocks(N) partials (16 waves split

@@ -319,10 +319,10 @@ def _mean_bound_check(X, C, rho, Cn):
     assert (err <= tol).all(), float((err / tol).max())
 
 
-# The fixed-point sums take K*d + K <= 10240 (80 KB of LDS accumulators);
-# larger shapes take the counting sort.  Both sides of the limit, float32 and
-# bfloat16 rows, d with and without 4-coordinate groups.
-@pytest.mark.parametrize("d,K,xt", [(16, 602, "f32"), (16, 603, "f32"), (7, 1280, "bf16"),
+# The fixed-point sums take K * (d | 1) + K <= 10240 (80 KB of LDS
+# accumulators); larger shapes take the counting sort.  Both sides of the
+# limit, float32 and bfloat16 rows, d with and without 4-coordinate groups.
+@pytest.mark.parametrize("d,K,xt", [(16, 568, "f32"), (16, 569, "f32"), (7, 1280, "bf16"),
                                     (7, 1281, "bf16"), (12, 100, "bf16"), (5, 64, "f32")])
 def test_update_sums_both_paths(d, K, xt):
     km = _lib()
@@ -348,3 +348,21 @@ def test_update_fixed_point_wide_range():
     a = ko.assign(X.astype(np.float64), C.astype(np.float64))
     mism = np.flatnonzero(a.rho != rho.cpu().numpy())
     assert (a.near_tie[mism]).all()
+
+
+@pytest.mark.parametrize("xt", ["f32", "bf16"])
+@pytest.mark.parametrize("pos", [0, 1, 2, 3, 4, 5, 6, 7, 40001, -1])
+def test_update_bound_sees_every_position(xt, pos):
+    """One coordinate 3e4 times larger than the rest, at each position inside
+    a 16-byte word and in the ragged tail: the |x| bound must include it, or
+    the fixed-point sums of its cluster overflow."""
+    km = _lib()
+    rng = np.random.default_rng(7)
+    N, d, K = 9001, 9, 12                 # N*d not a multiple of 8: a ragged tail
+    X = rng.normal(size=(N, d)).astype(np.float32)
+    X.reshape(-1)[pos] = 3e4
+    if xt == "bf16":
+        X = synth.to_bf16_bits(X)
+    C = x_values(X)[rng.choice(N, K, replace=False)].astype(np.float32)
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C))
+    _mean_bound_check(X, C, rho.cpu().numpy(), Cn.cpu().numpy())
