@@ -211,6 +211,7 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = 0; f.partial = c->w.partial; f.item_start = c->w.item_start;
   f.counts = c->w.counts; f.C_in = C; f.C_out = C_out; f.ctl = c->w.ctl; f.mode = kFinG;
+  f.fx = u.fx;
   f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
   f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
   HIP_TRY(c, launch_finalize(f, st_), "finalize");
@@ -312,6 +313,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   f.C_cand = c->w.C_cand; f.C_fb = c->w.C_fb;
   f.G_last = c->w.G_last; f.F_last = c->w.F_last; f.ring_dF = c->w.ring_dF; f.ring_dG = c->w.ring_dG;
   f.dots = c->w.dots; f.ctl = c->w.ctl; f.mode = kFinInit;
+  f.fx = u.fx;
   CombineArgs cb{};
   cb.ctl = c->w.ctl; cb.gated = 0; cb.G_last = c->w.G_last; cb.ring_dG = c->w.ring_dG;
   cb.K = K; cb.d = d; cb.cap = cap;

@@ -258,6 +258,7 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   f.C_cand = w.C_cand; f.C_fb = w.C_fb;
   f.G_last = w.G_last; f.F_last = w.F_last; f.ring_dF = w.ring_dF; f.ring_dG = w.ring_dG;
   f.dots = w.dots; f.ctl = w.ctl; f.mode = kFinInit;
+  f.fx = u.fx;
   r.f_init = f;
   r.f_iter = f;
   r.f_iter.mode = kFinIter; r.f_iter.C_in = nullptr;

@@ -71,15 +71,15 @@ struct UpdateArgs {
   Ctl* ctl;
   int gated;              // 1: skip when ctl->done
   int fx;                 // 1: fixed-point sums (fx_ok(K, d)) instead of the counting sort
-  unsigned* xbound;       // kXBoundSlots per-workgroup maxima of the |x| bit patterns
+  unsigned* xbound;       // kXBoundSlots per-workgroup maxima of the |x| bit patterns, then e
   unsigned long long* fxpart;  // fx_blocks(N) x (K*d + K) int64 partials
 };
 int update_max_items(int64_t N, int K);
 // blockcount entries a workspace for (N, K) must hold: enough for any K' <= K
 size_t update_blockcount_ints(int64_t N, int K);
 hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s);
-// Bound of |x| over X for the fixed-point sums (u.fx only): once per X, before
-// the first update with it.
+// Bound of |x| over X and the scale exponent e of the fixed-point sums
+// (u.fx only): once per X, before the first update with it.
 hipError_t launch_xbound(const UpdateArgs& u, hipStream_t s);
 // workgroups of update kernel `which` (0 rank, 1 scan, 2 scatter, 3 segsum,
 // 4 fixed-point sums, 5 their reduction, 6 the |x| bound); 0 where the
@@ -116,6 +116,7 @@ struct FinalizeArgs {
   double* dots;           // per-workgroup partial inner products (2 x cap each)
   Ctl* ctl;
   FinMode mode;
+  int fx;                 // 1: fixed-point sums (partial[j*d + k] is the sum of element (j, k))
 };
 int finalize_grid(int64_t KD);
 hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s);

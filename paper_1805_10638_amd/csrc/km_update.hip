@@ -412,18 +412,24 @@ __device__ __forceinline__ int fx_exponent(unsigned bits, int64_t n) {
 constexpr double kFxMagic = 0x1.8p52;                      // 1.5 * 2^52
 constexpr unsigned long long kFxMagicBits = 0x4338000000000000ull;
 
-// The bound over all slots (every thread of a kFxThreads workgroup).
-__device__ __forceinline__ unsigned fx_bound(const UpdateArgs& u, unsigned* sh) {
+// One workgroup of kFxThreads: the bound over all slots, then e into slot
+// kXBoundSlots (once per X, so the sums read one word instead of reducing
+// the slots behind a barrier).
+__device__ __forceinline__ void xexp_body(const UpdateArgs& u) {
+  __shared__ unsigned sh[kFxThreads / 64];
   const int tid = threadIdx.x;
   unsigned m = tid < kXBoundSlots ? u.xbound[tid] : 0u;
   m = wave_umax(m);
   if ((tid & 63) == 0) sh[tid >> 6] = m;
   __syncthreads();
-  unsigned b = 0;
-#pragma unroll
-  for (int w = 0; w < kFxThreads / 64; ++w) b = max(b, sh[w]);
-  return b;
+  if (tid == 0) {
+    unsigned b = 0;
+    for (int w = 0; w < kFxThreads / 64; ++w) b = max(b, sh[w]);
+    u.xbound[kXBoundSlots] = (unsigned)fx_exponent(b, u.N);
+  }
 }
+
+__device__ __forceinline__ int fx_exp_of(const UpdateArgs& u) { return (int)u.xbound[kXBoundSlots]; }
 
 // round(v * s) + bits(1.5 * 2^52), |v * s| < 2^51 (see above)
 __device__ __forceinline__ unsigned long long fx_quant(float v, double s) {
@@ -455,7 +461,6 @@ __device__ __forceinline__ float fx_load1(const UpdateArgs& u, int64_t i) {
 // labels are read once.
 __device__ __forceinline__ void fxsum_body(const UpdateArgs& u, int bx, int P, unsigned long long* acc) {
   if (u.gated && u.ctl->done) return;
-  __shared__ unsigned bsh[kFxThreads / 64];
   constexpr int T = kFxThreads;
   const int tid = threadIdx.x;
   const int d = u.d, K = u.K, KD = K * d, L = KD + K;
@@ -463,7 +468,8 @@ __device__ __forceinline__ void fxsum_body(const UpdateArgs& u, int bx, int P, u
   const int* lab = labels_of(u);
   for (int i = tid; i < KS + K; i += T) acc[i] = 0ull;
   if (bx == 0 && tid == 0) u.ctl->empty = 0;     // the reduction adds the empty clusters
-  const double s = ldexp(1.0, fx_exponent(fx_bound(u, bsh), u.N));   // ends with a barrier
+  const double s = ldexp(1.0, fx_exp_of(u));
+  __syncthreads();                                // accumulators cleared
   // consecutive threads take consecutive groups of g coordinates; (row, col)
   // of a thread's group advances by P * T groups per step
   const int g = (d & 3) == 0 ? 4 : 1;
@@ -532,11 +538,10 @@ __device__ __forceinline__ void fxsum_body(const UpdateArgs& u, int bx, int P, u
 __device__ __forceinline__ void fxreduce_body(const UpdateArgs& u, int bx) {
   if (u.gated && u.ctl->done) return;
   __shared__ unsigned long long r[kFxThreads / 64][64];
-  __shared__ unsigned bsh[kFxThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int KD = u.K * u.d, L = KD + u.K;
   const int P = fx_blocks(u.N);
-  const double inv = ldexp(1.0, -fx_exponent(fx_bound(u, bsh), u.N));   // ends with a barrier
+  const double inv = ldexp(1.0, -fx_exp_of(u));
   const int e = bx * 64 + lane;
   unsigned long long t = 0;
   if (e < L) {
@@ -604,6 +609,11 @@ __global__ __launch_bounds__(kFxThreads) void k_fxsum(UpdateArgs u) {
   fxsum_body(u, blockIdx.x, gridDim.x, fx_acc);
 }
 __global__ __launch_bounds__(kFxThreads) void k_fxreduce(UpdateArgs u) { fxreduce_body(u, blockIdx.x); }
+__global__ __launch_bounds__(kFxThreads) void k_xexp(UpdateArgs u) { xexp_body(u); }
+__global__ __launch_bounds__(kFxThreads) void k_xexp_batch(BatchRef<UpdateArgs> t) {
+  const UpdateArgs& u = t.tab[blockIdx.x];   // one workgroup per instance
+  if (u.fx) xexp_body(u);
+}
 
 __global__ __launch_bounds__(256) void k_xbound_batch(BatchRef<UpdateArgs> t) {
   const int b = batch_find(t.prefix, t.n, blockIdx.x);
@@ -636,6 +646,7 @@ hipError_t launch_xbound(const UpdateArgs& u, hipStream_t s) {
   if (!u.fx) return hipSuccess;
   clear_pending_error();
   hipLaunchKernelGGL(k_xbound, dim3(kXBoundSlots), dim3(256), 0, s, u);
+  hipLaunchKernelGGL(k_xexp, dim3(1), dim3(kFxThreads), 0, s, u);
   return hipGetLastError();
 }
 
@@ -643,6 +654,7 @@ hipError_t launch_xbound_batch(const UpdateBatch& ub, hipStream_t s) {
   clear_pending_error();
   if (ub.n <= 0 || ub.blocks[6] <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_xbound_batch, dim3(ub.blocks[6]), dim3(256), 0, s, BatchRef<UpdateArgs>{ub.tab, ub.prefix[6], ub.n});
+  hipLaunchKernelGGL(k_xexp_batch, dim3(ub.n), dim3(kFxThreads), 0, s, BatchRef<UpdateArgs>{ub.tab, nullptr, ub.n});
   return hipGetLastError();
 }
 
@@ -732,19 +744,23 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs& f, int bx, int
   for (int64_t e = (int64_t)bx * 256 + tid; e < KD; e += stride) {
     const int j = (int)((uint32_t)e / (uint32_t)d);   // K*d < 2^31
     const int n = f.counts[j];
-    const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
-    const int k = (int)(e - (int64_t)j * d);
-    // item partials in order, eight loads in flight
     double sum = 0.0;
-    int it = i0;
-    for (; it + 8 <= i1; it += 8) {
-      double v[8];
+    if (f.fx) {
+      sum = f.partial[e];
+    } else {
+      const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
+      const int k = (int)(e - (int64_t)j * d);
+      // item partials in order, eight loads in flight
+      int it = i0;
+      for (; it + 8 <= i1; it += 8) {
+        double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = f.partial[(int64_t)(it + q) * d + k];
+        for (int q = 0; q < 8; ++q) v[q] = f.partial[(int64_t)(it + q) * d + k];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sum += v[q];
+        for (int q = 0; q < 8; ++q) sum += v[q];
+      }
+      for (; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
     }
-    for (; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
     if (f.mode == kFinG) {
       f.C_out[e] = (float)(n > 0 ? sum / (double)n : (double)f.C_in[e]);
       continue;

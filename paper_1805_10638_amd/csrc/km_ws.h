@@ -35,7 +35,7 @@ struct Ws {
   int* item_cluster = nullptr;  // max_items
   double* e_part = nullptr;     // 2 x (N / 64 + 1): partials of the candidate and fall-back passes
   double* partial = nullptr;    // max_items x d
-  unsigned* xbound = nullptr;   // kXBoundSlots (fixed-point update)
+  unsigned* xbound = nullptr;   // kXBoundSlots + 1 (fixed-point update: maxima, then e)
   unsigned long long* fxpart = nullptr;  // fx_part_entries(N, K, d)
   double* G_last = nullptr;     // K x d
   double* F_last = nullptr;     // K x d
@@ -81,7 +81,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const size_t o_ic = take((size_t)max_items * 4);
   const size_t o_ep = take((size_t)2 * grid * 8);
   const size_t o_pa = take((size_t)max_items * s.d * 8);
-  const size_t o_xb = take((size_t)kXBoundSlots * 4);
+  const size_t o_xb = take((size_t)(kXBoundSlots + 1) * 4);
   const size_t o_fx = take((size_t)fx_part_entries(N, s.K, s.d) * 8);
   const size_t o_gl = take(KD * 8);
   const size_t o_fl = take(KD * 8);
