@@ -28,25 +28,34 @@ __device__ int ls_solve_group(const CombineArgs& a, int s_new, int len_new, int 
                               int* cols, int* misc) {
   const int cap = a.cap;
   const int tid = threadIdx.x;
-  // fixed-order sums of the per-workgroup partials: new Gram row and rhs
-  for (int q = tid; q < len_new; q += blockDim.x) {
-    const int sl = (s_new - q + cap) % cap;
-    double ga = 0.0, gb = 0.0;
-    for (int w0 = 0; w0 < a.n_dots; w0 += 8) {   // partials in order, 16 loads in flight
-      double va[8], vb[8];
+  // Fixed-order sums of the per-workgroup partials: new Gram row (sums
+  // 0..len_new) and rhs (len_new..2 len_new).  Eight lanes share a sum: lane
+  // r adds partials r, r + 8, ... in order (up to eight loads in flight),
+  // then the eight lane sums are added by a fixed shuffle tree.
+  for (int p0 = 0; p0 < 2 * len_new; p0 += (int)blockDim.x / 8) {
+    const int p = p0 + tid / 8, r = tid & 7;
+    double v = 0.0;
+    if (p < 2 * len_new) {
+      const int q = p < len_new ? p : p - len_new;
+      const int col = (p < len_new ? 0 : cap) + (s_new - q + cap) % cap;
+      for (int w0 = r; w0 < a.n_dots; w0 += 64) {
+        double t[8];
 #pragma unroll
-      for (int q8 = 0; q8 < 8; ++q8) {
-        const bool ok = w0 + q8 < a.n_dots;
-        va[q8] = ok ? a.dots[(int64_t)(w0 + q8) * 2 * cap + sl] : 0.0;
-        vb[q8] = ok ? a.dots[(int64_t)(w0 + q8) * 2 * cap + cap + sl] : 0.0;
-      }
+        for (int u = 0; u < 8; ++u) {
+          const int w = w0 + 8 * u;
+          t[u] = w < a.n_dots ? a.dots[(int64_t)w * 2 * cap + col] : 0.0;
+        }
 #pragma unroll
-      for (int q8 = 0; q8 < 8; ++q8) {
-        if (w0 + q8 < a.n_dots) { ga += va[q8]; gb += vb[q8]; }
+        for (int u = 0; u < 8; ++u) v += t[u];
       }
     }
-    newrow[q] = ga;
-    bvec[q] = gb;
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    v += __shfl_xor(v, 4, 8);
+    if (p < 2 * len_new && r == 0) {
+      if (p < len_new) newrow[p] = v;
+      else bvec[p - len_new] = v;
+    }
   }
   __syncthreads();
   auto gram = [&](int q, int r) -> double {   // Gram entry of columns q, r
@@ -243,16 +252,16 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
     const int64_t e = (int64_t)j * d + k;
     const double g = a.G_last[e];
     double v = g;
-    for (int q0 = 0; q0 < mt; q0 += 4) {   // history columns in order, 4 loads in flight
-      double r[4];
+    for (int q0 = 0; q0 < mt; q0 += 8) {   // history columns in order, 8 loads in flight
+      double r[8];
 #pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4) {
-        const int sl = (head - (q0 + q4) + cap) % cap;
-        r[q4] = q0 + q4 < mt ? a.ring_dG[(int64_t)sl * KD + e] : 0.0;
+      for (int q8 = 0; q8 < 8; ++q8) {
+        const int sl = (head - (q0 + q8) + cap) % cap;
+        r[q8] = q0 + q8 < mt ? a.ring_dG[(int64_t)sl * KD + e] : 0.0;
       }
 #pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4)
-        if (q0 + q4 < mt) v -= th[q0 + q4] * r[q4];
+      for (int q8 = 0; q8 < 8; ++q8)
+        if (q0 + q8 < mt) v -= th[q0 + q8] * r[q8];
     }
     put_centroid(a.C_cand, a.Cb_cand, KD, e, v, &n_c, &e_c);
     put_centroid(a.C_fb, a.Cb_fb, KD, e, g, &n_f, &e_f);

@@ -349,8 +349,11 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   ci.gated = 1;
   ci.dots = c->w.dots; ci.n_dots = finalize_grid(KD); ci.gram = c->w.gram; ci.trace_rec = opt.trace_rec;
 
-  // The candidate assignment is launched directly (between two HIP events
-  // when timing is on); the rest of the iteration is replayed from a graph.
+  // The iteration is replayed from a graph.  With timing on, the candidate
+  // assignment is launched directly between two HIP events and the graph
+  // holds the rest; with timing off it is the graph's first node, so one
+  // iteration is one graph launch (no graph-to-stream transition between
+  // iterations).
   CtlArgs k1{};
   k1.ctl = c->w.ctl; k1.e_part = c->w.e_part; k1.n_part = grid; k1.stage = 1;
   k1.tr.trace_C = opt.trace_C; k1.tr.trace_rec = opt.trace_rec; k1.tr.C_cand = c->w.C_cand;
@@ -362,9 +365,11 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   // pinned slot p (no copy node).
   int* done_dev = nullptr;
   HIP_TRY(c, hipHostGetDevicePointer((void**)&done_dev, c->done_host, 0), "hipHostGetDevicePointer");
+  const bool cand_in_graph = !c->timing;
   auto enqueue_rest = [&](int p) -> km_status {
     CombineArgs cp = ci;
     cp.done_out = done_dev + p;
+    if (cand_in_graph) HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
     HIP_TRY(c, launch_controller(k1, q), "controller");
     HIP_TRY(c, launch_assign(af, kRoleFallback, q), "assignment");
     HIP_TRY(c, launch_controller(k2, q), "controller");
@@ -375,8 +380,8 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   };
 
   char keybuf[512];
-  snprintf(keybuf, sizeof keybuf, "%p|%d|%lld|%d|%d|%d|%d|%d|%p|%p|%p", X, (int)xt, (long long)N, d, K,
-           cap, (int)gbf, a.shape, (void*)opt.trace_C, (void*)opt.trace_rec, c->arena);
+  snprintf(keybuf, sizeof keybuf, "%p|%d|%lld|%d|%d|%d|%d|%d|%p|%p|%p|%d", X, (int)xt, (long long)N, d, K,
+           cap, (int)gbf, a.shape, (void*)opt.trace_C, (void*)opt.trace_rec, c->arena, (int)cand_in_graph);
   if (c->gkey != keybuf) {
     for (hipGraphExec_t& g : c->gexec) {
       if (g) (void)hipGraphExecDestroy(g);
@@ -404,14 +409,19 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   while (launched < opt.max_iter && !finished) {
     const int it = launched;
     const int p = it & 1;
-    if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[p], q), "hipEventRecord");
-    HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
-    if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[p], q), "hipEventRecord");
+    if (!cand_in_graph) {
+      HIP_TRY(c, hipEventRecord(c->ta[p], q), "hipEventRecord");
+      HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
+      HIP_TRY(c, hipEventRecord(c->tb[p], q), "hipEventRecord");
+    }
     HIP_TRY(c, hipGraphLaunch(c->gexec[p], q), "hipGraphLaunch");
-    HIP_TRY(c, hipEventRecord(c->poll_ev[p], q), "hipEventRecord");
+    // Each event record costs the device a few microseconds between kernels,
+    // so with timing on the start event of iteration it also marks the end of
+    // iteration it - 1; with timing off one event per iteration does.
+    if (cand_in_graph) HIP_TRY(c, hipEventRecord(c->poll_ev[p], q), "hipEventRecord");
     if (it >= 1) {
       const int pp = (it - 1) & 1;
-      HIP_TRY(c, hipEventSynchronize(c->poll_ev[pp]), "hipEventSynchronize");
+      HIP_TRY(c, hipEventSynchronize(cand_in_graph ? c->poll_ev[pp] : c->ta[p]), "hipEventSynchronize");
       if (c->timing) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ta[pp], c->tb[pp]) != hipSuccess) {

@@ -721,7 +721,7 @@ int update_grid(const UpdateArgs& u, int which) {
 // ---------------------------------------------------------------------------
 // 6. means, residual, history push and Gram partials (one thread per element)
 // ---------------------------------------------------------------------------
-constexpr int kDotGroup = 8;    // history slots reduced per pass over the elements
+constexpr int kDotGroup = 12;   // history slots reduced per pass over the elements (m_max <= 12 in one pass)
 
 __device__ __forceinline__ void finalize_body(const FinalizeArgs& f, int bx, int gx) {
   Ctl* ctl = f.ctl;
