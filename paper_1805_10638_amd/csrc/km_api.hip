@@ -211,7 +211,7 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = 0; f.partial = c->w.partial; f.item_start = c->w.item_start;
   f.counts = c->w.counts; f.C_in = C; f.C_out = C_out; f.ctl = c->w.ctl; f.mode = kFinG;
-  f.fx = u.fx;
+  f.fx = u.fx; f.fxpart = c->w.fxpart; f.xbound = c->w.xbound; f.N = N;
   f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
   f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
   HIP_TRY(c, launch_finalize(f, st_), "finalize");
@@ -313,7 +313,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   f.C_cand = c->w.C_cand; f.C_fb = c->w.C_fb;
   f.G_last = c->w.G_last; f.F_last = c->w.F_last; f.ring_dF = c->w.ring_dF; f.ring_dG = c->w.ring_dG;
   f.dots = c->w.dots; f.ctl = c->w.ctl; f.mode = kFinInit;
-  f.fx = u.fx;
+  f.fx = u.fx; f.fxpart = c->w.fxpart; f.xbound = c->w.xbound; f.N = N;
   CombineArgs cb{};
   cb.ctl = c->w.ctl; cb.gated = 0; cb.G_last = c->w.G_last; cb.ring_dG = c->w.ring_dG;
   cb.K = K; cb.d = d; cb.cap = cap;
@@ -347,7 +347,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   fi.mode = kFinIter; fi.C_in = nullptr;
   CombineArgs ci = cb;
   ci.gated = 1;
-  ci.dots = c->w.dots; ci.n_dots = finalize_grid(KD); ci.gram = c->w.gram; ci.trace_rec = opt.trace_rec;
+  ci.dots = c->w.dots; ci.n_dots = finalize_grid_for(u.fx, K, d); ci.gram = c->w.gram; ci.trace_rec = opt.trace_rec;
 
   // The iteration is replayed from a graph.  With timing on, the candidate
   // assignment is launched directly between two HIP events and the graph

@@ -110,8 +110,8 @@ struct km_engine {
     size_t lds = 0;
   };
   std::vector<Bucket> it_buckets;
-  size_t o_k1 = 0, o_k2 = 0, o_u = 0, o_upre[kUpdateKinds] = {}, o_fi = 0, o_fpre = 0, o_cb = 0, o_cpre = 0, o_ctls = 0;
-  int ublocks[kUpdateKinds] = {}, fblocks = 0, cblocks = 0, n_it = 0;
+  size_t o_k1 = 0, o_k2 = 0, o_u = 0, o_upre[kUpdateKinds] = {}, o_fi = 0, o_fpre = 0, o_fxpre = 0, o_cb = 0, o_cpre = 0, o_ctls = 0;
+  int ublocks[kUpdateKinds] = {}, fblocks = 0, fxblocks = 0, cblocks = 0, n_it = 0;
 
   // Up to kSlots iterations in flight, each with its slot of done flags
   // (pinned), its poll event and its graph.
@@ -258,7 +258,7 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   f.C_cand = w.C_cand; f.C_fb = w.C_fb;
   f.G_last = w.G_last; f.F_last = w.F_last; f.ring_dF = w.ring_dF; f.ring_dG = w.ring_dG;
   f.dots = w.dots; f.ctl = w.ctl; f.mode = kFinInit;
-  f.fx = u.fx;
+  f.fx = u.fx; f.fxpart = w.fxpart; f.xbound = w.xbound; f.N = s.N;
   r.f_init = f;
   r.f_iter = f;
   r.f_iter.mode = kFinIter; r.f_iter.C_in = nullptr;
@@ -272,7 +272,7 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   cb.delta_fb = gbf ? w.del_fb : nullptr;
   r.c0 = cb;
   r.c1 = cb;
-  r.c1.gated = 1; r.c1.dots = w.dots; r.c1.n_dots = finalize_grid((int64_t)s.K * s.d); r.c1.gram = w.gram;
+  r.c1.gated = 1; r.c1.dots = w.dots; r.c1.n_dots = finalize_grid_for(u.fx, s.K, s.d); r.c1.gram = w.gram;
   r.c1.trace_rec = nullptr;
 
   CtlArgs k{};
@@ -355,7 +355,8 @@ km_status enqueue_iteration(km_engine* e, int p) {
   for (int k = 0; k < kUpdateKinds; ++k) { ub.prefix[k] = dptr<int>(e, e->o_upre[k]); ub.blocks[k] = e->ublocks[k]; }
   ub.n = e->n_it;
   ENG_TRY(e, launch_update_sums_batch(ub, q), "batched update");
-  ENG_TRY(e, launch_finalize_batch(dptr<FinalizeArgs>(e, e->o_fi), dptr<int>(e, e->o_fpre), e->n_it, e->fblocks, q),
+  ENG_TRY(e, launch_finalize_batch(dptr<FinalizeArgs>(e, e->o_fi), dptr<int>(e, e->o_fpre), e->fblocks,
+                                   dptr<int>(e, e->o_fxpre), e->fxblocks, e->n_it, q),
           "batched finalize");
   ENG_TRY(e, launch_combine_batch(dptr<CombineArgs>(e, e->o_cb), dptr<int>(e, e->o_cpre), e->n_it, e->cblocks, q),
           "batched combine");
@@ -446,7 +447,7 @@ km_status rebuild(km_engine* e, bool drain) {
   std::vector<UpdateArgs> pu;
   std::vector<int> pusz[kUpdateKinds];
   std::vector<FinalizeArgs> pf;
-  std::vector<int> pfsz;
+  std::vector<int> pfsz, pfxsz;   // finalisation workgroups: counting-sort, fixed-point instances
   std::vector<CombineArgs> pc;
   std::vector<int> pcsz;
   for (int i = 0; i < na; ++i) {
@@ -457,11 +458,12 @@ km_status rebuild(km_engine* e, bool drain) {
     pu.push_back(aa[i].u);
     for (int k = 0; k < kUpdateKinds; ++k) pusz[k].push_back(update_grid(aa[i].u, k));
     pf.push_back(aa[i].f_init);
-    pfsz.push_back(finalize_grid((int64_t)j->spec.K * j->spec.d));
+    pfsz.push_back(aa[i].u.fx ? 0 : finalize_grid_for(0, j->spec.K, j->spec.d));
+    pfxsz.push_back(aa[i].u.fx ? finalize_grid_for(1, j->spec.K, j->spec.d) : 0);
     pc.push_back(aa[i].c0);
     pcsz.push_back(combine_grid(j->spec.K));
   }
-  int prep_blocks = 0, pub[kUpdateKinds] = {}, pfb = 0, pcb = 0;
+  int prep_blocks = 0, pub[kUpdateKinds] = {}, pfb = 0, pfxb = 0, pcb = 0;
   const size_t o_prep = pk.add(prep), o_prep_pre = pk.add(prefix_of(prep_sz, &prep_blocks));
   std::vector<size_t> o_pb, o_pb_pre;
   std::vector<int> pb_blocks;
@@ -474,7 +476,7 @@ km_status rebuild(km_engine* e, bool drain) {
   const size_t o_pu = pk.add(pu);
   size_t o_pupre[kUpdateKinds];
   for (int k = 0; k < kUpdateKinds; ++k) o_pupre[k] = pk.add(prefix_of(pusz[k], &pub[k]));
-  const size_t o_pf = pk.add(pf), o_pfpre = pk.add(prefix_of(pfsz, &pfb));
+  const size_t o_pf = pk.add(pf), o_pfpre = pk.add(prefix_of(pfsz, &pfb)), o_pfxpre = pk.add(prefix_of(pfxsz, &pfxb));
   const size_t o_pc = pk.add(pc), o_pcpre = pk.add(prefix_of(pcsz, &pcb));
 
   // ---- iteration tables of all jobs ----
@@ -483,7 +485,7 @@ km_status rebuild(km_engine* e, bool drain) {
   std::vector<UpdateArgs> iu;
   std::vector<int> iusz[kUpdateKinds];
   std::vector<FinalizeArgs> fi;
-  std::vector<int> fisz;
+  std::vector<int> fisz, fixsz;
   std::vector<CombineArgs> ci;
   std::vector<int> cisz;
   std::vector<Ctl*> ctls;
@@ -495,7 +497,8 @@ km_status rebuild(km_engine* e, bool drain) {
     iu.push_back(r.u);
     for (int k = 0; k < kUpdateKinds; ++k) iusz[k].push_back(update_grid(r.u, k));
     fi.push_back(r.f_iter);
-    fisz.push_back(finalize_grid((int64_t)j->spec.K * j->spec.d));
+    fisz.push_back(r.u.fx ? 0 : finalize_grid_for(0, j->spec.K, j->spec.d));
+    fixsz.push_back(r.u.fx ? finalize_grid_for(1, j->spec.K, j->spec.d) : 0);
     ci.push_back(r.c1);
     cisz.push_back(combine_grid(j->spec.K));
     ctls.push_back(j->w.ctl);
@@ -517,6 +520,7 @@ km_status rebuild(km_engine* e, bool drain) {
   for (int k = 0; k < kUpdateKinds; ++k) e->o_upre[k] = pk.add(prefix_of(iusz[k], &e->ublocks[k]));
   e->o_fi = pk.add(fi);
   e->o_fpre = pk.add(prefix_of(fisz, &e->fblocks));
+  e->o_fxpre = pk.add(prefix_of(fixsz, &e->fxblocks));
   e->o_cb = pk.add(ci);
   e->o_cpre = pk.add(prefix_of(cisz, &e->cblocks));
   e->o_ctls = pk.add(ctls);
@@ -552,7 +556,8 @@ km_status rebuild(km_engine* e, bool drain) {
     ub.n = na;
     ENG_TRY(e, launch_xbound_batch(ub, q), "batched bound of |x|");
     ENG_TRY(e, launch_update_sums_batch(ub, q), "batched update");
-    ENG_TRY(e, launch_finalize_batch(dptr<FinalizeArgs>(e, o_pf), dptr<int>(e, o_pfpre), na, pfb, q),
+    ENG_TRY(e, launch_finalize_batch(dptr<FinalizeArgs>(e, o_pf), dptr<int>(e, o_pfpre), pfb,
+                                     dptr<int>(e, o_pfxpre), pfxb, na, q),
             "batched finalize");
     ENG_TRY(e, launch_combine_batch(dptr<CombineArgs>(e, o_pc), dptr<int>(e, o_pcpre), na, pcb, q),
             "batched combine");

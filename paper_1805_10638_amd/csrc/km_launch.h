@@ -82,8 +82,8 @@ hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s);
 // (u.fx only): once per X, before the first update with it.
 hipError_t launch_xbound(const UpdateArgs& u, hipStream_t s);
 // workgroups of update kernel `which` (0 rank, 1 scan, 2 scatter, 3 segsum,
-// 4 fixed-point sums, 5 their reduction, 6 the |x| bound); 0 where the
-// instance takes the other path
+// 4 fixed-point sums, 5 unused, 6 the |x| bound); 0 where the instance takes
+// the other path
 constexpr int kUpdateKinds = 7;
 int update_grid(const UpdateArgs& u, int which);
 // Batched update: tab (device) one UpdateArgs per instance; prefix[w]
@@ -116,11 +116,26 @@ struct FinalizeArgs {
   double* dots;           // per-workgroup partial inner products (2 x cap each)
   Ctl* ctl;
   FinMode mode;
-  int fx;                 // 1: fixed-point sums (partial[j*d + k] is the sum of element (j, k))
+  // fixed-point sums (fx = 1): the finalisation also adds the per-workgroup
+  // partials of k_fxsum (N rows, scale exponent in xbound[kXBoundSlots]);
+  // partial, item_start and counts are then unused
+  int fx;
+  const unsigned long long* fxpart;
+  const unsigned* xbound;
+  int64_t N;
 };
-int finalize_grid(int64_t KD);
+// workgroups of the finalisation (and rows of Gram partials it writes)
+int finalize_grid(int64_t KD);                // counting-sort path
+int finalize_grid_for(int fx, int K, int d);  // either path
+// rows of Gram partials a workspace for K*d must hold (either path)
+int finalize_grid_cap(int64_t KD);
 hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s);
-hipError_t launch_finalize_batch(const FinalizeArgs* tab, const int* prefix, int n, int blocks, hipStream_t s);
+// Batched: tab one FinalizeArgs per instance; prefix/blocks for the
+// counting-sort instances (256-thread workgroups) and fxprefix/fxblocks for
+// the fixed-point ones (kFxThreads); an instance has 0 workgroups in the
+// other launch.
+hipError_t launch_finalize_batch(const FinalizeArgs* tab, const int* prefix, int blocks, const int* fxprefix,
+                                 int fxblocks, int n, hipStream_t s);
 
 // ----- controller (Algorithm 1) -----
 struct CtlArgs {

@@ -532,48 +532,6 @@ __device__ __forceinline__ void fxsum_body(const UpdateArgs& u, int bx, int P, u
   }
 }
 
-// 64 entries per workgroup: sums of the fx_blocks(N) partials (16 waves split
-// them), then sums * 2^-e into partial[j*d + k] (one work item per cluster),
-// sizes into counts, item_start[j] = j, and the number of empty clusters.
-__device__ __forceinline__ void fxreduce_body(const UpdateArgs& u, int bx) {
-  if (u.gated && u.ctl->done) return;
-  __shared__ unsigned long long r[kFxThreads / 64][64];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int KD = u.K * u.d, L = KD + u.K;
-  const int P = fx_blocks(u.N);
-  const double inv = ldexp(1.0, -fx_exp_of(u));
-  const int e = bx * 64 + lane;
-  unsigned long long t = 0;
-  if (e < L) {
-    const unsigned long long* p0 = u.fxpart + e;
-    int p = w;
-    for (; p + 48 < P; p += 64) {
-      const unsigned long long a = p0[(int64_t)p * L], b = p0[(int64_t)(p + 16) * L];
-      const unsigned long long c = p0[(int64_t)(p + 32) * L], dd = p0[(int64_t)(p + 48) * L];
-      t += (a + b) + (c + dd);
-    }
-    for (; p < P; p += 16) t += p0[(int64_t)p * L];
-  }
-  r[w][lane] = t;
-  __syncthreads();
-  if (w != 0) return;
-  t = 0;
-#pragma unroll
-  for (int i = 0; i < kFxThreads / 64; ++i) t += r[i][lane];
-  bool empty = false;
-  if (e < KD) {
-    u.partial[e] = (double)(long long)t * inv;
-  } else if (e < L) {
-    const int j = e - KD;
-    u.counts[j] = (int)t;
-    u.item_start[j] = j;
-    if (j == u.K - 1) u.item_start[u.K] = u.K;
-    empty = t == 0;
-  }
-  const unsigned long long em = __ballot(empty);
-  if (lane == 0 && em) atomicAdd(&u.ctl->empty, (int)__popcll(em));
-}
-
 int update_max_items(int64_t N, int K) { return (int)((N + kSegRows - 1) / kSegRows) + K; }
 
 __global__ __launch_bounds__(256) void k_rank(UpdateArgs u) { rank_body(u, blockIdx.x); }
@@ -608,7 +566,6 @@ __global__ __launch_bounds__(kFxThreads) void k_fxsum(UpdateArgs u) {
   extern __shared__ unsigned long long fx_acc[];
   fxsum_body(u, blockIdx.x, gridDim.x, fx_acc);
 }
-__global__ __launch_bounds__(kFxThreads) void k_fxreduce(UpdateArgs u) { fxreduce_body(u, blockIdx.x); }
 __global__ __launch_bounds__(kFxThreads) void k_xexp(UpdateArgs u) { xexp_body(u); }
 __global__ __launch_bounds__(kFxThreads) void k_xexp_batch(BatchRef<UpdateArgs> t) {
   const UpdateArgs& u = t.tab[blockIdx.x];   // one workgroup per instance
@@ -623,10 +580,6 @@ __global__ __launch_bounds__(kFxThreads) void k_fxsum_batch(BatchRef<UpdateArgs>
   extern __shared__ unsigned long long fx_acc[];
   const int b = batch_find(t.prefix, t.n, blockIdx.x);
   fxsum_body(t.tab[b], blockIdx.x - t.prefix[b], t.prefix[b + 1] - t.prefix[b], fx_acc);
-}
-__global__ __launch_bounds__(kFxThreads) void k_fxreduce_batch(BatchRef<UpdateArgs> t) {
-  const int b = batch_find(t.prefix, t.n, blockIdx.x);
-  fxreduce_body(t.tab[b], blockIdx.x - t.prefix[b]);
 }
 
 // Dynamic LDS of the fixed-point sums: kFxMaxL accumulators (above the
@@ -666,8 +619,7 @@ hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
     if (a != hipSuccess) return a;
     clear_pending_error();
     hipLaunchKernelGGL(k_fxsum, dim3(fx_blocks(u.N)), dim3(kFxThreads), kFxLds, s, u);
-    hipLaunchKernelGGL(k_fxreduce, dim3(update_grid(u, 5)), dim3(kFxThreads), 0, s, u);
-    return hipGetLastError();
+    return hipGetLastError();   // the finalisation adds the partials
   }
   const int nblk = update_rank_blocks(u.N, u.K);
   clear_pending_error();
@@ -681,7 +633,8 @@ hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
 
 // Instances on the counting sort get workgroups in kernels 0-3 (and the
 // offsets kernel, one workgroup per instance, returns at once for the others);
-// fixed-point instances in kernels 4-5.
+// fixed-point instances in kernel 4 (their partials are added by the
+// finalisation).
 hipError_t launch_update_sums_batch(const UpdateBatch& ub, hipStream_t s) {
   clear_pending_error();
   if (ub.n <= 0) return hipSuccess;
@@ -697,8 +650,6 @@ hipError_t launch_update_sums_batch(const UpdateBatch& ub, hipStream_t s) {
     if (a != hipSuccess) return a;
     hipLaunchKernelGGL(k_fxsum_batch, dim3(ub.blocks[4]), dim3(kFxThreads), kFxLds, s,
                        BatchRef<UpdateArgs>{ub.tab, ub.prefix[4], ub.n});
-    hipLaunchKernelGGL(k_fxreduce_batch, dim3(ub.blocks[5]), dim3(kFxThreads), 0, s,
-                       BatchRef<UpdateArgs>{ub.tab, ub.prefix[5], ub.n});
   }
   return hipGetLastError();
 }
@@ -712,7 +663,6 @@ int update_grid(const UpdateArgs& u, int which) {
     case 2: return (int)((u.N + 255) / 256);
     case 3: return u.max_items;
     case 4: return fx_blocks(u.N);
-    case 5: return (u.K * u.d + u.K + 63) / 64;
     case 6: return kXBoundSlots;
   }
   return 0;
@@ -744,23 +694,19 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs& f, int bx, int
   for (int64_t e = (int64_t)bx * 256 + tid; e < KD; e += stride) {
     const int j = (int)((uint32_t)e / (uint32_t)d);   // K*d < 2^31
     const int n = f.counts[j];
+    const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
+    const int k = (int)(e - (int64_t)j * d);
+    // item partials in order, eight loads in flight
     double sum = 0.0;
-    if (f.fx) {
-      sum = f.partial[e];
-    } else {
-      const int i0 = f.item_start[j], i1 = f.item_start[j + 1];
-      const int k = (int)(e - (int64_t)j * d);
-      // item partials in order, eight loads in flight
-      int it = i0;
-      for (; it + 8 <= i1; it += 8) {
-        double v[8];
+    int it = i0;
+    for (; it + 8 <= i1; it += 8) {
+      double v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = f.partial[(int64_t)(it + q) * d + k];
+      for (int q = 0; q < 8; ++q) v[q] = f.partial[(int64_t)(it + q) * d + k];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sum += v[q];
-      }
-      for (; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
+      for (int q = 0; q < 8; ++q) sum += v[q];
     }
+    for (; it < i1; ++it) sum += f.partial[(int64_t)it * d + k];
     if (f.mode == kFinG) {
       f.C_out[e] = (float)(n > 0 ? sum / (double)n : (double)f.C_in[e]);
       continue;
@@ -822,30 +768,182 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs& f, int bx, int
   }
 }
 
+// Fixed-point path: the addition of the k_fxsum partials fused with the
+// finalisation.  Workgroup bx (kFxThreads threads) owns the centroid elements
+// e0 = 64 bx ... e0 + 63 and the sizes of the clusters they span.  Its 16
+// waves add the partials (wave w takes partials w, w + 16, ...; then the 16
+// wave sums in order; integer sums, so any order gives the same bits); wave 0
+// then does the work of finalize_body for its 64 elements and writes one row
+// of Gram partials (the combine adds finalize_grid_for rows).
+__device__ __forceinline__ void fxfinal_body(const FinalizeArgs& f, int bx) {
+  Ctl* ctl = f.ctl;
+  if (f.mode == kFinIter && ctl->done) return;
+  constexpr int NW = kFxThreads / 64;
+  __shared__ unsigned long long rs[NW][64], rc[NW][64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int d = f.d, K = f.K, cap = f.cap;
+  const int KD = K * d, L = KD + K;
+  const int P = fx_blocks(f.N);
+  const int e0 = bx * 64, e = e0 + lane;
+  const int j0 = e0 / d;                                   // first cluster spanned
+  const int jlast = min((e0 + 63) / d, K - 1);
+  const int jl = j0 + lane;                                // size column of this lane
+  const bool has_e = e < KD, has_c = jl <= jlast;
+  // wave 0 issues its element loads before the reduction (they do not depend on it)
+  int s_new = 0, len_new = 0;
+  double cin = 0.0, flast = 0.0, glast = 0.0;
+  if (w == 0 && has_e) {
+    if (f.mode == kFinIter) {
+      const float* Cacc = ctl->acc_src == 1 ? f.C_fb : f.C_cand;
+      cin = (double)Cacc[e];
+      if (cap > 0) {
+        flast = f.F_last[e];
+        glast = f.G_last[e];
+      }
+    } else {
+      cin = (double)f.C_in[e];
+    }
+  }
+  unsigned long long ts = 0, tc = 0;
+  {
+    const unsigned long long* ps = f.fxpart + (has_e ? e : 0);
+    const unsigned long long* pc = f.fxpart + KD + (has_c ? jl : 0);
+    for (int p = w; p < P; p += 8 * NW) {                  // up to sixteen loads in flight
+      unsigned long long a[8], c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = p + u * NW < P;
+        a[u] = (has_e && in) ? ps[(int64_t)(p + u * NW) * L] : 0ull;
+        c[u] = (has_c && in) ? pc[(int64_t)(p + u * NW) * L] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        ts += a[u];
+        tc += c[u];
+      }
+    }
+  }
+  rs[w][lane] = ts;
+  rc[w][lane] = tc;
+  __syncthreads();
+  if (w != 0) return;
+  ts = 0;
+  tc = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    ts += rs[i][lane];
+    tc += rc[i][lane];
+  }
+  // lane l holds the size of cluster j0 + l; this workgroup owns (counts as
+  // empty) the clusters whose first element it holds
+  const bool owned = has_c && jl * d >= e0;
+  const unsigned long long em = __ballot(owned && tc == 0);
+  if (lane == 0 && em) atomicAdd(&ctl->empty, (int)__popcll(em));
+  const int je = has_e ? e / d : j0;
+  const int n = __shfl((int)tc, je - j0, 64);
+  const double sum = (double)(long long)ts * ldexp(1.0, -(int)f.xbound[kXBoundSlots]);
+
+  if (f.mode == kFinIter && cap > 0) {
+    // the difference created at iteration t goes to ring slot (t - 1) mod cap
+    const int t = ctl->t;
+    s_new = (t - 1) % cap;
+    len_new = t < cap ? t : cap;
+  }
+  double dfn = 0.0, fv = 0.0;
+  if (has_e) {
+    if (f.mode == kFinG) {
+      f.C_out[e] = (float)(n > 0 ? sum / (double)n : cin);
+      return;
+    }
+    const double gv = n > 0 ? sum / (double)n : cin;
+    fv = gv - cin;
+    if (f.mode == kFinIter && cap > 0) {
+      dfn = fv - flast;
+      f.ring_dF[(int64_t)s_new * KD + e] = dfn;
+      f.ring_dG[(int64_t)s_new * KD + e] = gv - glast;
+    }
+    f.G_last[e] = gv;
+    f.F_last[e] = fv;
+  }
+  if (f.mode != kFinIter || cap == 0) return;
+  // Gram partials of this workgroup's elements: <dF_new, dF_sl> (index sl)
+  // and <dF_sl, F^t> (index cap + sl)
+  for (int q0 = 0; q0 < len_new; q0 += kDotGroup) {
+    double pa[kDotGroup], pb[kDotGroup];
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+      pa[g] = 0.0;
+      pb[g] = 0.0;
+      if (has_e && q0 + g < len_new) {
+        const int sl = (s_new - (q0 + g) + cap) % cap;
+        const double dfs = (q0 + g == 0) ? dfn : f.ring_dF[(int64_t)sl * KD + e];
+        pa[g] = dfn * dfs;
+        pb[g] = dfs * fv;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+      pa[g] = wave_sum(pa[g]);
+      pb[g] = wave_sum(pb[g]);
+    }
+    if (lane < kDotGroup && q0 + lane < len_new) {
+      const int sl = (s_new - (q0 + lane) + cap) % cap;
+      double va = 0.0, vb = 0.0;
+#pragma unroll
+      for (int g = 0; g < kDotGroup; ++g)
+        if (g == lane) { va = pa[g]; vb = pb[g]; }
+      f.dots[(int64_t)bx * 2 * cap + sl] = va;
+      f.dots[(int64_t)bx * 2 * cap + cap + sl] = vb;
+    }
+  }
+}
+
 int finalize_grid(int64_t KD) {
   const int64_t g = (KD + 255) / 256;
   return (int)(g < 128 ? (g > 0 ? g : 1) : 128);
 }
+int finalize_grid_for(int fx, int K, int d) {
+  const int64_t KD = (int64_t)K * d;
+  return fx ? (int)((KD + 63) / 64) : finalize_grid(KD);
+}
+int finalize_grid_cap(int64_t KD) {
+  const int64_t fx = ((KD < kFxMaxL ? KD : kFxMaxL) + 63) / 64;
+  const int64_t g = finalize_grid(KD);
+  return (int)(g > fx ? g : fx);
+}
 
 __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) { finalize_body(f, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kFxThreads) void k_fxfinal(FinalizeArgs f) { fxfinal_body(f, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void k_finalize_batch(BatchRef<FinalizeArgs> t) {
   const int b = batch_find(t.prefix, t.n, blockIdx.x);
   const int b0 = t.prefix[b];
   finalize_body(t.tab[b], blockIdx.x - b0, t.prefix[b + 1] - b0);
 }
+__global__ __launch_bounds__(kFxThreads) void k_fxfinal_batch(BatchRef<FinalizeArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  fxfinal_body(t.tab[b], blockIdx.x - t.prefix[b]);
+}
 
-hipError_t launch_finalize_batch(const FinalizeArgs* tab, const int* prefix, int n, int blocks, hipStream_t s) {
+hipError_t launch_finalize_batch(const FinalizeArgs* tab, const int* prefix, int blocks, const int* fxprefix,
+                                 int fxblocks, int n, hipStream_t s) {
   clear_pending_error();
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize_batch, dim3(blocks), dim3(256), 0, s, BatchRef<FinalizeArgs>{tab, prefix, n});
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_finalize_batch, dim3(blocks), dim3(256), 0, s, BatchRef<FinalizeArgs>{tab, prefix, n});
+  if (fxblocks > 0)
+    hipLaunchKernelGGL(k_fxfinal_batch, dim3(fxblocks), dim3(kFxThreads), 0, s,
+                       BatchRef<FinalizeArgs>{tab, fxprefix, n});
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s) {
   if (f.cap > kMaxM) return hipErrorInvalidValue;
   clear_pending_error();
-  hipLaunchKernelGGL(k_finalize, dim3(finalize_grid((int64_t)f.K * f.d)), dim3(256), 0, s, f);
+  if (f.fx)
+    hipLaunchKernelGGL(k_fxfinal, dim3(finalize_grid_for(1, f.K, f.d)), dim3(kFxThreads), 0, s, f);
+  else
+    hipLaunchKernelGGL(k_finalize, dim3(finalize_grid((int64_t)f.K * f.d)), dim3(256), 0, s, f);
   return hipGetLastError();
 }
 

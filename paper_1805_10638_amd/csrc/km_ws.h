@@ -66,7 +66,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const int64_t grid = N / 64 + 1;   // upper bound of an assignment grid
   const int max_items = update_max_items(N, s.K);
   const int nblk = update_rank_blocks(N, s.K);
-  const int fin_grid = finalize_grid(KD);
+  const int fin_grid = finalize_grid_cap(KD);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += ws_up(bytes); return o; };
   const size_t o_ctl = take(sizeof(Ctl));
