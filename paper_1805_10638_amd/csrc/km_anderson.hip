@@ -294,10 +294,13 @@ hipError_t launch_combine_batch(const CombineArgs* tab, const int* prefix, int n
   return hipGetLastError();
 }
 
-hipError_t launch_combine(const CombineArgs& a, hipStream_t s) {
+hipError_t launch_combine(const CombineArgs& a, hipStream_t s, hipEvent_t ev1) {
   if (a.cap > kMaxM) return hipErrorInvalidValue;
   clear_pending_error();
-  hipLaunchKernelGGL(k_combine, dim3((a.K + 3) / 4), dim3(256), 0, s, a);
+  if (ev1)
+    hipExtLaunchKernelGGL(k_combine, dim3((a.K + 3) / 4), dim3(256), 0, s, nullptr, ev1, 0, a);
+  else
+    hipLaunchKernelGGL(k_combine, dim3((a.K + 3) / 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -23,11 +23,6 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
     HIP_TRY(c, hipStreamSynchronize(c->q), "hipStreamSynchronize");
     HIP_TRY(c, hipFree(c->arena), "hipFree");
     c->arena = nullptr;
-    for (hipGraphExec_t& g : c->gexec) {
-      if (g) (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
-    c->gkey.clear();
   }
   const size_t off = ws_layout(s, nullptr, nullptr);
   void* p = nullptr;
@@ -84,8 +79,7 @@ km_status km_create(int device, void* stream, km_ctx** out) {
             hipHostMalloc((void**)&c->ctl_host, sizeof(Ctl), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&c->done_host, 2 * sizeof(int), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&c->scal_host, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
-            hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&c->poll_ev[1], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreate(&c->poll_ev[0]) == hipSuccess && hipEventCreate(&c->poll_ev[1]) == hipSuccess &&
             hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess;
   if (!ok) {
     km_destroy(c);
@@ -99,7 +93,6 @@ void km_destroy(km_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->q) (void)hipStreamSynchronize(c->q);
-  for (hipGraphExec_t g : c->gexec) if (g) (void)hipGraphExecDestroy(g);
   if (c->arena) (void)hipFree(c->arena);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
   if (c->done_host) (void)hipHostFree(c->done_host);
@@ -201,21 +194,19 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   // bound of |x| for the fixed-point sums: part of preparing X, outside the
   // phase times (a solve computes it once)
   HIP_TRY(c, launch_xbound(u, st_), "bound of |x|");
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[0], st_), "hipEventRecord");
-  HIP_TRY(c, launch_assign(a, kRolePlain, st_), "assignment");
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[0], st_), "hipEventRecord");
+  // with timing on, the events take the times of the kernels' own dispatches
+  HIP_TRY(c, launch_assign(a, kRolePlain, st_, c->timing ? c->ta[0] : nullptr, c->timing ? c->tb[0] : nullptr),
+          "assignment");
   const int grid = assign_grid(a);
   HIP_TRY(c, launch_reduce_energy(c->w.e_part, grid, c->w.e_out, st_), "energy");
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ta[1], st_), "hipEventRecord");
-  HIP_TRY(c, launch_update_sums(u, st_), "update");
+  HIP_TRY(c, launch_update_sums(u, st_, c->timing ? c->ta[1] : nullptr), "update");
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = 0; f.partial = c->w.partial; f.item_start = c->w.item_start;
   f.counts = c->w.counts; f.C_in = C; f.C_out = C_out; f.ctl = c->w.ctl; f.mode = kFinG;
   f.fx = u.fx; f.fxpart = c->w.fxpart; f.xbound = c->w.xbound; f.N = N;
   f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
   f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
-  HIP_TRY(c, launch_finalize(f, st_), "finalize");
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->tb[1], st_), "hipEventRecord");
+  HIP_TRY(c, launch_finalize(f, st_, c->timing ? c->tb[1] : nullptr), "finalize");
   HIP_TRY(c, hipMemcpyAsync(c->scal_host, c->w.e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
   HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
   HIP_TRY(c, hipStreamSynchronize(st_), "hipStreamSynchronize");
@@ -349,11 +340,10 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   ci.gated = 1;
   ci.dots = c->w.dots; ci.n_dots = finalize_grid_for(u.fx, K, d); ci.gram = c->w.gram; ci.trace_rec = opt.trace_rec;
 
-  // The iteration is replayed from a graph.  With timing on, the candidate
-  // assignment is launched directly between two HIP events and the graph
-  // holds the rest; with timing off it is the graph's first node, so one
-  // iteration is one graph launch (no graph-to-stream transition between
-  // iterations).
+  // Each iteration is launched directly on the stream (a graph launch left
+  // the device idle for about 13 us at every iteration boundary; kernels
+  // launched back to back start without a gap while the host stays ahead).
+  // The host keeps two iterations in flight.
   CtlArgs k1{};
   k1.ctl = c->w.ctl; k1.e_part = c->w.e_part; k1.n_part = grid; k1.stage = 1;
   k1.tr.trace_C = opt.trace_C; k1.tr.trace_rec = opt.trace_rec; k1.tr.C_cand = c->w.C_cand;
@@ -362,45 +352,24 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   k2.e_part = c->w.e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
 
   // The combine kernel, last of the iteration, writes the done flag into
-  // pinned slot p (no copy node).
+  // pinned slot p; its dispatch's end event tells the host the iteration is
+  // complete (no separate event record, which would idle the device).
   int* done_dev = nullptr;
   HIP_TRY(c, hipHostGetDevicePointer((void**)&done_dev, c->done_host, 0), "hipHostGetDevicePointer");
-  const bool cand_in_graph = !c->timing;
-  auto enqueue_rest = [&](int p) -> km_status {
+  auto enqueue_iteration = [&](int p) -> km_status {
     CombineArgs cp = ci;
     cp.done_out = done_dev + p;
-    if (cand_in_graph) HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
+    // with timing on, ta/tb take the candidate assignment's own start and end
+    HIP_TRY(c, launch_assign(ac, kRoleCand, q, c->timing ? c->ta[p] : nullptr, c->timing ? c->tb[p] : nullptr),
+            "assignment");
     HIP_TRY(c, launch_controller(k1, q), "controller");
     HIP_TRY(c, launch_assign(af, kRoleFallback, q), "assignment");
     HIP_TRY(c, launch_controller(k2, q), "controller");
     HIP_TRY(c, launch_update_sums(u, q), "update");
     HIP_TRY(c, launch_finalize(fi, q), "finalize");
-    HIP_TRY(c, launch_combine(cp, q), "combine");
+    HIP_TRY(c, launch_combine(cp, q, c->poll_ev[p]), "combine");
     return KM_OK;
   };
-
-  char keybuf[512];
-  snprintf(keybuf, sizeof keybuf, "%p|%d|%lld|%d|%d|%d|%d|%d|%p|%p|%p|%d", X, (int)xt, (long long)N, d, K,
-           cap, (int)gbf, a.shape, (void*)opt.trace_C, (void*)opt.trace_rec, c->arena, (int)cand_in_graph);
-  if (c->gkey != keybuf) {
-    for (hipGraphExec_t& g : c->gexec) {
-      if (g) (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
-    c->gkey.clear();
-    for (int p = 0; p < 2; ++p) {
-      hipGraph_t graph = nullptr;
-      HIP_TRY(c, hipStreamBeginCapture(q, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
-      km_status es = enqueue_rest(p);
-      hipError_t ee = hipStreamEndCapture(q, &graph);
-      if (es != KM_OK) return es;
-      if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
-      ee = hipGraphInstantiate(&c->gexec[p], graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ee != hipSuccess) return hip_fail(c, ee, "hipGraphInstantiate");
-    }
-    c->gkey = keybuf;
-  }
 
   std::vector<float> it_ms;
   it_ms.reserve(64);
@@ -409,19 +378,11 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   while (launched < opt.max_iter && !finished) {
     const int it = launched;
     const int p = it & 1;
-    if (!cand_in_graph) {
-      HIP_TRY(c, hipEventRecord(c->ta[p], q), "hipEventRecord");
-      HIP_TRY(c, launch_assign(ac, kRoleCand, q), "assignment");
-      HIP_TRY(c, hipEventRecord(c->tb[p], q), "hipEventRecord");
-    }
-    HIP_TRY(c, hipGraphLaunch(c->gexec[p], q), "hipGraphLaunch");
-    // Each event record costs the device a few microseconds between kernels,
-    // so with timing on the start event of iteration it also marks the end of
-    // iteration it - 1; with timing off one event per iteration does.
-    if (cand_in_graph) HIP_TRY(c, hipEventRecord(c->poll_ev[p], q), "hipEventRecord");
+    const km_status es = enqueue_iteration(p);
+    if (es != KM_OK) return es;
     if (it >= 1) {
       const int pp = (it - 1) & 1;
-      HIP_TRY(c, hipEventSynchronize(cand_in_graph ? c->poll_ev[pp] : c->ta[p]), "hipEventSynchronize");
+      HIP_TRY(c, hipEventSynchronize(c->poll_ev[pp]), "hipEventSynchronize");
       if (c->timing) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ta[pp], c->tb[pp]) != hipSuccess) {

@@ -81,7 +81,7 @@ int64_t assign_resident(const KernelPick& p, int64_t N, double frac) {
   return groups < g ? groups : g;
 }
 
-hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s) {
+hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.N <= 0 || a.K <= 0 || a.d <= 0 || a.d > kMaxD || a.K > kMaxK || !a.flags) return hipErrorInvalidValue;
   const KernelPick p = assign_pick(a);
   if (!p.fn) return hipErrorInvalidValue;
@@ -93,6 +93,7 @@ hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s) {
   hipError_t e = allow_lds(p);
   if (e != hipSuccess) return e;
   clear_pending_error();
+  if (ev0 || ev1) return hipExtLaunchKernel(p.fn, dim3(grid), dim3(p.threads), params, p.lds, s, ev0, ev1, 0);
   return hipLaunchKernel(p.fn, dim3(grid), dim3(p.threads), params, p.lds, s);
 }
 

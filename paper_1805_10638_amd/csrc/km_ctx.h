@@ -37,8 +37,6 @@ struct km_ctx {
   int8_t tile_shape[2][2][10][9] = {};
 
   // per-iteration graphs (two, so that one can be inspected while the other runs)
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  std::string gkey;
 
   Ws w;                         // workspace carve-up
 };

@@ -1,6 +1,7 @@
 // Host-side launch interface between the C ABI layer and the HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,7 +30,10 @@ struct AssignArgs {
   int shape;              // tile shape id (0 = default)
 };
 int assign_grid(const AssignArgs& a);   // workgroups of one launch (persistent grid)
-hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s);
+// ev0 / ev1 (nullable): events that take the start and end time of this
+// launch's own dispatch (no separate event record on the stream).
+hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 struct KernelPick;
 KernelPick assign_pick(const AssignArgs& a);
 // resident workgroups of kernel p on the device x frac, capped at N's row groups
@@ -77,7 +81,8 @@ struct UpdateArgs {
 int update_max_items(int64_t N, int K);
 // blockcount entries a workspace for (N, K) must hold: enough for any K' <= K
 size_t update_blockcount_ints(int64_t N, int K);
-hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s);
+// ev0 (nullable): takes the start time of the update's first kernel
+hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s, hipEvent_t ev0 = nullptr);
 // Bound of |x| over X and the scale exponent e of the fixed-point sums
 // (u.fx only): once per X, before the first update with it.
 hipError_t launch_xbound(const UpdateArgs& u, hipStream_t s);
@@ -129,7 +134,8 @@ int finalize_grid(int64_t KD);                // counting-sort path
 int finalize_grid_for(int fx, int K, int d);  // either path
 // rows of Gram partials a workspace for K*d must hold (either path)
 int finalize_grid_cap(int64_t KD);
-hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s);
+// ev1 (nullable): takes the end time of the finalisation kernel
+hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s, hipEvent_t ev1 = nullptr);
 // Batched: tab one FinalizeArgs per instance; prefix/blocks for the
 // counting-sort instances (256-thread workgroups) and fxprefix/fxblocks for
 // the fixed-point ones (kFxThreads); an instance has 0 workgroups in the
@@ -164,7 +170,8 @@ struct CombineArgs {
   float* C_fb; float* nc_fb; uint16_t* Cb_fb; float* delta_fb;
   int* done_out;          // nullable: pinned host slot that receives ctl->done (solver iterations)
 };
-hipError_t launch_combine(const CombineArgs& a, hipStream_t s);
+// ev1 (nullable): takes the end time of the combine's dispatch
+hipError_t launch_combine(const CombineArgs& a, hipStream_t s, hipEvent_t ev1 = nullptr);
 int combine_grid(int K);
 hipError_t launch_combine_batch(const CombineArgs* tab, const int* prefix, int n, int blocks, hipStream_t s);
 

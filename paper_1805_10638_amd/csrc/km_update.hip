@@ -611,19 +611,25 @@ hipError_t launch_xbound_batch(const UpdateBatch& ub, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s) {
+hipError_t launch_update_sums(const UpdateArgs& u, hipStream_t s, hipEvent_t ev0) {
   if (u.K > kMaxK || u.d > kMaxD) return hipErrorInvalidValue;
   if (u.fx) {
     if (!fx_ok(u.K, u.d)) return hipErrorInvalidValue;
     const hipError_t a = fx_lds_attr();
     if (a != hipSuccess) return a;
     clear_pending_error();
-    hipLaunchKernelGGL(k_fxsum, dim3(fx_blocks(u.N)), dim3(kFxThreads), kFxLds, s, u);
+    if (ev0)
+      hipExtLaunchKernelGGL(k_fxsum, dim3(fx_blocks(u.N)), dim3(kFxThreads), kFxLds, s, ev0, nullptr, 0, u);
+    else
+      hipLaunchKernelGGL(k_fxsum, dim3(fx_blocks(u.N)), dim3(kFxThreads), kFxLds, s, u);
     return hipGetLastError();   // the finalisation adds the partials
   }
   const int nblk = update_rank_blocks(u.N, u.K);
   clear_pending_error();
-  hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(256), 0, s, u);
+  if (ev0)
+    hipExtLaunchKernelGGL(k_rank, dim3(nblk), dim3(256), 0, s, ev0, nullptr, 0, u);
+  else
+    hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(256), 0, s, u);
   hipLaunchKernelGGL(k_scan, dim3(u.K), dim3(256), 0, s, u);
   hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, u);
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)((u.N + 255) / 256)), dim3(256), 0, s, u);
@@ -937,13 +943,18 @@ hipError_t launch_finalize_batch(const FinalizeArgs* tab, const int* prefix, int
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s) {
+hipError_t launch_finalize(const FinalizeArgs& f, hipStream_t s, hipEvent_t ev1) {
   if (f.cap > kMaxM) return hipErrorInvalidValue;
   clear_pending_error();
-  if (f.fx)
-    hipLaunchKernelGGL(k_fxfinal, dim3(finalize_grid_for(1, f.K, f.d)), dim3(kFxThreads), 0, s, f);
-  else
-    hipLaunchKernelGGL(k_finalize, dim3(finalize_grid((int64_t)f.K * f.d)), dim3(256), 0, s, f);
+  const dim3 grid(f.fx ? finalize_grid_for(1, f.K, f.d) : finalize_grid((int64_t)f.K * f.d));
+  const dim3 block(f.fx ? kFxThreads : 256);
+  if (ev1) {
+    if (f.fx) hipExtLaunchKernelGGL(k_fxfinal, grid, block, 0, s, nullptr, ev1, 0, f);
+    else hipExtLaunchKernelGGL(k_finalize, grid, block, 0, s, nullptr, ev1, 0, f);
+  } else {
+    if (f.fx) hipLaunchKernelGGL(k_fxfinal, grid, block, 0, s, f);
+    else hipLaunchKernelGGL(k_finalize, grid, block, 0, s, f);
+  }
   return hipGetLastError();
 }
 
