@@ -352,8 +352,11 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   k2.e_part = c->w.e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
 
   // The combine kernel, last of the iteration, writes the done flag into
-  // pinned slot p; its dispatch's end event tells the host the iteration is
-  // complete (no separate event record, which would idle the device).
+  // pinned slot p.  An event taken by a dispatch still idles the device for a
+  // few microseconds, so one event per iteration tells the host that the
+  // previous iteration is complete: with timing on, the start event of the
+  // candidate assignment (which also times it); with timing off, the end
+  // event of the combine.
   int* done_dev = nullptr;
   HIP_TRY(c, hipHostGetDevicePointer((void**)&done_dev, c->done_host, 0), "hipHostGetDevicePointer");
   auto enqueue_iteration = [&](int p) -> km_status {
@@ -367,7 +370,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     HIP_TRY(c, launch_controller(k2, q), "controller");
     HIP_TRY(c, launch_update_sums(u, q), "update");
     HIP_TRY(c, launch_finalize(fi, q), "finalize");
-    HIP_TRY(c, launch_combine(cp, q, c->poll_ev[p]), "combine");
+    HIP_TRY(c, launch_combine(cp, q, c->timing ? nullptr : c->poll_ev[p]), "combine");
     return KM_OK;
   };
 
@@ -382,7 +385,8 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     if (es != KM_OK) return es;
     if (it >= 1) {
       const int pp = (it - 1) & 1;
-      HIP_TRY(c, hipEventSynchronize(c->poll_ev[pp]), "hipEventSynchronize");
+      // iteration it - 1 is complete once iteration it has started
+      HIP_TRY(c, hipEventSynchronize(c->timing ? c->ta[p] : c->poll_ev[pp]), "hipEventSynchronize");
       if (c->timing) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ta[pp], c->tb[pp]) != hipSuccess) {
