@@ -325,7 +325,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   // counters of the first candidate pass start from zero
   HIP_TRY(c, hipMemcpyAsync(c->w.ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, q), "copy ctl");
 
-  // ---- per-iteration launch sequence, captured once into two graphs ----
+  // ---- per-iteration launch sequence ----
   const int grid = assign_grid(a);
   if (grid <= 0) return fail(c, KM_EUNSUPPORTED, "no assignment kernel for this shape");
   AssignArgs ac = a;

@@ -27,16 +27,14 @@ struct km_ctx {
   Ctl* ctl_host = nullptr;      // pinned host mirror
   int* done_host = nullptr;     // pinned poll slots
   double* scal_host = nullptr;  // pinned scalars
-  hipStream_t q = nullptr;      // internal stream (graph capture needs a non-null stream)
+  hipStream_t q = nullptr;      // internal stream
   hipEvent_t enter = nullptr;   // orders q after the caller's stream
-  hipEvent_t poll_ev[2] = {nullptr, nullptr};
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};   // end of an iteration (timing off)
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  hipEvent_t ta[2] = {nullptr, nullptr}, tb[2] = {nullptr, nullptr};  // around assignment
+  hipEvent_t ta[2] = {nullptr, nullptr}, tb[2] = {nullptr, nullptr};  // start / end of an assignment dispatch
 
   // assignment tile shape per (precision, X type, padded width, K bucket)
   int8_t tile_shape[2][2][10][9] = {};
-
-  // per-iteration graphs (two, so that one can be inspected while the other runs)
 
   Ws w;                         // workspace carve-up
 };
