@@ -1,6 +1,15 @@
 // Update step (Sec. 1, Eq. (4)): c_j = mean of the samples labelled j.
 //
-// Deterministic and free of floating-point atomics:
+// Two paths, both deterministic and free of floating-point atomics; which
+// one runs depends only on (K, d).
+//
+// Fixed-point sums, when K * (d | 1) + K int64 accumulators fit in LDS
+// (fx_ok), described at k_fxsum below:
+//   k_xbound, k_xexp  once per X: bound of |x| and the scale exponent;
+//   k_fxsum           one pass over X into per-workgroup int64 partials;
+//   k_fxfinal         adds the partials and does the work of k_finalize.
+//
+// Counting sort otherwise:
 //   1. k_rank     stable within-block ranks of every label (wave match by
 //                 ballots, per-wave LDS counters) and each block's histogram,
 //                 stored label-major: blockcount[j][b];
@@ -326,12 +335,13 @@ size_t update_blockcount_ints(int64_t N, int K) {
 // ---------------------------------------------------------------------------
 // Fixed-point sums (fx_ok(K, d)): X is read once, in row order
 // ---------------------------------------------------------------------------
-// Each workgroup adds the rows of one contiguous range into K*d + K int64
+// Each workgroup of k_fxsum adds its share of the rows into int64
 // accumulators in LDS (sums of the scaled, rounded coordinates, then the
-// cluster sizes); a second kernel adds the per-workgroup partials and converts
-// the sums back.  Integer addition is associative, so the order of the LDS
-// atomics does not change the result: runs are bitwise reproducible, and the
-// sums do not depend on how the rows are split between workgroups.
+// cluster sizes) and writes them as partials; the finalisation (k_fxfinal)
+// adds the per-workgroup partials and converts the sums back.  Integer
+// addition is associative, so the order of the LDS atomics does not change
+// the result: runs are bitwise reproducible, and the sums do not depend on
+// how the rows are split between workgroups.
 //
 // Scale: 2^e with n * max|x| * 2^e < 2^62, so no partial sum of at most n
 // scaled values overflows, and max|x| * 2^e < 2^51 (below).  e is the largest
