@@ -80,9 +80,10 @@ const char *km_last_error(const km_ctx *ctx);
 /* Library version as 10000*major + 100*minor + patch. */
 int km_version(void);
 
-/* Record HIP events around every assignment-kernel launch of kmeans_solve
- * (1) or not (0, default).  Results appear in km_solve_stats.assign_ms, and
- * for kmeans_g in km_g_stats.assign_ms / update_ms. */
+/* Time every candidate-assignment launch of kmeans_solve (1) or not (0,
+ * default), with HIP start and end events taken by the kernel's own dispatch.
+ * Results appear in km_solve_stats.assign_ms, and for kmeans_g in
+ * km_g_stats.assign_ms / update_ms. */
 km_status km_set_timing(km_ctx *ctx, int enable);
 
 /* Tile shape of the assignment kernel for later calls on this context whose
