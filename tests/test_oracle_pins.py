@@ -198,6 +198,36 @@ def test_m0_is_lloyd(tol):
     assert res.accepted == 0 and res.rejected == 0
 
 
+# The classical fixed-m variant (Sec. 2.2 compares it with dynamic m): with m
+# held at 0 no difference ever enters the least squares, so the run is Lloyd's
+# algorithm whatever m_max is; with m held at 2 the dynamic rule's changes of
+# m must not happen.
+
+@pytest.mark.parametrize("tol", [0.0, 1e-4])
+def test_fixed_m_zero_is_lloyd(tol):
+    from paper_1805_10638_amd import synth
+    X, _ = synth.plain_small(rep=0, n=3000)
+    C0 = synth.init_centroids(X, 10, 1)   # slow Lloyd run: the energy ratio often exceeds eps2
+    res = ko.solve(X, C0, m_max=10, m_init=0, fixed_m=True, tol=tol)
+    C, P, E, t = _lloyd_loop(X, C0, tol, 500)
+    assert res.iters == t
+    assert np.array_equal(res.C, C)
+    assert np.array_equal(res.rho, P)
+    assert res.E == E
+    assert res.accepted == 0 and res.rejected == 0 and res.m_final == 0
+
+
+def test_fixed_m_keeps_m():
+    from paper_1805_10638_amd import synth
+    X, _ = synth.plain_small(rep=2, n=3000)
+    C0 = synth.init_centroids(X, 10, 3)
+    dyn = ko.solve(X, C0, m_max=10, m_init=2, tol=0.0)
+    assert {r["m"] for r in dyn.trace if "m" in r} != {2}    # the dynamic rule moves m here
+    fix = ko.solve(X, C0, m_max=10, m_init=2, fixed_m=True, tol=0.0)
+    assert {r["m"] for r in fix.trace if "m" in r} == {2}
+    assert all(r["mt"] == min(2, r["t"]) for r in fix.trace if "mt" in r)
+
+
 # ---------------------------------------------------------------------------
 # P6 exact convergence returns a fixed point of G (Eq. 6)
 # ---------------------------------------------------------------------------
@@ -424,3 +454,32 @@ def test_golden_tiny_1d():
     lit = ko.solve(X, C0, m_max=g["m_max"], tol=0.0, literal_return=True)
     np.testing.assert_allclose(lit.C.ravel(), [_frac(v) for v in exp["literal_C"]], rtol=1e-9)
     assert lit.iters == exp["iters"] and lit.rejected == 0
+
+
+def test_golden_tol_reject_1d():
+    """Stopping rule on the accepted energy after a rejection (reading R3):
+    tests/golden/tol_reject_1d.json, derived by hand in exact rationals."""
+    with open(os.path.join(GOLDEN, "tol_reject_1d.json")) as f:
+        g = json.load(f)
+    X = np.array(g["X"], dtype=np.float64)
+    C0 = np.array(g["C0"], dtype=np.float64)
+    exp = g["expected"]
+    res = ko.solve(X, C0, m_max=g["m_max"], tol=g["tol"])
+    assert res.status == ko.STATUS_CONVERGED
+    assert res.iters == exp["iters"]
+    assert (res.accepted, res.rejected, res.assign_passes) == (exp["accepted"], exp["rejected"],
+                                                               exp["assign_passes"])
+    assert res.m_final == exp["m_final"]
+    assert res.rho.tolist() == exp["rho"]
+    assert [r["decision"] for r in res.trace] == exp["decisions"]
+    assert [r["E_cand"] for r in res.trace] == pytest.approx([_frac(v) for v in exp["E_cand"]], rel=1e-11)
+    assert res.trace[1]["E_fb"] == _frac(exp["E_fb_t2"])
+    assert [r["theta"][0] for r in res.trace[:2]] == pytest.approx([_frac(v) for v in exp["theta"]], rel=1e-9)
+    assert res.trace[-1]["stop"] == "tol"
+    np.testing.assert_allclose(res.C.ravel(), [_frac(v) for v in exp["C"]], rtol=1e-12)
+    assert res.E == pytest.approx(_frac(exp["E"]), rel=1e-11)
+    z = exp["tol0"]
+    r0 = ko.solve(X, C0, m_max=g["m_max"], tol=0.0)
+    assert r0.iters == z["iters"] and r0.rho.tolist() == z["rho"]
+    np.testing.assert_allclose(r0.C.ravel(), [_frac(v) for v in z["C"]], rtol=1e-15)
+    assert r0.E == _frac(z["E"])
