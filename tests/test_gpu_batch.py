@@ -9,7 +9,7 @@ import pytest
 from oracle import kmeans_oracle as ko
 from paper_1805_10638_amd import synth
 
-from helpers import dev, x_tensor, x_values
+from helpers import centroid_errors, dev, x_tensor, x_values
 
 pytestmark = pytest.mark.gpu
 
@@ -133,6 +133,57 @@ def test_engine_staggered_admission():
     for i, (X, C0) in enumerate(ts):
         _same(_solo(km, X, C0, m_max=10, tol=1e-6), got[i])
         assert got[i][2].latency_ms > 0
+
+
+def _oracle_same(X, C0, C, rho, res, prec):
+    """End-to-end parity of one engine result with the FP64 oracle from the
+    same C^0: iterations and decisions equal, energy to 1e-6, centroids to
+    1e-5, labels equal except oracle near ties."""
+    X64 = x_values(X)
+    o = ko.solve(X64, C0.astype(np.float64), m_max=10, tol=1e-6)
+    assert (res.iters, res.accepted, res.rejected) == (o.iters, o.accepted, o.rejected), prec
+    assert res.E == pytest.approx(o.E, rel=1e-6)
+    assert centroid_errors(C.cpu().numpy(), o.C, X64).max() <= 1e-5
+    a = ko.assign(X64, C.cpu().numpy().astype(np.float64))
+    assert np.all((a.rho == rho.cpu().numpy()) | a.near_tie)
+
+
+def test_engine_served_against_oracle():
+    """Continuous batching compared with the oracle itself (not only with the
+    solo GPU solve): jobs admitted while others run, on both update paths
+    (K*(d|1) + K above and below 10240) and both GEMM precisions."""
+    km = _lib()
+    spec = [(3000, 16, 30, False), (4000, 64, 200, False), (2500, 64, 170, True), (5000, 3, 12, False)]
+    probs = []
+    for i, (n, d, k, bf) in enumerate(spec):
+        x, _ = synth.instance(n, d, k, seed=700 + i)
+        if bf:
+            x = synth.to_bf16_bits(x)
+        probs.append((x, synth.init_centroids(x, k, 700 + i), "bf16" if bf else "f32"))
+    eng = km.Engine(m_max=10, tol=1e-6, graphs=True)
+    tickets, got = {}, {}
+
+    def drain(steps):
+        for _ in range(steps):
+            if len(got) == len(probs):
+                return
+            eng.step()
+            for t, C, rho, res in eng.poll():
+                got[tickets[t]] = (C, rho, res)
+
+    for i in (0, 1):
+        x, c0, prec = probs[i]
+        tickets[eng.submit(x_tensor(x), dev(c0), prec=prec)] = i
+    drain(3)
+    for i in (2, 3):
+        x, c0, prec = probs[i]
+        tickets[eng.submit(x_tensor(x), dev(c0), prec=prec)] = i
+        drain(2)
+    drain(5000)
+    eng.close()
+    assert len(got) == len(probs)
+    for i, (x, c0, prec) in enumerate(probs):
+        _oracle_same(x, c0, *got[i], prec)
 
 
 def test_engine_budget_admission():

@@ -48,6 +48,8 @@ def lockstep(X, C0, m_max, tol, max_iter=500, **kw):
         oracle_kw["fixed_m"] = True
     if "m_init" in kw:
         oracle_kw["m_init"] = kw["m_init"]
+    if kw.get("literal_return"):
+        oracle_kw["literal_return"] = True
     res = ko.solve(X64, C0.astype(np.float64), m_max=m_max, tol=tol, max_iter=max_iter,
                    replay=lambda t: Ctr[t] if t <= iters else None,
                    stored=lambda G: G.astype(np.float32), **oracle_kw)
@@ -100,10 +102,55 @@ def test_lockstep_mixtures(N, d, K, seed):
     lockstep(X, C0, 10, 1e-6)
 
 
-def test_lockstep_fixed_m_and_literal():
+def test_lockstep_fixed_m():
     X, _ = synth.plain_small(rep=5)
     C0 = synth.init_centroids(X, 10, 5)
-    lockstep(X, C0, 5, 0.0, fixed_m=True, m_init=5)
+    *_, st, res, _ = lockstep(X, C0, 5, 0.0, fixed_m=True, m_init=5)
+    assert {r["m"] for r in res.trace if "m" in r} == {5}
+
+
+@pytest.mark.parametrize("rep", [1, 6])
+def test_lockstep_literal_return(rep):
+    """Algorithm 1's printed early return (KM_FLAG_LITERAL_RETURN): on these
+    inputs the run stops at an accelerated iterate whose assignment repeats
+    the previous one, earlier than the default reading would."""
+    X, _ = synth.plain_small(rep=rep)
+    C0 = synth.init_centroids(X, 10, rep)
+    C, rho, E, iters, st, res, _ = lockstep(X, C0, 10, 0.0, literal_return=True)
+    last = res.trace[-1]
+    assert last["decision"] == "converged" and not last["cand_is_lloyd"]
+    default = ko.solve(x_values(X), C0.astype(np.float64), m_max=10, tol=0.0)
+    assert iters < default.iters
+    assert E == pytest.approx(res.E, rel=1e-6)
+    assert centroid_errors(C, res.C, x_values(X)).max() <= 1e-5
+
+
+def _fx_path(K, d):
+    """Whether the update takes the fixed-point sums (K*(d|1) + K <= 10240)."""
+    return K * (d | 1) + K <= 10240
+
+
+# Shapes whose Gram partial rows exceed 64 (the combine's reduction then
+# takes more than one pass per lane), on both update paths, and the
+# bfloat16 GEMM on the counting-sort path.
+@pytest.mark.parametrize("N,d,K,xt,seed", [
+    (20000, 64, 300, "f32", 0),    # counting sort + float64 segmented sums; 75 Gram partial rows
+    (20000, 32, 256, "f32", 1),    # fixed-point sums; 128 Gram partial rows (the benchmark's d and K)
+    (20000, 64, 300, "bf16", 2),   # bfloat16 rows and GEMM on the counting-sort path
+])
+def test_lockstep_production_shapes(N, d, K, xt, seed):
+    X, _ = synth.plain_large(rep=seed, n=N, d=d, k=K, cfg=64)
+    if xt == "bf16":
+        X = synth.to_bf16_bits(X)
+    C0 = synth.init_centroids(X, K, seed)
+    rows = (K * d + 255) // 256 if not _fx_path(K, d) else (K * d + 63) // 64
+    assert rows > 64
+    C, rho, E, iters, st, res, _ = lockstep(X, C0, 10, 1e-6, prec=xt)
+    assert res.rejected + res.accepted > 0
+    assert st.accepted == res.accepted and st.rejected == res.rejected
+    assert E == pytest.approx(res.E, rel=1e-6)
+    assert centroid_errors(C, res.C, x_values(X)).max() <= 1e-5
+    _labels_match(rho, x_values(X), C.astype(np.float64))
 
 
 @pytest.mark.parametrize("seed", [0, 3])
