@@ -30,7 +30,7 @@ WORKLOAD = dict(N=1_000_000, d=32, K=256, m_max=10, tol=1e-6, max_iter=500)
 # WRITE_SIZE, each scaled by its reading for a plain copy of known size
 # (profiles/assign_f32_N1M_d32_K256_traffic.md).  Set to None when the kernel
 # changes until it is measured again.
-TRAFFIC_BYTES_PER_LAUNCH = 136240854
+TRAFFIC_BYTES_PER_LAUNCH = 137109169
 
 
 def parse():
@@ -41,14 +41,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time budget of the oracle baseline sample")
-    ap.add_argument("--workload", choices=["plain", "precision", "batched", "served", "studies", "update"],
+    ap.add_argument("--workload", choices=["plain", "small", "precision", "batched", "served", "studies",
+                                           "update"],
                     default="plain",
-                    help="plain: N=1e6 d=32 K=256 float32 (default line); precision: "
+                    help="plain: N=1e6 d=32 K=256 float32 (default line); small: N=1e4 d=2 K=10 over "
+                         "100 seeds, Lloyd and Anderson, p50/p99 latency beside the oracle on the host; precision: "
                          "N=4e6 d=128 K=1024 bfloat16-stored X, float32 vs bfloat16 GEMM; batched: "
                          "512 uneven instances in one engine vs one at a time; served: Poisson arrivals "
                          "(200 jobs/s) through the continuous-batching engine vs a FIFO loop; studies: fixed vs "
                          "dynamic m and Lloyd vs Anderson on synthetic mixtures; update: the update step "
                          "against the HBM roofline at N=1e7 d=16 K=256 and N=1e6 d=32 K=256")
+    ap.add_argument("--seeds", type=int, default=100, help="small: number of seeds")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of instances")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
@@ -110,6 +113,9 @@ def main():
         return
     import paper_1805_10638_amd as km
     from paper_1805_10638_amd import synth
+    if args.workload == "small":
+        small_workload(args, km, synth, torch)
+        return
     if args.workload == "precision":
         precision_workload(args, km, synth, torch)
         return
@@ -219,6 +225,76 @@ def main():
 
 
 BF16_MFMA_PEAK_TFLOPS = 2516.6   # MI355X dense bf16 matrix peak
+
+
+def _pct(v, p):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, int(round(p / 100.0 * (len(v) - 1)))))] if v else None
+
+
+def small_workload(args, km, synth, torch):
+    """Many small solves: N=10,000, d=2, K=10 (the plain small mixture), one
+    instance per seed s (data rep s, init seed s), Lloyd (m_max=0) and
+    Anderson (m_max=10, m_init=2), tol=1e-6, max_iter=500.  Each GPU solve is
+    timed on the host around the call (X and C0 already on the device), so the
+    latency includes the binding and the final copies.  Beside it the float64
+    oracle solves the same inputs on the host CPU, each timed the same way;
+    every GPU result is compared with the oracle's (iterations, accepted
+    count, energy to 1e-6 relative)."""
+    from oracle import kmeans_oracle as ko
+    seeds = list(range(args.seeds))
+    K = 10
+    host = [synth.plain_small(rep=s)[0] for s in seeds]
+    inits = [synth.init_centroids(x, K, s) for s, x in zip(seeds, host)]
+    Xd = [torch.from_numpy(x).to("cuda") for x in host]
+    Cd = [torch.from_numpy(c).to("cuda") for c in inits]
+    ctx = km.Context(0)
+    for j in range(3):                                   # warm-up (code objects, workspace)
+        km.kmeans_solve(Xd[j], Cd[j], m_max=10, tol=1e-6, ctx=ctx)
+    torch.cuda.synchronize()
+    res = {}
+    for mode, m_max in (("lloyd", 0), ("aa", 10)):
+        lat, its, Es, acc = [], [], [], []
+        t0 = time.perf_counter()
+        for j in range(len(seeds)):
+            ts = time.perf_counter()
+            _, _, E, it, st = km.kmeans_solve(Xd[j], Cd[j], m_max=m_max, tol=1e-6, ctx=ctx)
+            lat.append((time.perf_counter() - ts) * 1e3)
+            its.append(it)
+            Es.append(E)
+            acc.append(st.accepted)
+        wall = time.perf_counter() - t0
+        clat, cits, mism = [], [], 0
+        ct0 = time.perf_counter()
+        for j in range(len(seeds)):
+            ts = time.perf_counter()
+            r = ko.solve(host[j].astype(np.float64), inits[j].astype(np.float64), m_max=m_max, tol=1e-6)
+            clat.append((time.perf_counter() - ts) * 1e3)
+            cits.append(r.iters)
+            if r.iters != its[j] or r.accepted != acc[j] or abs(r.E - Es[j]) > 1e-6 * abs(r.E):
+                mism += 1
+        cwall = time.perf_counter() - ct0
+        res[mode] = {"solves_per_s": len(seeds) / wall, "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                     "iters_mean": statistics.mean(its),
+                     "oracle_cpu": {"solves_per_s": len(seeds) / cwall, "p50_ms": _pct(clat, 50),
+                                    "p99_ms": _pct(clat, 99), "iters_mean": statistics.mean(cits),
+                                    "cores": 1},
+                     "seeds_differing_from_oracle": mism}
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        threads = os.cpu_count()
+    print(json.dumps({
+        "metric": "small solves: solves/s and p50/p99 latency, Lloyd and Anderson, GPU vs float64 oracle on CPU",
+        "value": res["aa"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": f"gaussian-mixture N=10000 d=2 K=10 (10 unit-variance components, centres "
+                               f"U[-10,10]^2), {len(seeds)} seeds, random-sample init, tol=1e-6 max_iter=500; "
+                               "Lloyd = m_max 0, Anderson = m_max 10 m_init 2",
+                   "N": 10000, "d": 2, "K": K, "seeds": len(seeds)},
+        "results": res,
+        "oracle_note": f"single-threaded NumPy float64 (direct differences, no BLAS) on a host with "
+                       f"{threads} visible cores",
+    }), flush=True)
 
 
 def update_workload(args, km, synth, torch):

@@ -41,6 +41,8 @@
 
 #pragma once
 
+#include <type_traits>
+
 #include "km_launch.h"
 
 namespace km {
@@ -614,16 +616,18 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
   };
 
-  int nb = 0;   // row-group boundaries passed (selects the wc buffer)
-  for (int64_t grp = bx; grp < groups; grp += gx) {
+  // One unit of work of this wave: U 16-sample blocks from row row0 (U = SB
+  // inside a row group; U = 1 for the single blocks that end a balanced
+  // range).
+  auto unit = [&](auto ut, const int64_t row0) {
+    constexpr int U = decltype(ut)::value;
     // Sample rows of this wave, kept in registers.
-    const int64_t row0 = grp * group_rows + (int64_t)wave * (16 * SB);
-    float xv[SB][KF ? KS : 1];
-    i16x8 xbv[SB][NB];
-    i16x8 xlv[SB][XLO ? NB : 1];
-    float xres[SB];  // ||x - hi - lo||^2 lane partial (XLO)
+    float xv[U][KF ? KS : 1];
+    i16x8 xbv[U][NB];
+    i16x8 xlv[U][XLO ? NB : 1];
+    float xres[U];  // ||x - hi - lo||^2 lane partial (XLO)
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
+    for (int s = 0; s < U; ++s) {
       xres[s] = 0.f;
       const int64_t i = row0 + 16 * s + r16;
       if constexpr (GBF && XBF) {
@@ -668,10 +672,10 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       }
     }
 
-    float best[SB], sec[SB];
-    int bidx[SB];
+    float best[U], sec[U];
+    int bidx[U];
 #pragma unroll
-    for (int s = 0; s < SB; ++s) { best[s] = -__builtin_inff(); sec[s] = -__builtin_inff(); bidx[s] = 0; }
+    for (int s = 0; s < U; ++s) { best[s] = -__builtin_inff(); sec[s] = -__builtin_inff(); bidx[s] = 0; }
 
     for (int c0 = 0; c0 < Kpad; c0 += kchunk) {
       const int rows = (Kpad - c0) < kchunk ? (Kpad - c0) : kchunk;
@@ -685,11 +689,11 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       // tile t.  The index of a load past the chunk's last tile is clamped to
       // a tile of the chunk; that operand is then not used.
       auto step = [&](const AO& op, int tt) {
-        f32x4 acc[SB];
-        tile_mfma<KS, SB, GBF, XLO, LB>(op, xv, xbv, xlv, acc);
+        f32x4 acc[U];
+        tile_mfma<KS, U, GBF, XLO, LB>(op, xv, xbv, xlv, acc);
         const int jb = c0 + tt;
 #pragma unroll
-        for (int s = 0; s < SB; ++s) {
+        for (int s = 0; s < U; ++s) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const float v = acc[s][r];
@@ -726,11 +730,11 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
 
     // Epilogue: combine the 4 lane groups, flag near ties, exact energy terms.
-    int bi_s[SB];
-    bool fl_s[SB];
-    double term_s[SB];
+    int bi_s[U];
+    bool fl_s[U];
+    double term_s[U];
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
+    for (int s = 0; s < U; ++s) {
       const int64_t i = row0 + 16 * s + r16;
       const bool valid = i < a.N;
       float b = best[s], sc = sec[s];
@@ -823,7 +827,9 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
 
       unsigned long long fm = __ballot(flag) & 0xFFFFull;
       n_flag += (unsigned)__popcll(fm);
-      if (defer) {
+      bool listed = false;
+      if constexpr (U == SB) listed = defer;   // lists exist in row-group mode only
+      if (listed) {
         if (flag && g == 0) {
           const int pos = nfl + __popcll(fm & ((1ull << r16) - 1ull));
           const int64_t own = (bx + (int64_t)(pos / (16 * SB)) * gx) * group_rows + wave * (16 * SB) +
@@ -853,12 +859,12 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       }
       bi_s[s] = bi;
       term_s[s] = term;
-      fl_s[s] = defer && flag;
+      fl_s[s] = listed && flag;
     }
 
     double e_lane = 0.0;
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
+    for (int s = 0; s < U; ++s) {
       const int64_t i = row0 + 16 * s + r16;
       const bool valid = i < a.N;
       const bool mine = valid && g == 0 && !fl_s[s];   // deferred rows are written later
@@ -871,16 +877,39 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       e_lane += mine ? term_s[s] : 0.0;
     }
     e_wave += wave_sum(e_lane);
-    // With streamed centroids the chunk area is free here: re-check full
-    // batches now, so that the re-check overlaps other workgroups' MFMA work
-    // instead of piling up after the last row group (bf16 GEMM kernels; in
-    // the float32 kernels the extra live registers of this call would spill).
-    if (kInterleave && defer && !resident) {
-      int* wc = wcnt + (nb & 1) * 16;   // two buffers: a slow wave may still read the previous one
-      if (lane == 0) wc[wave] = nfl;
-      __syncthreads();
-      recheck_batches(wc, false);
-      ++nb;
+  };
+
+  int nb = 0;   // row-group boundaries passed (selects the wc buffer)
+  bool balanced = false;
+  if constexpr (!GBF) balanced = resident;   // then defer is false: no lists, no barriers
+  if (balanced) {
+    // Float32 centroids resident in LDS: the waves are independent, so the
+    // 16-sample blocks are split evenly over every wave of the launch (wave
+    // gw takes blocks [gw B / GW, (gw + 1) B / GW)), in units of SB blocks
+    // and single blocks for the rest.  With row groups a grid apart the last
+    // round would run on a fraction of the waves (at N = 1e6 and 768
+    // workgroups of 256 rows: 5.09 rounds of work take 6).
+    const int64_t nblk = (a.N + 15) / 16;
+    const int64_t GW = (int64_t)gx * W, gw = (int64_t)bx * W + wave;
+    const int64_t b1 = (gw + 1) * nblk / GW;
+    int64_t b = gw * nblk / GW;
+    for (; b + SB <= b1; b += SB) unit(std::integral_constant<int, SB>{}, b * 16);
+    if constexpr (SB > 1)
+      for (; b < b1; ++b) unit(std::integral_constant<int, 1>{}, b * 16);
+  } else {
+    for (int64_t grp = bx; grp < groups; grp += gx) {
+      unit(std::integral_constant<int, SB>{}, grp * group_rows + (int64_t)wave * (16 * SB));
+      // With streamed centroids the chunk area is free here: re-check full
+      // batches now, so that the re-check overlaps other workgroups' MFMA work
+      // instead of piling up after the last row group (bf16 GEMM kernels; in
+      // the float32 kernels the extra live registers of this call would spill).
+      if (kInterleave && defer && !resident) {
+        int* wc = wcnt + (nb & 1) * 16;   // two buffers: a slow wave may still read the previous one
+        if (lane == 0) wc[wave] = nfl;
+        __syncthreads();
+        recheck_batches(wc, false);
+        ++nb;
+      }
     }
   }
 
