@@ -22,6 +22,8 @@ Acceleration" (arXiv 1805.10638).
   * energy safeguard        -- Sec. 2.1 (revert to the Lloyd iterate)
   * dynamic m               -- Sec. 2.2, Algorithm 1
   * default parameters      -- Sec. 3 (eps1=0.02, eps2=0.5, m initialised to 2)
+  * bound-based assignment  -- Sec. 3 (the experiments run the assignment
+                               step with Hamerly's lower-bound method)
 
 Readings of points the paper leaves open (each is listed with its reason in
 the design notes of the repository):
@@ -115,6 +117,55 @@ def assign(X, C, rows_per_chunk: int | None = None) -> Assignment:
     near = (d2 - d1) < NEAR_TIE_REL * d2
     near |= (d2 == 0.0)
     return Assignment(rho, d1, d2, near)
+
+
+def assign_bounded(X, C, C_ref, rho_ref, lb_ref):
+    """Assignment step with one lower bound per sample (Hamerly's method, the
+    assignment the paper's experiments use, Sec. 3).
+
+    ``lb_ref[i]`` is a lower bound of the distance from x_i to every centroid
+    of ``C_ref`` other than its label ``rho_ref[i]``.  When the centroids move
+    to C, each distance to a centroid j changes by at most
+    delta_j = ||C_j - C_ref_j|| (triangle inequality), so
+    lp_i = lb_ref[i] - max_{j != rho_ref[i]} delta_j bounds the distance from
+    x_i to every other centroid of C.  If the distance d1 to C[rho_ref[i]]
+    satisfies d1^2 (1 + 2.1e-6) < lp_i^2, the label is unchanged (and the row
+    is not a near tie, R11); otherwise the row is assigned in full.  The new
+    bound is lp_i for kept rows and the second smallest distance for the
+    others.
+
+    Returns (Assignment, lb_new, kept) where the Assignment is the one of
+    assign(X, C) (labels identical; d1, d2 and near ties of the full rows,
+    d2 = lp^2 and no near tie for kept rows)."""
+    X = _f64(X)
+    C = _f64(C)
+    C_ref = _f64(C_ref)
+    rho_ref = np.asarray(rho_ref)
+    lb_ref = _f64(lb_ref)
+    n, k = X.shape[0], C.shape[0]
+    delta = np.sqrt(((C - C_ref) ** 2).sum(axis=1))
+    if k > 1:
+        order = np.argsort(-delta, kind="stable")
+        excl = np.where(rho_ref == order[0], delta[order[1]], delta[order[0]])
+    else:
+        excl = np.zeros(n)
+    lp = lb_ref - excl
+    diff = X - C[rho_ref]
+    d1 = np.einsum("ij,ij->i", diff, diff)
+    kept = (lp > 0) & (d1 * (1.0 + 2.1e-6) < lp * lp)
+    rest = np.flatnonzero(~kept)
+    full = assign(X[rest], C)
+    rho = rho_ref.astype(np.int64).copy()
+    rho[rest] = full.rho
+    out_d1 = d1.copy()
+    out_d1[rest] = full.d1
+    out_d2 = np.where(kept, lp * lp, np.inf)
+    out_d2[rest] = full.d2
+    near = np.zeros(n, dtype=bool)
+    near[rest] = full.near_tie
+    lb_new = np.where(kept, lp, 0.0)
+    lb_new[rest] = np.sqrt(full.d2)
+    return Assignment(rho, out_d1, out_d2, near), lb_new, kept
 
 
 def energy(X, rho, C) -> float:

@@ -483,3 +483,82 @@ def test_golden_tol_reject_1d():
     assert r0.iters == z["iters"] and r0.rho.tolist() == z["rho"]
     np.testing.assert_allclose(r0.C.ravel(), [_frac(v) for v in z["C"]], rtol=1e-15)
     assert r0.E == _frac(z["E"])
+
+
+# ---------------------------------------------------------------------------
+# Bound-based assignment (Hamerly's lower bound, Sec. 3)
+# ---------------------------------------------------------------------------
+
+def _true_labels_and_second(X, C):
+    """Brute force: every distance written out, lowest index on ties."""
+    n, k = X.shape[0], C.shape[0]
+    D = np.empty((n, k))
+    for j in range(k):
+        D[:, j] = np.sqrt(((X - C[j]) ** 2).sum(axis=1))
+    rho = np.argmin(D, axis=1)
+    D2 = D.copy()
+    D2[np.arange(n), rho] = np.inf
+    return rho, D2.min(axis=1)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_bounded_assignment_walk(seed):
+    """Along a walk of centroid sets with shrinking and growing steps the
+    bounded assignment gives the brute-force labels, every bound stays below
+    the true distance to every other centroid, and small steps keep most
+    rows while large ones keep few."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(600, 3)) * 3.0
+    C = X[rng.choice(600, 7, replace=False)].copy()
+    rho, second = _true_labels_and_second(X, C)
+    lb = second.copy()
+    kept_frac = []
+    for scale in (1e-3, 1e-2, 0.1, 1e-3, 1.0, 3.0, 1e-4, 1e-2):
+        Cn = C + rng.normal(size=C.shape) * scale
+        a, lbn, kept = ko.assign_bounded(X, Cn, C, rho, lb)
+        r_true, s_true = _true_labels_and_second(X, Cn)
+        assert np.array_equal(a.rho, r_true)
+        assert np.all(lbn <= s_true * (1 + 1e-12))
+        kept_frac.append(kept.mean())
+        C, rho, lb = Cn, a.rho, lbn
+    assert kept_frac[0] > 0.9 and kept_frac[6] > 0.9
+    assert kept_frac[5] < 0.5
+
+
+def test_bounded_assignment_other_centroid_moves_in():
+    """One sample at 0 labelled with c_0 = 0.1 (bound 0.9 from c_1 = 1.0).
+    c_1 moves to 0.05: the largest shift of another centroid (0.95) exceeds
+    the bound, so the row is assigned in full and takes c_1.  Subtracting the
+    row's own centroid shift (0) instead would keep the stale label."""
+    X = np.array([[0.0]])
+    C_ref = np.array([[0.1], [1.0]])
+    a, lb, kept = ko.assign_bounded(X, np.array([[0.1], [0.05]]), C_ref, np.array([0]), np.array([0.9]))
+    assert not kept[0]
+    assert a.rho.tolist() == [1]
+    assert lb[0] == pytest.approx(0.1)
+
+
+def test_bounded_assignment_own_centroid_moves_most():
+    """c_0 (the row's own centroid) moves by 0.5, the others stay: the shift
+    subtracted from the bound is the largest among the OTHER centroids (0),
+    so the row is kept with its bound 0.9; subtracting the overall largest
+    shift (0.5) would give 0.4 < 0.6 and force a full assignment."""
+    X = np.array([[0.0]])
+    C_ref = np.array([[0.1], [1.0], [2.0]])
+    Cn = np.array([[0.6], [1.0], [2.0]])
+    a, lb, kept = ko.assign_bounded(X, Cn, C_ref, np.array([0]), np.array([0.9]))
+    assert kept[0]
+    assert a.rho.tolist() == [0]
+    assert lb[0] == pytest.approx(0.9)
+
+
+def test_bounded_assignment_static_centroids_keep_all_but_near_ties():
+    """Centroids that do not move and exact bounds: every row is kept except
+    those within the near-tie margin, which are assigned in full."""
+    X = np.array([[0.0], [0.5], [0.5 + 1e-9], [2.0]])
+    C = np.array([[0.0], [1.0], [2.5]])
+    rho, second = _true_labels_and_second(X, C)
+    a, lb, kept = ko.assign_bounded(X, C, C, rho, second)
+    assert kept.tolist() == [True, False, False, True]
+    assert np.array_equal(a.rho, rho)
+    assert a.near_tie.tolist() == [False, True, True, False]
