@@ -53,7 +53,7 @@ def parse():
                          "against the HBM roofline at N=1e7 d=16 K=256 and N=1e6 d=32 K=256")
     ap.add_argument("--seeds", type=int, default=100, help="small: number of seeds")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of instances")
-    ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
+    ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
     ap.add_argument("--engines", type=int, choices=[1, 2], default=1,
                     help="served: one engine for all jobs, or one per size class (large jobs on "
@@ -86,10 +86,12 @@ def cpu_baseline(X, C0, passes_per_solve, budget_s):
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle G pass (float64 direct differences, assignment+update+energy) on the "
-                   f"first {rows} of {n} rows in {dt:.1f} s, scaled to full passes "
-                   f"({pass_s:.2f} s/pass) times {passes_per_solve:.1f} assignment passes per "
-                   f"solve; single-threaded NumPy on a host with {threads} visible cores"),
+        "sample": (f"extrapolated, not a timed solve: one oracle G pass (float64 direct differences, "
+                   f"assignment+update+energy) timed on the first {rows} of {n} rows in {dt:.1f} s, "
+                   f"scaled to a full pass ({pass_s:.2f} s/pass) times the GPU's mean of "
+                   f"{passes_per_solve:.1f} assignment passes per solve (a full oracle solve would take "
+                   f"about {pass_s * passes_per_solve / 60:.0f} min); single-threaded NumPy on a host with "
+                   f"{threads} visible cores"),
         "dist_evals_per_s": rows * C0.shape[0] / dt,
     }
 
@@ -159,7 +161,7 @@ def main():
         passes.append(st.assign_passes)
         acc.append(st.accepted)
         rej.append(st.rejected)
-        flagged.append(st.flagged_rows)
+        flagged.append(st.recheck_rows)
         assign_ms += st.assign_ms
         assign_n += st.assign_launches
     torch.cuda.synchronize()
@@ -204,7 +206,7 @@ def main():
         "assign_passes_mean": statistics.mean(passes),
         "accepted_mean": statistics.mean(acc),
         "rejected_mean": statistics.mean(rej),
-        "flagged_rows_per_pass": sum(flagged) / max(sum(passes), 1),
+        "recheck_rows_per_pass": sum(flagged) / max(sum(passes), 1),
         "roofline": {
             "kernel": "assignment (k_assign, candidate role)",
             "bound": "mfma",
@@ -339,7 +341,17 @@ def precision_workload(args, km, synth, torch):
     """N=4,000,000, d=128, K=1024 with X stored as bfloat16: time to converge
     with the float32 and the bfloat16 distance GEMM from the same C0, the
     assignment kernel against its roofline, and the error of each result
-    against the float64 oracle (labels on sampled rows, energy, centroids)."""
+    against the float64 oracle:
+      * labels: the result's labels against the oracle's assignment at the
+        result's centroids on 20,000 sampled rows (mismatches outside oracle
+        near ties, and the near ties);
+      * energy: |E - E_oracle| / E_oracle with E_oracle the float64 energy of
+        the result's labels at its centroids over all N rows;
+      * centroids: one more kmeans_g at the result's centroids (same GEMM)
+        against the oracle's means of its labels, max over all K centroids of
+        ||dc_j|| / max(||c_j||, s_X) (s_X the RMS spread of X), and its
+        energy against the oracle's;
+      * flagged (re-checked) rows per assignment pass."""
     from oracle import kmeans_oracle as ko
     N, d, K = 4_000_000, 128, 1024
     Xb, _ = synth.precision(rep=0, n=N, d=d, k=K)
@@ -347,8 +359,16 @@ def precision_workload(args, km, synth, torch):
     steps = max(1, min(args.steps, 3))
     inits = [torch.from_numpy(synth.init_centroids(Xb, K, s)).to("cuda") for s in range(steps + 1)]
     ctx = km.Context(0)
-    rows = np.random.default_rng(7).choice(N, 4096, replace=False)
-    X64s = synth.bf16_bits_to_f32(Xb[rows]).astype(np.float64)
+    rows = np.sort(np.random.default_rng(7).choice(N, 20000, replace=False))
+    X64 = synth.bf16_bits_to_f32(Xb).astype(np.float64)
+    sX = float(np.sqrt(((X64 - X64.mean(axis=0)) ** 2).sum(axis=1).mean()))
+
+    def energy_all(lab, C):
+        tot = 0.0
+        for a in range(0, N, 500_000):
+            tot += ko.energy(X64[a:a + 500_000], lab[a:a + 500_000], C)
+        return tot
+
     res = {}
     for prec, peak in (("f32", FP32_MFMA_PEAK_TFLOPS), ("bf16", BF16_MFMA_PEAK_TFLOPS)):
         km.kmeans_solve(Xd, inits[0], m_max=10, tol=1e-6, prec=prec, ctx=ctx, max_iter=3)  # warm-up
@@ -362,20 +382,35 @@ def precision_workload(args, km, synth, torch):
         el = time.perf_counter() - t0
         ctx.set_timing(False)
         C, rho, E, it, st = outs[-1]
+        print(f"[precision] {prec}: {steps} solves in {el:.2f} s; oracle checks", file=sys.stderr, flush=True)
         a_ms = sum(o[4].assign_ms for o in outs) / max(1, sum(o[4].assign_launches for o in outs))
         ach = 2.0 * N * K * d / (a_ms / 1e3) / 1e12
         Cn = C.cpu().numpy().astype(np.float64)
-        a = ko.assign(X64s, Cn)
-        lab = rho.cpu().numpy()[rows]
+        lab_all = rho.cpu().numpy().astype(np.int64)
+        a = ko.assign(X64[rows], Cn)
+        lab = lab_all[rows]
         mism = int(((a.rho != lab) & ~a.near_tie).sum())
-        e_rows = ko.energy(X64s, lab, Cn)
-        e_gpu_rows = float(((X64s - Cn[lab]) ** 2).sum())
+        E_or = energy_all(lab_all, Cn)
+        # G at the result: labels, means and energy against the oracle
+        rho_g, C_g, E_g, gst = km.kmeans_g(Xd, C, prec=prec, ctx=ctx)
+        lab_g = rho_g.cpu().numpy().astype(np.int64)
+        Co, _ = ko.update(X64, lab_g, Cn)
+        cerr = np.linalg.norm(C_g.cpu().numpy().astype(np.float64) - Co, axis=1) / \
+            np.maximum(np.linalg.norm(Co, axis=1), sX)
+        E_or_g = energy_all(lab_g, Cn)
         res[prec] = {"solves_per_s": steps / el, "time_to_converge_ms": el * 1e3 / steps,
                      "iters": it, "assign_passes": st.assign_passes, "E": E,
                      "assign_avg_us": a_ms * 1e3, "assign_tflops": ach, "peak_tflops": peak,
-                     "frac": ach / peak, "flagged_rows_per_pass": st.flagged_rows / st.assign_passes,
-                     "oracle_label_mismatch_sampled": mism, "oracle_near_ties_sampled": int(a.near_tie.sum()),
-                     "sampled_energy_rel_err": abs(e_gpu_rows - e_rows) / e_rows}
+                     "frac": ach / peak, "recheck_rows_per_pass": st.recheck_rows / st.assign_passes,
+                     "oracle_errors": {
+                         "label_mismatch_outside_near_ties_sampled": mism,
+                         "label_near_ties_sampled": int(a.near_tie.sum()),
+                         "label_sample_rows": int(rows.size),
+                         "energy_rel_err": abs(E - E_or) / E_or,
+                         "g_labels_equal_result": bool((lab_g == lab_all).all()),
+                         "g_energy_rel_err": abs(E_g - E_or_g) / E_or_g,
+                         "g_max_rel_centroid_err": float(cerr.max()),
+                         "g_recheck_rows": gst.recheck_rows, "g_near_tie_rows": gst.near_tie_rows}}
     ef, eb = res["f32"]["E"], res["bf16"]["E"]
     print(json.dumps({"metric": "precision mode: time to converge, f32 vs bf16 distance GEMM",
                       "config": {"workload": "gaussian-mixture N=4000000 d=128 K=1024, 5% outliers, "
@@ -490,8 +525,13 @@ def served_workload(args, km, synth, torch):
             e.step()
             warm -= len(e.poll())
 
-    lat, lag, lat_large = [], [], []
+    lat, lag, lat_large, lat_small = [], [], [], []
     t_sub = {}
+    fin_at = [0.0] * n                               # finish time of each job (s after the start)
+    keep = {}                                        # sampled small jobs kept for the oracle check
+    sample = set(j for j in range(n) if not spec[j][3] and spec[j][0] * spec[j][1] * spec[j][2] <= 5e7)
+    sample = set(sorted(sample)[len(sample) // 4::max(1, len(sample) // 3)][:3])
+    backlog_at_end = None
     t_start = time.perf_counter()
     i = done = 0
     while done < n:
@@ -511,14 +551,29 @@ def served_workload(args, km, synth, torch):
                 j, ts = t_sub.pop((id(e), tk))
                 dt = (time.perf_counter() - ts) * 1e3
                 lat.append(dt)
-                if spec[j][3]:
-                    lat_large.append(dt)
+                (lat_large if spec[j][3] else lat_small).append(dt)
+                fin_at[j] = time.perf_counter() - t_start
+                if j in sample:
+                    keep[j] = (C.cpu().numpy(), rho.cpu().numpy(), res)
                 done += 1
+        if backlog_at_end is None and i == n:
+            backlog_at_end = n - done
         if busy == 0 and i < n:
             time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t_start))))
     t_served = time.perf_counter() - t_start
     for e in engines:
         e.close()
+    # served results against the float64 oracle (a few small jobs; their data
+    # is regenerated from the same seeded device generator)
+    from oracle import kmeans_oracle as ko
+    o_mism = 0
+    for j, (Cj, rj, res) in sorted(keep.items()):
+        X, C0 = make(j)
+        r = ko.solve(X.cpu().numpy().astype(np.float64), C0.cpu().numpy().astype(np.float64), m_max=10, tol=1e-6)
+        if r.iters != res.iters or abs(r.E - res.E) > 1e-6 * abs(r.E) or \
+                np.abs(Cj.astype(np.float64) - r.C).max() > 1e-4 * max(1.0, np.abs(r.C).max()):
+            o_mism += 1
+        del X, C0
 
     # FIFO baseline: float32 GEMM, one job at a time, in arrival order
     fin = 0.0
@@ -548,7 +603,13 @@ def served_workload(args, km, synth, torch):
                                "mix, 2% large (N=2e6 d=96 K=2048 bfloat16 X, bfloat16 GEMM); HBM budget 200 GB",
                    "jobs": n, "large_jobs": int(large.sum()), "engines": args.engines},
         "served": {"solves_per_s": n / t_served, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-                   "large_p50_ms": pct(lat_large, 50), "mean_submit_lag_ms": 1e3 * statistics.mean(lag)},
+                   "small_p50_ms": pct(lat_small, 50), "small_p99_ms": pct(lat_small, 99),
+                   "large_p50_ms": pct(lat_large, 50), "large_p99_ms": pct(lat_large, 99),
+                   "mean_submit_lag_ms": 1e3 * statistics.mean(lag),
+                   "arrival_rate": n / args.duration, "keeps_up": n / t_served >= 0.98 * n / args.duration,
+                   "unfinished_when_arrivals_end": backlog_at_end,
+                   "drain_after_arrivals_s": t_served - args.duration,
+                   "oracle_checked_jobs": len(keep), "oracle_mismatches": o_mism},
         "fifo_f32": {"solves_per_s": n / fin, "p50_ms": pct(base_lat, 50), "p99_ms": pct(base_lat, 99),
                      "busy_s": busy},
     }), flush=True)

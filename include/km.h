@@ -56,6 +56,13 @@ typedef enum { KM_GEMM_F32 = 0, KM_GEMM_BF16 = 1 } km_prec;
 #define KM_FLAG_FIXED_M        1u  /* keep m at m_init (classical fixed-m Anderson, Sec. 2.2) */
 #define KM_FLAG_LITERAL_RETURN 2u  /* return as soon as an assignment repeats, even for an
                                       accelerated iterate (Algorithm 1 read literally) */
+#define KM_FLAG_BOUNDS         4u  /* kmeans_solve: keep per-row lower bounds of the distance to
+                                      the second-nearest centroid (Hamerly's bound, as the paper's
+                                      assignment step does, Sec. 3) and skip the distance GEMM for
+                                      rows whose bound proves their label; float32 GEMM with the
+                                      K x d centroids fitting the kernel's LDS budget only (ignored
+                                      otherwise and by the engine).  Labels and decisions are those
+                                      of the full assignment; E may differ in its last bits. */
 
 #define KM_M_MAX_LIMIT 64          /* largest supported m_max */
 #define KM_TRACE_REC 80            /* doubles per trace record (see km_opts) */
@@ -101,7 +108,11 @@ int32_t km_get_tile_shape(const km_ctx *ctx, km_prec prec, km_xtype xt, int32_t 
 
 typedef struct {
   int64_t changed;         /* rows whose label differs from rho_prev (0 if rho_prev NULL) */
-  int64_t flagged_rows;    /* rows re-checked with float64 differences */
+  int64_t recheck_rows;    /* rows whose label was re-checked with float64 differences (the
+                              GEMM's rounding bound could not separate the two best scores) */
+  int64_t near_tie_rows;   /* rows whose two smallest float64 squared distances d1 <= d2
+                              satisfy (d2 - d1) < 1e-6 d2 (or d2 = 0): the near ties of the
+                              parity definition; every such row is among the re-checked rows */
   int32_t empty_clusters;  /* clusters with no sample (centroid kept, reading R9) */
   float assign_ms;         /* device time of the assignment kernel, -1 unless timing is on */
   float update_ms;         /* device time of the update step (cluster sums and sizes,
@@ -144,9 +155,14 @@ typedef struct {
    *     m-rule, 4 decision (0 Lloyd candidate kept, 1 accelerated kept,
    *     2 rejected, 3 converged, 4 stopped by tol, 5 max_iter),
    *     5 E(fall-back), 6 changed labels of fall-back, 7 accepted energy,
-   *     8 m_t, 9 columns used, 10 flagged rows, 16.. theta_1..theta_{m_t}. */
+   *     8 m_t, 9 columns used, 10 re-checked rows, 11 stop code, 12 near-tie rows,
+   *     16.. theta_1..theta_{m_t}. */
   float *trace_C;
   double *trace_rec;
+  /* Optional HOST pointer, NULL or (max_iter + 1) ints: entry 0 is the initial m,
+   * entry t (1 <= t <= iters) the m after the dynamic-m rule of iteration t
+   * (Sec. 2.2); entries past iters are not written. */
+  int32_t *m_traj;
 } km_opts;
 
 /* Fill `opt` with the defaults listed above. */
@@ -159,7 +175,11 @@ typedef struct {
   int32_t assign_passes;   /* assignment passes incl. the one of G(C0) */
   int32_t m_final;         /* m at return */
   int32_t assign_launches; /* timed candidate assignment launches (timing on) */
-  int64_t flagged_rows;    /* rows re-checked in float64, summed over passes */
+  int64_t recheck_rows;    /* rows re-checked in float64, summed over passes */
+  int64_t near_tie_rows;   /* near-tie rows (see km_g_stats), summed over passes */
+  int64_t gemm_rows;       /* rows that went through the distance GEMM, summed over passes
+                              (N per pass unless KM_FLAG_BOUNDS skipped rows) */
+  int32_t bounds;          /* 1 if row bounds were in use */
   double device_ms;        /* wall time of the call measured with HIP events */
   double assign_ms;        /* summed duration of the timed assignment launches */
 } km_solve_stats;
@@ -211,7 +231,7 @@ typedef struct {
   int32_t iters;
   double E;
   int32_t accepted, rejected, assign_passes, m_final;
-  int64_t flagged_rows;
+  int64_t recheck_rows, near_tie_rows;
   double latency_ms;     /* host time from submission to the result being ready */
 } km_job_result;
 
@@ -219,8 +239,9 @@ typedef struct km_engine km_engine;
 
 /* Engine on ctx's device (its own internal stream, ordered after ctx's
  * stream at creation).  Jobs share m_max, tol and opt (opt may be NULL; its
- * trace pointers must be NULL).  hbm_budget bounds the bytes of job
- * workspaces on the device at once (0: no bound); queued jobs are admitted
+ * trace and m_traj pointers must be NULL).  hbm_budget bounds the device bytes
+ * of the admitted jobs at once (0: no bound): each job counts its workspace
+ * plus its X, C0, C_out and rho_out; queued jobs are admitted
  * in submission order when they fit.  graphs = 1 replays iterations from a
  * HIP graph while the job set is unchanged.  Each job's GEMM precision is
  * its own (km_job.prec; opt->prec is not used). */
@@ -234,7 +255,8 @@ int64_t km_job_workspace_bytes(const km_job *job, int32_t m_max);
 
 /* Queue a job (checked like kmeans_solve); *ticket names its result.  Its
  * buffers must stay valid until km_engine_poll has returned the result.
- * KM_ENOMEM if its workspace alone exceeds the budget. */
+ * KM_ENOMEM if its device memory alone (workspace, X, C0, C_out, rho_out)
+ * exceeds the budget. */
 km_status km_engine_submit(km_engine *e, const km_job *job, int64_t *ticket);
 
 /* Admit queued jobs that fit (at iteration boundaries), launch one

@@ -33,21 +33,22 @@ class KMError(RuntimeError):
 
 
 class _GStats(ct.Structure):
-    _fields_ = [("changed", ct.c_int64), ("flagged_rows", ct.c_int64),
+    _fields_ = [("changed", ct.c_int64), ("recheck_rows", ct.c_int64), ("near_tie_rows", ct.c_int64),
                 ("empty_clusters", ct.c_int32), ("assign_ms", ct.c_float), ("update_ms", ct.c_float)]
 
 
 class _Opts(ct.Structure):
     _fields_ = [("eps1", ct.c_double), ("eps2", ct.c_double), ("ridge", ct.c_double),
                 ("m_init", ct.c_int32), ("max_iter", ct.c_int32), ("prec", ct.c_int),
-                ("flags", ct.c_uint32), ("trace_C", ct.c_void_p), ("trace_rec", ct.c_void_p)]
+                ("flags", ct.c_uint32), ("trace_C", ct.c_void_p), ("trace_rec", ct.c_void_p),
+                ("m_traj", ct.c_void_p)]
 
 
 class _SolveStats(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("accepted", ct.c_int32), ("rejected", ct.c_int32),
                 ("assign_passes", ct.c_int32), ("m_final", ct.c_int32),
-                ("assign_launches", ct.c_int32), ("flagged_rows", ct.c_int64),
-                ("device_ms", ct.c_double), ("assign_ms", ct.c_double)]
+                ("assign_launches", ct.c_int32), ("recheck_rows", ct.c_int64),
+                ("near_tie_rows", ct.c_int64), ("device_ms", ct.c_double), ("assign_ms", ct.c_double)]
 
 
 class _Job(ct.Structure):
@@ -60,7 +61,7 @@ class _JobResult(ct.Structure):
     _fields_ = [("ticket", ct.c_int64), ("status", ct.c_int32), ("iters", ct.c_int32),
                 ("E", ct.c_double), ("accepted", ct.c_int32), ("rejected", ct.c_int32),
                 ("assign_passes", ct.c_int32), ("m_final", ct.c_int32),
-                ("flagged_rows", ct.c_int64), ("latency_ms", ct.c_double)]
+                ("recheck_rows", ct.c_int64), ("near_tie_rows", ct.c_int64), ("latency_ms", ct.c_double)]
 
 
 @dataclass
@@ -73,19 +74,21 @@ class JobResult:
     rejected: int
     assign_passes: int
     m_final: int
-    flagged_rows: int
+    recheck_rows: int
+    near_tie_rows: int
     latency_ms: float
 
 
 def _job_result(r: _JobResult) -> JobResult:
     return JobResult(r.ticket, r.status, r.iters, r.E, r.accepted, r.rejected, r.assign_passes,
-                     r.m_final, r.flagged_rows, r.latency_ms)
+                     r.m_final, r.recheck_rows, r.near_tie_rows, r.latency_ms)
 
 
 @dataclass
 class GStats:
     changed: int
-    flagged_rows: int
+    recheck_rows: int       # rows re-checked with float64 differences
+    near_tie_rows: int      # float64 near ties (parity definition), all among the re-checked rows
     empty_clusters: int
     assign_ms: float = -1.0   # device times from HIP events when Context.set_timing(True)
     update_ms: float = -1.0
@@ -98,11 +101,13 @@ class SolveStats:
     rejected: int
     assign_passes: int
     m_final: int
-    flagged_rows: int
+    recheck_rows: int
+    near_tie_rows: int
     device_ms: float
     assign_ms: float
     assign_launches: int
     status: int
+    m_traj: list | None = None   # m after the dynamic-m rule per iteration (entry 0: initial m)
 
 
 _lib = None
@@ -262,10 +267,15 @@ def _check_dev(t: torch.Tensor, name: str, device: int):
 
 
 def kmeans_g(X: torch.Tensor, C: torch.Tensor, prec="f32", rho_prev: torch.Tensor | None = None,
-             ctx: Context | None = None):
+             ctx: Context | None = None, out: tuple | None = None):
     """One application of G (assignment then update).
 
-    Returns (rho int32 [N], C_out float32 [K,d], E float (energy of C), GStats)."""
+    Returns (rho int32 [N], C_out float32 [K,d], E float (energy of C), GStats).
+    ``out`` = (rho, C_out) writes into caller-owned tensors."""
+    return _g_call("kmeans_g", X, C, prec, rho_prev, ctx, out)
+
+
+def _g_call(name, X, C, prec, rho_prev, ctx, out):
     dev = X.device.index
     ctx = ctx or _context(dev)
     _check_dev(X, "X", dev)
@@ -276,8 +286,17 @@ def kmeans_g(X: torch.Tensor, C: torch.Tensor, prec="f32", rho_prev: torch.Tenso
     K = C.shape[0]
     if C.shape[1] != d:
         raise ValueError("C must be K x d")
-    rho = torch.empty(N, dtype=torch.int32, device=X.device)
-    C_out = torch.empty_like(C)
+    if out is None:
+        rho = torch.empty(N, dtype=torch.int32, device=X.device)
+        C_out = torch.empty_like(C)
+    else:
+        rho, C_out = out
+        _check_dev(rho, "rho", dev)
+        _check_dev(C_out, "C_out", dev)
+        if rho.dtype != torch.int32 or rho.numel() != N:
+            raise ValueError("rho must be int32 with N entries")
+        if C_out.dtype != torch.float32 or C_out.shape != C.shape:
+            raise ValueError("C_out must be float32 K x d")
     E = ct.c_double()
     gs = _GStats()
     if rho_prev is not None:
@@ -285,21 +304,21 @@ def kmeans_g(X: torch.Tensor, C: torch.Tensor, prec="f32", rho_prev: torch.Tenso
         if rho_prev.dtype != torch.int32:
             raise TypeError("rho_prev must be int32")
     ctx._bind_stream()
-    st = ctx.lib.kmeans_g(ctx.h, ct.c_void_p(X.data_ptr()), _xtype(X), N, d, K,
+    st = getattr(ctx.lib, name)(ctx.h, ct.c_void_p(X.data_ptr()), _xtype(X), N, d, K,
                           ct.c_void_p(C.data_ptr()), _prec(prec),
                           ct.c_void_p(rho_prev.data_ptr()) if rho_prev is not None else None,
                           ct.c_void_p(rho.data_ptr()), ct.c_void_p(C_out.data_ptr()),
                           ct.byref(E), ct.byref(gs))
-    ctx._check(st, "kmeans_g")
-    return rho, C_out, E.value, GStats(gs.changed, gs.flagged_rows, gs.empty_clusters, gs.assign_ms,
-                                       gs.update_ms)
+    ctx._check(st, name)
+    return rho, C_out, E.value, GStats(gs.changed, gs.recheck_rows, gs.near_tie_rows, gs.empty_clusters,
+                                       gs.assign_ms, gs.update_ms)
 
 
 def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float = 1e-6,
                  max_iter: int = 500, eps1: float = 0.02, eps2: float = 0.5, m_init: int = 2,
                  prec="f32", fixed_m: bool = False, literal_return: bool = False,
                  ridge: float = 1e-10, trace: bool = False, ctx: Context | None = None,
-                 out: tuple | None = None):
+                 out: tuple | None = None, m_traj: bool = False):
     """Anderson-accelerated Lloyd K-Means (Algorithm 1).
 
     Returns (C float32 [K,d], rho int32 [N], E, iters, SolveStats) and, with
@@ -328,6 +347,10 @@ def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float 
               "rec": torch.zeros((max_iter + 1, KM_TRACE_REC), dtype=torch.float64, device=X.device)}
         o.trace_C = tr["C"].data_ptr()
         o.trace_rec = tr["rec"].data_ptr()
+    mt = None
+    if m_traj:
+        mt = (ct.c_int32 * (max_iter + 1))()
+        o.m_traj = ct.cast(mt, ct.c_void_p)
     E = ct.c_double()
     it = ct.c_int32()
     ss = _SolveStats()
@@ -338,7 +361,8 @@ def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float 
                               ct.byref(E), ct.byref(it), ct.byref(ss))
     ctx._check(st, "kmeans_solve", allow=(KM_OK, KM_NOT_CONVERGED))
     stats = SolveStats(ss.iters, ss.accepted, ss.rejected, ss.assign_passes, ss.m_final,
-                       ss.flagged_rows, ss.device_ms, ss.assign_ms, ss.assign_launches, st)
+                       ss.recheck_rows, ss.near_tie_rows, ss.device_ms, ss.assign_ms, ss.assign_launches, st,
+                       list(mt[:it.value + 1]) if mt is not None else None)
     if trace:
         return C, rho, E.value, it.value, stats, tr
     return C, rho, E.value, it.value, stats

@@ -20,6 +20,8 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
     s.K = s.K > c->shape.K ? s.K : c->shape.K;
     s.cap = s.cap > c->shape.cap ? s.cap : c->shape.cap;
     s.bf = s.bf > c->shape.bf ? s.bf : c->shape.bf;
+    s.it = s.it > c->shape.it ? s.it : c->shape.it;
+    s.bnd = s.bnd > c->shape.bnd ? s.bnd : c->shape.bnd;
     HIP_TRY(c, hipStreamSynchronize(c->q), "hipStreamSynchronize");
     HIP_TRY(c, hipFree(c->arena), "hipFree");
     c->arena = nullptr;
@@ -38,6 +40,104 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
   c->arena_bytes = off;
   c->shape = s;
   ws_layout(s, (char*)p, &c->w);
+  return KM_OK;
+}
+
+// Clears n 32-bit words (a kernel rather than a memset node, so that the
+// launch sequence can be recorded into a graph).
+__global__ __launch_bounds__(256) void k_clear_words(unsigned* p, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0u;
+}
+
+static hipError_t launch_clear(void* p, size_t bytes, hipStream_t s) {
+  const int n = (int)(bytes / 4);
+  clear_pending_error();
+  hipLaunchKernelGGL(k_clear_words, dim3((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), dim3(256), 0, s,
+                     (unsigned*)p, n);
+  return hipGetLastError();
+}
+
+// Argument checks of one G application.
+static km_status g_check(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                         const float* C, km_prec prec, const int32_t* rho_prev, int32_t* rho, float* C_out,
+                         double* E) {
+  km_status s = check_common(c, X, xt, N, d, K, prec);
+  if (s != KM_OK) return s;
+  if (!E) return fail(c, KM_EINVAL, "E must be a host pointer");
+  if (!is_device_ptr(C) || !is_device_ptr(rho) || !is_device_ptr(C_out))
+    return fail(c, KM_EINVAL, "C, rho and C_out must be device pointers");
+  if (!aligned16(C) || !aligned16(C_out)) return fail(c, KM_EINVAL, "C and C_out must start on a 16-byte boundary");
+  if (rho_prev && !is_device_ptr(rho_prev)) return fail(c, KM_EINVAL, "rho_prev must be a device pointer");
+  const size_t xbytes = (size_t)N * d * (xt == KM_X_BF16 ? 2 : 4);
+  const size_t cbytes = (size_t)K * d * 4;
+  if (overlap(C_out, cbytes, C, cbytes) || overlap(C_out, cbytes, X, xbytes) ||
+      overlap(rho, (size_t)N * 4, X, xbytes) || overlap(rho, (size_t)N * 4, C_out, cbytes))
+    return fail(c, KM_EINVAL, "outputs must not alias the inputs");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  return KM_OK;
+}
+
+// The launches of one G application on the buffers of w: prep, bound of
+// |x|, assignment, energy, update, means; then the scalars come back through
+// the context's pinned slots.
+static km_status g_run(km_ctx* c, const Ws& w, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                       const float* C, km_prec prec, const int32_t* rho_prev, int32_t* rho, float* C_out,
+                       double* E, km_g_stats* st) {
+  hipStream_t st_ = c->q;
+  const bool gbf = prec == KM_GEMM_BF16;
+  HIP_TRY(c, hipEventRecord(c->enter, c->stream), "hipEventRecord");
+  HIP_TRY(c, hipStreamWaitEvent(st_, c->enter, 0), "hipStreamWaitEvent");
+
+  HIP_TRY(c, launch_clear(w.ctl, sizeof(Ctl), st_), "clear control block");
+  HIP_TRY(c, launch_prep(C, K, d, w.nc_tmp, gbf ? w.Cb_tmp : nullptr, gbf ? w.del_tmp : nullptr, st_), "prep");
+  AssignArgs a{};
+  a.X = X; a.N = N; a.d = d; a.K = K; a.C = C; a.nc = w.nc_tmp;
+  a.Cb = gbf ? w.Cb_tmp : nullptr; a.delta = gbf ? w.del_tmp : nullptr;
+  a.lab = rho; a.lab_prev = rho_prev; a.e_part = w.e_part; a.flags = w.flags; a.ctl = w.ctl;
+  a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
+  a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
+  UpdateArgs u{};
+  u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
+  u.lab = rho; u.lab_from_ctl = 0; u.lrank = w.lrank; u.blockcount = w.blockcount;
+  u.counts = w.counts; u.seg_start = w.seg_start; u.item_start = w.item_start;
+  u.item_cluster = w.item_cluster; u.perm = w.perm; u.partial = w.partial;
+  u.max_items = update_max_items(N, K); u.ctl = w.ctl; u.gated = 0;
+  u.fx = fx_ok(K, d); u.xbound = w.xbound; u.fxpart = w.fxpart;
+  // bound of |x| for the fixed-point sums: part of preparing X, outside the
+  // phase times (a solve computes it once)
+  HIP_TRY(c, launch_xbound(u, st_), "bound of |x|");
+  // with timing on, the events take the times of the kernels' own dispatches
+  HIP_TRY(c, launch_assign(a, kRolePlain, st_, c->timing ? c->ta[0] : nullptr, c->timing ? c->tb[0] : nullptr),
+          "assignment");
+  const int grid = assign_grid(a);
+  HIP_TRY(c, launch_reduce_energy(w.e_part, grid, w.e_out, st_), "energy");
+  HIP_TRY(c, launch_update_sums(u, st_, c->timing ? c->ta[1] : nullptr), "update");
+  FinalizeArgs f{};
+  f.d = d; f.K = K; f.cap = 0; f.partial = w.partial; f.item_start = w.item_start;
+  f.counts = w.counts; f.C_in = C; f.C_out = C_out; f.ctl = w.ctl; f.mode = kFinG;
+  f.fx = u.fx; f.fxpart = w.fxpart; f.xbound = w.xbound; f.N = N;
+  f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
+  f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
+  HIP_TRY(c, launch_finalize(f, st_, c->timing ? c->tb[1] : nullptr), "finalize");
+  HIP_TRY(c, hipMemcpyAsync(c->scal_host, w.e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
+  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
+  HIP_TRY(c, hipStreamSynchronize(st_), "hipStreamSynchronize");
+  *E = c->scal_host[0];
+  if (st) {
+    st->changed = rho_prev ? (int64_t)c->ctl_host->cnt_changed[0] : 0;
+    st->recheck_rows = (int64_t)c->ctl_host->cnt_flagged[0];
+    st->near_tie_rows = (int64_t)c->ctl_host->cnt_near[0];
+    st->empty_clusters = c->ctl_host->empty;
+    st->assign_ms = st->update_ms = -1.f;
+    if (c->timing) {
+      if (hipEventElapsedTime(&st->assign_ms, c->ta[0], c->tb[0]) != hipSuccess ||
+          hipEventElapsedTime(&st->update_ms, c->ta[1], c->tb[1]) != hipSuccess) {
+        clear_pending_error();
+        st->assign_ms = st->update_ms = -1.f;
+      }
+    }
+  }
+  if (!isfinite(*E)) return fail(c, KM_ENONFINITE, "energy is not finite");
   return KM_OK;
 }
 
@@ -148,84 +248,19 @@ void km_opts_default(km_opts* o) {
   o->flags = 0;
   o->trace_C = nullptr;
   o->trace_rec = nullptr;
+  o->m_traj = nullptr;
 }
 
 km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
                    const float* C, km_prec prec, const int32_t* rho_prev, int32_t* rho, float* C_out,
                    double* E, km_g_stats* st) {
-  km_status s = check_common(c, X, xt, N, d, K, prec);
+  km_status s = g_check(c, X, xt, N, d, K, C, prec, rho_prev, rho, C_out, E);
   if (s != KM_OK) return s;
-  if (!E) return fail(c, KM_EINVAL, "E must be a host pointer");
-  if (!is_device_ptr(C) || !is_device_ptr(rho) || !is_device_ptr(C_out))
-    return fail(c, KM_EINVAL, "C, rho and C_out must be device pointers");
-  if (!aligned16(C) || !aligned16(C_out)) return fail(c, KM_EINVAL, "C and C_out must start on a 16-byte boundary");
-  if (rho_prev && !is_device_ptr(rho_prev)) return fail(c, KM_EINVAL, "rho_prev must be a device pointer");
-  const size_t xbytes = (size_t)N * d * (xt == KM_X_BF16 ? 2 : 4);
-  const size_t cbytes = (size_t)K * d * 4;
-  if (overlap(C_out, cbytes, C, cbytes) || overlap(C_out, cbytes, X, xbytes) ||
-      overlap(rho, (size_t)N * 4, X, xbytes) || overlap(rho, (size_t)N * 4, C_out, cbytes))
-    return fail(c, KM_EINVAL, "outputs must not alias the inputs");
-  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   Shape want;
   want.N = N; want.d = d; want.K = K; want.cap = 0; want.bf = prec == KM_GEMM_BF16;
   s = ensure_ws(c, want);
   if (s != KM_OK) return s;
-  hipStream_t st_ = c->q;
-  const bool gbf = prec == KM_GEMM_BF16;
-  HIP_TRY(c, hipEventRecord(c->enter, c->stream), "hipEventRecord");
-  HIP_TRY(c, hipStreamWaitEvent(st_, c->enter, 0), "hipStreamWaitEvent");
-
-  HIP_TRY(c, hipMemsetAsync(c->w.ctl, 0, sizeof(Ctl), st_), "hipMemsetAsync");
-  HIP_TRY(c, launch_prep(C, K, d, c->w.nc_tmp, gbf ? c->w.Cb_tmp : nullptr, gbf ? c->w.del_tmp : nullptr, st_),
-          "prep");
-  AssignArgs a{};
-  a.X = X; a.N = N; a.d = d; a.K = K; a.C = C; a.nc = c->w.nc_tmp;
-  a.Cb = gbf ? c->w.Cb_tmp : nullptr; a.delta = gbf ? c->w.del_tmp : nullptr;
-  a.lab = rho; a.lab_prev = rho_prev; a.e_part = c->w.e_part; a.flags = c->w.flags; a.ctl = c->w.ctl;
-  a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
-  a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
-  UpdateArgs u{};
-  u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
-  u.lab = rho; u.lab_from_ctl = 0; u.lrank = c->w.lrank; u.blockcount = c->w.blockcount;
-  u.counts = c->w.counts; u.seg_start = c->w.seg_start; u.item_start = c->w.item_start;
-  u.item_cluster = c->w.item_cluster; u.perm = c->w.perm; u.partial = c->w.partial;
-  u.max_items = update_max_items(N, K); u.ctl = c->w.ctl; u.gated = 0;
-  u.fx = fx_ok(K, d); u.xbound = c->w.xbound; u.fxpart = c->w.fxpart;
-  // bound of |x| for the fixed-point sums: part of preparing X, outside the
-  // phase times (a solve computes it once)
-  HIP_TRY(c, launch_xbound(u, st_), "bound of |x|");
-  // with timing on, the events take the times of the kernels' own dispatches
-  HIP_TRY(c, launch_assign(a, kRolePlain, st_, c->timing ? c->ta[0] : nullptr, c->timing ? c->tb[0] : nullptr),
-          "assignment");
-  const int grid = assign_grid(a);
-  HIP_TRY(c, launch_reduce_energy(c->w.e_part, grid, c->w.e_out, st_), "energy");
-  HIP_TRY(c, launch_update_sums(u, st_, c->timing ? c->ta[1] : nullptr), "update");
-  FinalizeArgs f{};
-  f.d = d; f.K = K; f.cap = 0; f.partial = c->w.partial; f.item_start = c->w.item_start;
-  f.counts = c->w.counts; f.C_in = C; f.C_out = C_out; f.ctl = c->w.ctl; f.mode = kFinG;
-  f.fx = u.fx; f.fxpart = c->w.fxpart; f.xbound = c->w.xbound; f.N = N;
-  f.C_cand = nullptr; f.C_fb = nullptr; f.G_last = nullptr; f.F_last = nullptr;
-  f.ring_dF = nullptr; f.ring_dG = nullptr; f.dots = nullptr;
-  HIP_TRY(c, launch_finalize(f, st_, c->timing ? c->tb[1] : nullptr), "finalize");
-  HIP_TRY(c, hipMemcpyAsync(c->scal_host, c->w.e_out, 8, hipMemcpyDeviceToHost, st_), "copy E");
-  HIP_TRY(c, hipMemcpyAsync(c->ctl_host, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st_), "copy ctl");
-  HIP_TRY(c, hipStreamSynchronize(st_), "hipStreamSynchronize");
-  *E = c->scal_host[0];
-  if (st) {
-    st->changed = rho_prev ? (int64_t)c->ctl_host->cnt_changed[0] : 0;
-    st->flagged_rows = (int64_t)c->ctl_host->cnt_flagged[0];
-    st->empty_clusters = c->ctl_host->empty;
-    st->assign_ms = st->update_ms = -1.f;
-    if (c->timing) {
-      if (hipEventElapsedTime(&st->assign_ms, c->ta[0], c->tb[0]) != hipSuccess ||
-          hipEventElapsedTime(&st->update_ms, c->ta[1], c->tb[1]) != hipSuccess) {
-        clear_pending_error();
-        st->assign_ms = st->update_ms = -1.f;
-      }
-    }
-  }
-  if (!isfinite(*E)) return fail(c, KM_ENONFINITE, "energy is not finite");
-  return KM_OK;
+  return g_run(c, c->w, X, xt, N, d, K, C, prec, rho_prev, rho, C_out, E, st);
 }
 
 km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
@@ -257,8 +292,18 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     return fail(c, KM_EINVAL, "outputs must not alias X or each other");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   const bool gbf = opt.prec == KM_GEMM_BF16;
+  // row bounds: float32 GEMM with the centroids resident in the kernel's LDS
+  bool bnd = false;
+  if (opt.flags & KM_FLAG_BOUNDS) {
+    AssignArgs t{};
+    t.N = N; t.d = d; t.K = K; t.xbf16 = xt == KM_X_BF16; t.gemm_bf16 = gbf;
+    t.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
+    bnd = assign_bounds_ok(t) != 0;
+  }
   Shape want;
   want.N = N; want.d = d; want.K = K; want.cap = m_max; want.bf = gbf;
+  want.it = opt.m_traj ? opt.max_iter + 1 : 0;
+  want.bnd = bnd ? 1 : 0;
   s = ensure_ws(c, want);
   if (s != KM_OK) return s;
   hipStream_t q = c->q;
@@ -291,6 +336,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   a.lab = c->w.labels; a.lab_prev = nullptr; a.e_part = c->w.e_part; a.flags = c->w.flags; a.ctl = c->w.ctl;
   a.xbf16 = xbf; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xbf, d, K);
+  a.lb = bnd ? c->w.lb : nullptr; a.C_ref = bnd ? c->w.C_ref : nullptr; a.bounds = 0;
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xbf;
   u.lab = c->w.labels; u.lab_from_ctl = 1; u.lrank = c->w.lrank; u.blockcount = c->w.blockcount;
@@ -305,6 +351,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   f.G_last = c->w.G_last; f.F_last = c->w.F_last; f.ring_dF = c->w.ring_dF; f.ring_dG = c->w.ring_dG;
   f.dots = c->w.dots; f.ctl = c->w.ctl; f.mode = kFinInit;
   f.fx = u.fx; f.fxpart = c->w.fxpart; f.xbound = c->w.xbound; f.N = N;
+  f.C_ref = bnd ? c->w.C_ref : nullptr;
   CombineArgs cb{};
   cb.ctl = c->w.ctl; cb.gated = 0; cb.G_last = c->w.G_last; cb.ring_dG = c->w.ring_dG;
   cb.K = K; cb.d = d; cb.cap = cap;
@@ -330,10 +377,10 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   if (grid <= 0) return fail(c, KM_EUNSUPPORTED, "no assignment kernel for this shape");
   AssignArgs ac = a;
   ac.C = c->w.C_cand; ac.nc = c->w.nc_cand; ac.Cb = gbf ? c->w.Cb_cand : nullptr;
-  ac.delta = gbf ? c->w.del_cand : nullptr; ac.e_part = c->w.e_part;
+  ac.delta = gbf ? c->w.del_cand : nullptr; ac.e_part = c->w.e_part; ac.bounds = bnd ? 1 : 0;
   AssignArgs af = a;
   af.C = c->w.C_fb; af.nc = c->w.nc_fb; af.Cb = gbf ? c->w.Cb_fb : nullptr;
-  af.delta = gbf ? c->w.del_fb : nullptr; af.e_part = c->w.e_part + grid;
+  af.delta = gbf ? c->w.del_fb : nullptr; af.e_part = c->w.e_part + grid; af.bounds = bnd ? 1 : 0;
   FinalizeArgs fi = f;
   fi.mode = kFinIter; fi.C_in = nullptr;
   CombineArgs ci = cb;
@@ -348,6 +395,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   k1.ctl = c->w.ctl; k1.e_part = c->w.e_part; k1.n_part = grid; k1.stage = 1;
   k1.tr.trace_C = opt.trace_C; k1.tr.trace_rec = opt.trace_rec; k1.tr.C_cand = c->w.C_cand;
   k1.tr.K = K; k1.tr.d = d;
+  k1.tr.m_traj = opt.m_traj ? c->w.m_traj : nullptr;
   CtlArgs k2 = k1;
   k2.e_part = c->w.e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
 
@@ -415,10 +463,14 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   HIP_TRY(c, hipMemcpyAsync(C_out, Cres, cbytes, hipMemcpyDeviceToDevice, q), "copy C");
   HIP_TRY(c, hipMemcpyAsync(rho_out, c->w.labels + (size_t)r.lab_prev * N, (size_t)N * 4,
                             hipMemcpyDeviceToDevice, q), "copy rho");
+  if (opt.m_traj && r.t > 0)
+    HIP_TRY(c, hipMemcpyAsync(opt.m_traj + 1, c->w.m_traj + 1, (size_t)r.t * 4, hipMemcpyDeviceToHost, q),
+            "copy m trajectory");
   HIP_TRY(c, hipEventRecord(c->t1, q), "hipEventRecord");
   HIP_TRY(c, hipStreamSynchronize(q), "hipStreamSynchronize");
   *E = r.E_acc;
   *iters = r.t;
+  if (opt.m_traj) opt.m_traj[0] = opt.m_init < m_max ? opt.m_init : m_max;
   if (st) {
     memset(st, 0, sizeof(*st));
     st->iters = r.t;
@@ -426,7 +478,10 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     st->rejected = r.rejected;
     st->assign_passes = r.assign_passes;
     st->m_final = r.m;
-    st->flagged_rows = (int64_t)r.flagged_total;
+    st->recheck_rows = (int64_t)r.flagged_total;
+    st->near_tie_rows = (int64_t)r.near_total;
+    st->gemm_rows = (int64_t)r.gemm_total + N;   // the prologue pass assigns every row
+    st->bounds = bnd ? 1 : 0;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->t0, c->t1) == hipSuccess) st->device_ms = ms;
     else clear_pending_error();

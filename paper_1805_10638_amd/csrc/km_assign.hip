@@ -28,7 +28,22 @@ KernelPick assign_pick(const AssignArgs& a) {
   if (ks < 0) return KernelPick();
   const int ov = shape_override();
   const int shape = ov >= 0 ? ov : a.shape;
-  return a.gemm_bf16 ? pick_bf16(ks, a.xbf16 != 0, a.K, shape) : pick_f32(ks, a.xbf16 != 0, a.K, shape);
+  KernelPick p = a.gemm_bf16 ? pick_bf16(ks, a.xbf16 != 0, a.K, shape) : pick_f32(ks, a.xbf16 != 0, a.K, shape);
+  // launches that keep row bounds run the bounds variant (more LDS: the row queues)
+  if (a.lb && p.fn_bnd && p.resident) {
+    p.fn = p.fn_bnd;
+    p.lds = p.lds_bnd;
+  }
+  return p;
+}
+
+int assign_bounds_ok(const AssignArgs& a) {
+  if (a.gemm_bf16) return 0;
+  const int ks = pick_ks(a.d, 0);
+  if (ks < 0) return 0;
+  const int ov = shape_override();
+  const KernelPick p = pick_f32(ks, a.xbf16 != 0, a.K, ov >= 0 ? ov : a.shape);
+  return (p.fn_bnd && p.resident) ? 1 : 0;
 }
 
 // Kernels whose LDS budget exceeds the default 64 KB must say so once.
@@ -39,7 +54,8 @@ static hipError_t allow_lds(const KernelPick& p) {
   for (int i = 0; i < n_done; ++i)
     if (done[i] == p.fn) return hipSuccess;
   hipError_t e = hipFuncSetAttribute(p.fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e == hipSuccess) e = hipFuncSetAttribute(p.fn_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess && p.fn_batch && p.fn_batch != p.fn)
+    e = hipFuncSetAttribute(p.fn_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
   if (n_done < 64) done[n_done++] = p.fn;
   return hipSuccess;

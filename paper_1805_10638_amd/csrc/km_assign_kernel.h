@@ -97,28 +97,95 @@ __device__ __forceinline__ void load_chunk(const void* X, int64_t i, int d, int 
   }
 }
 
-// Exact re-check of one flagged sample by the whole wave: float64 direct
-// differences to all K centroids, lowest index on ties.  Returns the label
-// (or -1 if every distance is NaN) and its distance in *dist.
-__device__ __forceinline__ int wave_argmin(double bd, int bj, double* dist) {
+// Wave reduction of per-lane (smallest distance bd, its index bj, second
+// smallest distance bd2): lowest index on ties; the second smallest counts a
+// second centroid at the smallest distance (then it equals the smallest).
+// Every lane returns the label (-1 if every distance is NaN), with the two
+// distances in *dist and *dist2.
+__device__ __forceinline__ int wave_argmin2(double bd, double bd2, int bj, double* dist, double* dist2) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const double ob = __shfl_xor(bd, off, kWave);
+    const double ob2 = __shfl_xor(bd2, off, kWave);
     const int oj = __shfl_xor(bj, off, kWave);
     const bool take = (ob < bd) || (ob == bd && (unsigned)oj < (unsigned)bj);
+    const double hi = bd < ob ? ob : bd, lo2 = bd2 < ob2 ? bd2 : ob2;
+    bd2 = hi < lo2 ? hi : lo2;
     bd = take ? ob : bd;
     bj = take ? oj : bj;
   }
   *dist = bd;
+  *dist2 = bd2;
   return bj;
+}
+
+// Running smallest / second smallest distance of a lane (indices ascend).
+__device__ __forceinline__ void keep_two(double s, int j, double& bd, double& bd2, int& bj) {
+  if (s < bd) { bd2 = bd; bd = s; bj = j; }
+  else if (s < bd2) bd2 = s;
+}
+
+// Near tie as the float64 oracle defines it: relative gap between the two
+// smallest squared distances below 1e-6, or both zero.
+__device__ __forceinline__ bool near_tie(double d1, double d2) {
+  return (d2 - d1) < 1e-6 * d2 || d2 == 0.0;
+}
+
+// Largest float32 not above v (v >= 0 or +inf).
+__device__ __forceinline__ float f32_down(double v) {
+  float f = (float)v;
+  if ((double)f > v) f = __uint_as_float(__float_as_uint(f) - 1u);
+  return f;
+}
+
+// A float32 lower bound of sqrt(l2) (0 when l2 is not positive).
+__device__ __forceinline__ float sqrt_down(double l2) {
+  if (!(l2 > 0.0)) return 0.f;
+  return f32_down(sqrt(l2) * (1.0 - 1e-15));
+}
+
+// Squared float64 distance between a sample and a centroid row, this lane's
+// KS dimensions (xe: the sample's, cr: the centroid's), summed over the four
+// lane groups: float64 differences of the float32 values, squares added in
+// dimension order, then lane groups 16 and 32 apart.  Every lane holds the
+// result.
+template <int KS>
+__device__ __forceinline__ double row_dist2(const float (&xe)[KS], const float* cr, int d, int g, bool vec) {
+  double p = 0.0;
+  bool done4 = false;
+  if constexpr (KS % 4 == 0) {
+    if (vec) {  // whole chunk real: 16-byte loads of the centroid row
+#pragma unroll
+      for (int q = 0; q < KS; q += 4) {
+        const float4 c4 = *(const float4*)(cr + q);
+        double df = (double)xe[q] - (double)c4.x; p = fma(df, df, p);
+        df = (double)xe[q + 1] - (double)c4.y; p = fma(df, df, p);
+        df = (double)xe[q + 2] - (double)c4.z; p = fma(df, df, p);
+        df = (double)xe[q + 3] - (double)c4.w; p = fma(df, df, p);
+      }
+      done4 = true;
+    }
+  }
+  if (!done4) {
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      if (g * KS + q < d) {
+        const double df = (double)xe[q] - (double)cr[q];
+        p = fma(df, df, p);
+      }
+    }
+  }
+  p += __shfl_xor(p, 16, kWave);
+  p += __shfl_xor(p, 32, kWave);
+  return p;
 }
 
 // Centroids resident in LDS (row stride ld, zero-padded to DP) and the
 // sample staged in LDS (xrow, zero-padded to DP).
 template <int DP>
 __device__ __forceinline__ int exact_argmin_lds(const float* xrow, const float* Cs, int ld, int K, int lane,
-                                             double* dist) {
-  double bd = __builtin_inf();
+                                             double* dist, double* dist2) {
+  double bd = __builtin_inf(), bd2 = __builtin_inf();
   int bj = -1;
   for (int j = lane; j < K; j += kWave) {
     const float* cr = Cs + j * ld;
@@ -139,9 +206,9 @@ __device__ __forceinline__ int exact_argmin_lds(const float* xrow, const float* 
         s = fma(df, df, s);
       }
     }
-    if (s < bd) { bd = s; bj = j; }
+    keep_two(s, j, bd, bd2, bj);
   }
-  return wave_argmin(bd, bj, dist);
+  return wave_argmin2(bd, bd2, bj, dist, dist2);
 }
 
 // LDS layout.  HEAD: workgroup scratch (maxima: 32 floats; energy partials:
@@ -163,7 +230,7 @@ struct Tile {
   static constexpr int ROW_BYTES = GBF ? LDB * 2 : LD * 4;
   static constexpr int HEAD = kAssignScratch + 16 * DP * 4;
   static constexpr int RX = DP <= 128 ? 16 : 8;        // rows per deferred re-check batch
-  static constexpr int DEF_FIXED = RX * DP * 8 + RX * 16 * 16;
+  static constexpr int DEF_FIXED = RX * DP * 8 + RX * 16 * 24;
   static constexpr int DEF_MIN = DEF_FIXED + 16 * LD * 4;
   // centroid rows per LDS chunk (multiple of 16) for a given K
   static __host__ __device__ int chunk_rows(int K) {
@@ -293,7 +360,7 @@ constexpr int assign_wpe() {
 // per workgroup (they share one LDS copy of the centroids); LB: LDS bytes.
 // bx / gx: this workgroup's index and the number of workgroups working on
 // this instance.
-template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
+template <int KS, int SB, int W, bool XBF, bool GBF, int LB, bool BND = false>
 __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx) {
   constexpr int NT = 64 * W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -318,6 +385,22 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     prev = a.lab_prev;
   }
   const int slot = (role == kRoleFallback) ? 1 : 0;
+  // row bounds: written for this pass's labels (lbo), read for the previous ones (lbi)
+  float* lbo = nullptr;
+  const float* lbi = nullptr;
+  if constexpr (BND) {
+    if (a.lb) {
+      if (role == kRoleCand) {
+        lbo = a.lb + (int64_t)ctl->lab_cand * a.N;
+        lbi = a.lb + (int64_t)ctl->lab_prev * a.N;
+      } else if (role == kRoleFallback) {
+        lbo = a.lb + (int64_t)ctl->lab_fb * a.N;
+        lbi = a.lb + (int64_t)ctl->lab_prev * a.N;
+      } else {
+        lbo = a.lb;
+      }
+    }
+  }
 
   const int d = a.d, K = a.K;
   const int Kpad = (K + 15) & ~15;
@@ -457,6 +540,54 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     stage(0, Kpad);
     __syncthreads();
   }
+  // Row bounds in use (candidate and fall-back passes, centroids resident):
+  // the largest and second largest centroid shift ||c_j - c_ref_j|| (upper
+  // bounds, float64) and the index of the largest.  A row whose previous
+  // label is j1 moved away from every other centroid by at most sm2, any
+  // other row by at most sm1.
+  const bool use_in = BND && lbi != nullptr && a.bounds && resident;
+  double sm1 = 0.0, sm2 = 0.0;
+  int sj1 = -1;
+  if constexpr (BND) {
+    if (use_in) {
+      double m1 = 0.0, m2 = 0.0;
+      int j1 = -1;
+      for (int j = tid; j < K; j += NT) {
+        const float* cr = Cs + j * LD;
+        const float* rr = a.C_ref + (int64_t)j * d;
+        double s2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double df = (double)cr[k] - (double)rr[k];
+          s2 = fma(df, df, s2);
+        }
+        const double sh = sqrt(s2) * (1.0 + 1e-12);
+        if (sh > m1) { m2 = m1; m1 = sh; j1 = j; }
+        else if (sh > m2) m2 = sh;
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double o1 = __shfl_xor(m1, off, kWave), o2 = __shfl_xor(m2, off, kWave);
+        const int oj = __shfl_xor(j1, off, kWave);
+        const double lo = o1 < m1 ? o1 : m1, hi2 = o2 > m2 ? o2 : m2;
+        m2 = lo > hi2 ? lo : hi2;
+        if (o1 > m1 || (o1 == m1 && (unsigned)oj < (unsigned)j1)) { m1 = o1; j1 = oj; }
+      }
+      double* t1 = dred;                        // W doubles
+      double* t2 = (double*)(smem_raw + 256);   // W doubles (the list-length slots, unused here)
+      int* tj = pw;                             // W ints
+      if (lane == 0) { t1[wave] = m1; t2[wave] = m2; tj[wave] = j1; }
+      __syncthreads();
+      for (int w = 0; w < W; ++w) {
+        const double o1 = t1[w], o2 = t2[w];
+        const int oj = tj[w];
+        const double lo = o1 < sm1 ? o1 : sm1, hi2 = o2 > sm2 ? o2 : sm2;
+        sm2 = lo > hi2 ? lo : hi2;
+        if (o1 > sm1 || (o1 == sm1 && (unsigned)oj < (unsigned)sj1)) { sm1 = o1; sj1 = oj; }
+      }
+      __syncthreads();
+      if (tid < 16) pw[tid] = 0;
+    }
+  }
   // Flagged rows.  With float32 centroids resident in LDS a wave re-checks a
   // row at once from the LDS copy (xrow: its staged row).  Otherwise each
   // wave appends the rows it flags to its own list, and the workgroup
@@ -475,7 +606,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   const int64_t groups = (a.N + group_rows - 1) / group_rows;
   const bool vec = (d == DP);
   double e_wave = 0.0;
-  unsigned n_changed = 0, n_flag = 0;
+  unsigned n_changed = 0, n_flag = 0, n_near = 0, n_gemm = 0;
   // float32 copy of the rows in registers only for the float32 GEMM; bf16 rows
   // are exact as bf16; float32 rows on the bf16 GEMM keep hi and lo (XLO)
   constexpr bool KF = !GBF;
@@ -505,7 +636,8 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   auto recheck_batches = [&](const int* wc, bool final) {
     double* xb = (double*)area;                          // RX x DP
     double* redd = (double*)(area + RX * DP * 8);        // RX x 16 waves
-    int* redj = (int*)(redd + RX * 16);                  // RX x 16 waves
+    double* redd2 = redd + RX * 16;                      // RX x 16 waves: second smallest
+    int* redj = (int*)(redd2 + RX * 16);                 // RX x 16 waves
     int* rowidx = redj + RX * 16;                        // RX
     double* rowdist = (double*)(rowidx + RX);            // RX
     float* cc = (float*)(area + T::DEF_FIXED);           // def_rows(K) x LD
@@ -534,10 +666,13 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
         if (u < rb && k < d) v = (double)ld_x(a.X, (int64_t)rowidx[u] * d + k, XBF);
         xb[e] = v;
       }
+      // second smallest distance per row kept in float32 (it only decides
+      // whether a re-checked row counts as a near tie), saving registers
       double bd[MR];
+      float bd2[MR];
       int bj[MR];
 #pragma unroll
-      for (int m = 0; m < MR; ++m) { bd[m] = __builtin_inf(); bj[m] = -1; }
+      for (int m = 0; m < MR; ++m) { bd[m] = __builtin_inf(); bd2[m] = __builtin_inff(); bj[m] = -1; }
       for (int c0 = 0; c0 < K; c0 += crows) {
         const int rows = (K - c0) < crows ? (K - c0) : crows;
         __syncthreads();
@@ -566,8 +701,11 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
               }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (acc[r] < bd[m0 + r]) { bd[m0 + r] = acc[r]; bj[m0 + r] = j; }
+            for (int r = 0; r < 4; ++r) {
+              const int m = m0 + r;
+              if (acc[r] < bd[m]) { bd2[m] = (float)bd[m]; bd[m] = acc[r]; bj[m] = j; }
+              else bd2[m] = fminf(bd2[m], (float)acc[r]);
+            }
           }
         }
       }
@@ -575,21 +713,23 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       for (int m = 0; m < MR; ++m) {
         const int u = rg + G * m;
         if (u < rb) {
-          double dist;
-          const int j = wave_argmin(bd[m], bj[m], &dist);
-          if (lane == 0) { redd[u * 16 + wave] = dist; redj[u * 16 + wave] = j; }
+          double dist, dist2;
+          const int j = wave_argmin2(bd[m], (double)bd2[m], bj[m], &dist, &dist2);
+          if (lane == 0) { redd[u * 16 + wave] = dist; redd2[u * 16 + wave] = dist2; redj[u * 16 + wave] = j; }
         }
       }
       __syncthreads();
-      bool ch = false;
+      bool ch = false, nt = false;
       if (tid < rb) {
         const int w0 = (tid % G) * (S / 64), w1 = w0 + S / 64;
-        double bdist = redd[tid * 16 + w0];
+        double bdist = redd[tid * 16 + w0], bdist2 = redd2[tid * 16 + w0];
         int bjj = redj[tid * 16 + w0];
         for (int w = w0 + 1; w < w1; ++w) {
-          const double od = redd[tid * 16 + w];
+          const double od = redd[tid * 16 + w], od2 = redd2[tid * 16 + w];
           const int oj = redj[tid * 16 + w];
           const bool take = (od < bdist) || (od == bdist && (unsigned)oj < (unsigned)bjj);
+          const double hi = bdist < od ? od : bdist, lo2 = bdist2 < od2 ? bdist2 : od2;
+          bdist2 = hi < lo2 ? hi : lo2;
           bdist = take ? od : bdist;
           bjj = take ? oj : bjj;
         }
@@ -597,9 +737,13 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
         const int jl = bjj >= 0 ? bjj : 0;
         rho[i] = jl;
         ch = (prev != nullptr) && (prev[i] != jl);
+        nt = near_tie(bdist, bdist2);
         rowdist[tid] = bdist;
       }
-      if (wave == 0) n_changed += (unsigned)__popcll(__ballot(ch));
+      if (wave == 0) {
+        n_changed += (unsigned)__popcll(__ballot(ch));
+        n_near += (unsigned)__popcll(__ballot(nt));
+      }
       __syncthreads();
       if (tid == 0) {
         for (int u = 0; u < rb; ++u) e_def += rowdist[u];
@@ -619,8 +763,16 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   // One unit of work of this wave: U 16-sample blocks from row row0 (U = SB
   // inside a row group; U = 1 for the single blocks that end a balanced
   // range).
-  auto unit = [&](auto ut, const int64_t row0) {
+  auto unit = [&](auto ut, const int64_t row0, const int* qrows, const int qcnt) {
     constexpr int U = decltype(ut)::value;
+    // rows of the unit: consecutive from row0, or the first qcnt entries of
+    // an LDS queue (positions past qcnt are not rows: index N)
+    int64_t ii[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+      if (qrows) ii[s] = (16 * s + r16 < qcnt) ? (int64_t)qrows[16 * s + r16] : a.N;
+      else ii[s] = row0 + 16 * s + r16;
+    }
     // Sample rows of this wave, kept in registers.
     float xv[U][KF ? KS : 1];
     i16x8 xbv[U][NB];
@@ -629,7 +781,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
 #pragma unroll
     for (int s = 0; s < U; ++s) {
       xres[s] = 0.f;
-      const int64_t i = row0 + 16 * s + r16;
+      const int64_t i = ii[s];
       if constexpr (GBF && XBF) {
         const uint16_t* xr = (const uint16_t*)a.X + i * d + g * KS;
 #pragma unroll
@@ -733,9 +885,10 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     int bi_s[U];
     bool fl_s[U];
     double term_s[U];
+    double l2_s[BND ? U : 1];   // squared lower bound of the distance to every other centroid
 #pragma unroll
     for (int s = 0; s < U; ++s) {
-      const int64_t i = row0 + 16 * s + r16;
+      const int64_t i = ii[s];
       const bool valid = i < a.N;
       float b = best[s], sc = sec[s];
       int bi = bidx[s] + 4 * g;
@@ -790,40 +943,31 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       } else {
         bound = gam * (nx + cmax) * (nx + cmax);
       }
-      const bool flag = valid && !((b - sc) > bound);
+      // Re-check when the gap is within the bound, or so small that the row
+      // could be a float64 near tie: a gap above bound/2 + 5.1e-7 (|x| +
+      // max|c|)^2 leaves an exact squared-distance gap above 1.02e-6
+      // (|x| + max|c|)^2, at least 1.02e-6 times the second distance, so
+      // every near tie is among the re-checked rows (and counted there).
+      const float nb2 = (nx + cb) * (nx + cb);
+      const float thr = fmaxf(bound, 0.5f * bound + 5.1e-7f * nb2);
+      const bool flag = valid && !((b - sc) > thr);
+      // Lower bound for the row bounds: every other centroid j has exact score
+      // s_j <= sc + e with e <= bound / 4, so its squared distance is at least
+      // ||x||^2 - 2 sc - bound / 2; taken with a factor 2 of margin, and
+      // ||x||^2 in float64 less 1e-12 of itself for its rounding.
+      double l2 = 0.0;
+      if constexpr (BND) {
+        double x2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) x2 = fma((double)xe[q], (double)xe[q], x2);
+        x2 += __shfl_xor(x2, 16, kWave);
+        x2 += __shfl_xor(x2, 32, kWave);
+        l2 = x2 * (1.0 - 1e-12) - 2.0 * (double)sc - (double)bound;
+      }
 
       // exact energy term of the provisional label
-      double term;
-      {
-        const float* cr = (resident && !GBF) ? Cs + bi * LD + g * KS : a.C + (int64_t)bi * d + g * KS;
-        double p = 0.0;
-        bool done4 = false;
-        if constexpr (KS % 4 == 0) {
-          if (vec) {  // whole chunk real: 16-byte loads of the centroid row
-#pragma unroll
-            for (int q = 0; q < KS; q += 4) {
-              const float4 c4 = *(const float4*)(cr + q);
-              double df = (double)xe[q] - (double)c4.x; p = fma(df, df, p);
-              df = (double)xe[q + 1] - (double)c4.y; p = fma(df, df, p);
-              df = (double)xe[q + 2] - (double)c4.z; p = fma(df, df, p);
-              df = (double)xe[q + 3] - (double)c4.w; p = fma(df, df, p);
-            }
-            done4 = true;
-          }
-        }
-        if (!done4) {
-#pragma unroll
-          for (int q = 0; q < KS; ++q) {
-            if (g * KS + q < d) {
-              const double df = (double)xe[q] - (double)cr[q];
-              p = fma(df, df, p);
-            }
-          }
-        }
-        p += __shfl_xor(p, 16, kWave);
-        p += __shfl_xor(p, 32, kWave);
-        term = p;
-      }
+      double term = row_dist2<KS>(xe, (resident && !GBF) ? Cs + bi * LD + g * KS : a.C + (int64_t)bi * d + g * KS,
+                                  d, g, vec);
 
       unsigned long long fm = __ballot(flag) & 0xFFFFull;
       n_flag += (unsigned)__popcll(fm);
@@ -849,34 +993,127 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          double dist;
-          const int j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist);
+          double dist, dist2;
+          const int j = exact_argmin_lds<DP>(xrow, Cs, LD, K, lane, &dist, &dist2);
+          n_near += near_tie(dist, dist2) ? 1u : 0u;   // the same on every lane
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          if (j >= 0 && r16 == f) { bi = j; term = dist; }
+          if (j >= 0 && r16 == f) {
+            bi = j;
+            term = dist;
+            if constexpr (BND) l2 = dist2 * (1.0 - 1e-12);
+          }
         }
       }
       bi_s[s] = bi;
       term_s[s] = term;
       fl_s[s] = listed && flag;
+      if constexpr (BND) l2_s[s] = listed ? 0.0 : l2;
     }
 
     double e_lane = 0.0;
 #pragma unroll
     for (int s = 0; s < U; ++s) {
-      const int64_t i = row0 + 16 * s + r16;
+      const int64_t i = ii[s];
       const bool valid = i < a.N;
       const bool mine = valid && g == 0 && !fl_s[s];   // deferred rows are written later
       bool ch = false;
       if (mine) {
         rho[i] = bi_s[s];
         ch = (prev != nullptr) && (prev[i] != bi_s[s]);
+        if constexpr (BND) {
+          if (lbo) lbo[i] = sqrt_down(l2_s[s]);
+        }
+      }
+      if constexpr (BND) {   // listed rows get no bound (they are re-checked later)
+        if (lbo && valid && g == 0 && fl_s[s]) lbo[i] = 0.f;
       }
       n_changed += (unsigned)__popcll(__ballot(ch));
+      n_gemm += (unsigned)__popcll(__ballot(valid && g == 0));
       e_lane += mine ? term_s[s] : 0.0;
     }
     e_wave += wave_sum(e_lane);
+  };
+
+  // Bounds pass over blocks [b, b1) of this wave (row bounds in use): each
+  // row's exact float64 distance d1 to the new centroid of its previous
+  // label is compared with its bound lp = lb - (largest shift of another
+  // centroid).  Every other centroid is then at least lp away, so if
+  // d1 (1 + 2.1e-6) < lp^2 the previous label is the exact argmin, by a
+  // relative margin wider than a near tie: the row keeps its label, its
+  // energy term is d1 and its bound lp.  The other rows are queued in LDS
+  // (in row order) and go through the distance GEMM in units of SB blocks,
+  // the rest in single blocks.
+  auto bounds_pass = [&](int64_t b, const int64_t b1) {
+    if constexpr (BND) {
+      int* q = (int*)(smem_raw + T::lds_bytes(K)) + wave * (32 * SB);
+      int nq = 0;
+      double e_skip = 0.0;
+      auto wave_sync = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      };
+      // drop the first `used` entries of the queue (fewer than 64 remain)
+      auto consume = [&](int used) {
+        const int rest = nq - used;
+        wave_sync();
+        const int v = lane < rest ? q[used + lane] : 0;
+        wave_sync();
+        if (lane < rest) q[lane] = v;
+        wave_sync();
+        nq = rest;
+      };
+      for (; b < b1; b += SB) {
+        float xr[SB][KS];
+        int ar[SB];
+        float lr[SB];
+        int64_t ir[SB];
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+          const int64_t i = (b + s) * 16 + r16;
+          const bool valid = b + s < b1 && i < a.N;
+          ir[s] = valid ? i : a.N;
+          if (valid) {
+            load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xr[s]);
+          } else {
+#pragma unroll
+            for (int q2 = 0; q2 < KS; ++q2) xr[s][q2] = 0.f;
+          }
+          ar[s] = valid ? prev[i] : 0;
+          lr[s] = valid ? lbi[i] : 0.f;
+        }
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+          const bool valid = ir[s] < a.N;
+          const int la = (ar[s] >= 0 && ar[s] < K) ? ar[s] : 0;
+          const double d1 = row_dist2<KS>(xr[s], Cs + la * LD + g * KS, d, g, vec);
+          const double lp = (double)lr[s] - (la == sj1 ? sm2 : sm1);
+          const bool skip = valid && lp > 0.0 && d1 * (1.0 + 2.1e-6) < lp * lp * (1.0 - 1e-9);
+          if (skip && g == 0) {
+            rho[ir[s]] = la;
+            lbo[ir[s]] = f32_down(lp * (1.0 - 1e-15));
+            e_skip += d1;
+          }
+          const bool act = valid && !skip && g == 0;
+          const unsigned long long am = __ballot(act);
+          if (act) q[nq + __popcll(am & ((1ull << r16) - 1ull))] = (int)ir[s];
+          nq += (int)__popcll(am);
+        }
+        wave_sync();
+        if (nq >= 16 * SB) {
+          unit(std::integral_constant<int, SB>{}, 0, q, 16 * SB);
+          consume(16 * SB);
+        }
+      }
+      while (nq > 0) {
+        const int c = nq < 16 ? nq : 16;
+        unit(std::integral_constant<int, 1>{}, 0, q, c);
+        consume(c);
+      }
+      e_wave += wave_sum(e_skip);
+    }
   };
 
   int nb = 0;   // row-group boundaries passed (selects the wc buffer)
@@ -893,12 +1130,21 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     const int64_t GW = (int64_t)gx * W, gw = (int64_t)bx * W + wave;
     const int64_t b1 = (gw + 1) * nblk / GW;
     int64_t b = gw * nblk / GW;
-    for (; b + SB <= b1; b += SB) unit(std::integral_constant<int, SB>{}, b * 16);
-    if constexpr (SB > 1)
-      for (; b < b1; ++b) unit(std::integral_constant<int, 1>{}, b * 16);
+    bool filtered = false;
+    if constexpr (BND) {
+      if (use_in) {
+        bounds_pass(b, b1);
+        filtered = true;
+      }
+    }
+    if (!filtered) {
+      for (; b + SB <= b1; b += SB) unit(std::integral_constant<int, SB>{}, b * 16, nullptr, 0);
+      if constexpr (SB > 1)
+        for (; b < b1; ++b) unit(std::integral_constant<int, 1>{}, b * 16, nullptr, 0);
+    }
   } else {
     for (int64_t grp = bx; grp < groups; grp += gx) {
-      unit(std::integral_constant<int, SB>{}, grp * group_rows + (int64_t)wave * (16 * SB));
+      unit(std::integral_constant<int, SB>{}, grp * group_rows + (int64_t)wave * (16 * SB), nullptr, 0);
       // With streamed centroids the chunk area is free here: re-check full
       // batches now, so that the re-check overlaps other workgroups' MFMA work
       // instead of piling up after the last row group (bf16 GEMM kernels; in
@@ -924,6 +1170,8 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     dred[wave] = e_wave;
     if (n_changed) atomicAdd(&ctl->cnt_changed[slot], (unsigned long long)n_changed);
     if (n_flag) atomicAdd(&ctl->cnt_flagged[slot], (unsigned long long)n_flag);
+    if (n_near) atomicAdd(&ctl->cnt_near[slot], (unsigned long long)n_near);
+    if (n_gemm) atomicAdd(&ctl->cnt_gemm[slot], (unsigned long long)n_gemm);
   }
   __syncthreads();
   if (tid == 0) {
@@ -940,6 +1188,14 @@ void k_assign(AssignArgs a) {
   assign_body<KS, SB, W, XBF, GBF, LB>(a, blockIdx.x, gridDim.x);
 }
 
+// Single instance with row bounds (float32 GEMM; the bounds are used when the
+// centroids are resident in LDS, which the host ensures).
+template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(assign_wpe<KS, SB, W, XBF, GBF>())))
+void k_assign_bnd(AssignArgs a) {
+  assign_body<KS, SB, W, XBF, GBF, LB, true>(a, blockIdx.x, gridDim.x);
+}
+
 // Batched launch: the grid is the concatenation of every instance's slice.
 template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(assign_wpe<KS, SB, W, XBF, GBF>())))
@@ -953,6 +1209,9 @@ void k_assign_batch(BatchRef<AssignArgs> t) {
 struct KernelPick {
   const void* fn = nullptr;        // k_assign
   const void* fn_batch = nullptr;  // k_assign_batch
+  const void* fn_bnd = nullptr;    // k_assign_bnd (float32 GEMM only)
+  bool resident = false;           // the K centroids fit the LDS budget at once
+  size_t lds_bnd = 0;              // LDS bytes of k_assign_bnd (lds + the row queues)
   int rows = 0;                    // samples per row group (16 * SB * W)
   int threads = 0;                 // 64 * W
   int lb = 0;                      // LDS budget (bytes)
@@ -968,6 +1227,11 @@ KernelPick make_pick(int K) {
   p.threads = 64 * W;
   p.lb = LB;
   p.lds = Tile<KS, GBF, LB>::lds_bytes(K);
+  p.resident = Tile<KS, GBF, LB>::chunk_rows(K) >= ((K + 15) & ~15);
+  if constexpr (!GBF) {
+    p.fn_bnd = (const void*)&k_assign_bnd<KS, SB, W, XBF, GBF, LB>;
+    p.lds_bnd = p.lds + (size_t)W * 32 * SB * 4;
+  }
   return p;
 }
 

@@ -89,8 +89,12 @@ struct Ctl {
   double E1, E2;           // accepted energies E^{t-1}, E^{t-2}
   double E_cand, E_fb, E_acc;
   unsigned long long cnt_changed[2];   // [candidate/plain, fall-back]
-  unsigned long long cnt_flagged[2];
+  unsigned long long cnt_flagged[2];   // rows re-checked in float64
   unsigned long long flagged_total;
+  unsigned long long cnt_near[2];      // re-checked rows that are float64 near ties
+  unsigned long long near_total;
+  unsigned long long cnt_gemm[2];      // rows that went through the distance GEMM (not skipped by bounds)
+  unsigned long long gemm_total;
   double theta[kMaxM];
 };
 

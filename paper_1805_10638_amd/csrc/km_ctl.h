@@ -20,6 +20,7 @@ namespace km {
 struct CtlTrace {
   float* trace_C;         // (max_iter + 1) x K x d, or null
   double* trace_rec;      // (max_iter + 1) x kTraceRec, or null
+  int* m_traj;            // (max_iter + 1) ints: m after the dynamic-m rule at iteration t, or null
   const float* C_cand;    // candidate centroids (copied into trace_C)
   int K, d;
 };
@@ -56,10 +57,15 @@ __device__ inline void controller_decide(Ctl* c, double E, int stage, int t_next
     const unsigned long long changed = c->cnt_changed[0];
     c->assign_passes += 1;
     c->flagged_total += c->cnt_flagged[0];
+    c->near_total += c->cnt_near[0];
+    c->gemm_total += c->cnt_gemm[0];
     if (rec) {
       rec[0] = t_next; rec[1] = E; rec[2] = (double)changed; rec[10] = (double)c->cnt_flagged[0];
+      rec[12] = (double)c->cnt_near[0];
+      rec[13] = (double)c->cnt_gemm[0];
       rec[3] = c->m;
     }
+    if (tr.m_traj) tr.m_traj[t_next] = c->m;
     if (!isfinite(E)) {
       c->E_acc = E;
       ctl_finish(c, -5, false, rec, kStopNonFinite);
@@ -78,11 +84,14 @@ __device__ inline void controller_decide(Ctl* c, double E, int stage, int t_next
       else if (num > c->eps2 * den) c->m = c->m + 1 < c->m_max ? c->m + 1 : c->m_max;
     }
     if (rec) rec[3] = c->m;
+    if (tr.m_traj) tr.m_traj[t_next] = c->m;
     const bool reject = !c->cand_is_lloyd && (same || E >= c->E1);
     c->reject = reject ? 1 : 0;
     if (reject) {
       c->cnt_changed[1] = 0;
       c->cnt_flagged[1] = 0;
+      c->cnt_near[1] = 0;
+      c->cnt_gemm[1] = 0;
     }
     return;
   }
@@ -96,6 +105,8 @@ __device__ inline void controller_decide(Ctl* c, double E, int stage, int t_next
     const unsigned long long changed = c->cnt_changed[1];
     c->assign_passes += 1;
     c->flagged_total += c->cnt_flagged[1];
+    c->near_total += c->cnt_near[1];
+    c->gemm_total += c->cnt_gemm[1];
     c->rejected += 1;
     c->E_acc = E;
     if (rec) { rec[4] = kDecRejected; rec[5] = E; rec[6] = (double)changed; rec[7] = E; }
@@ -121,6 +132,8 @@ __device__ inline void controller_decide(Ctl* c, double E, int stage, int t_next
   c->E1 = Ea;
   c->cnt_changed[0] = 0;
   c->cnt_flagged[0] = 0;
+  c->cnt_near[0] = 0;
+  c->cnt_gemm[0] = 0;
 }
 
 // red: 256 doubles of LDS.  Must be called by all 256 threads of the group.

@@ -56,7 +56,8 @@ struct Job {
   int64_t ticket = 0;
   Shape shape;
   bool gbf = false, xbf = false;
-  size_t bytes = 0;
+  size_t bytes = 0;       // workspace (allocated at admission)
+  size_t footprint = 0;   // what the HBM budget counts: workspace + X + C0 + C_out + labels
   void* mem = nullptr;
   Ws w;
   KernelPick pick;
@@ -400,7 +401,7 @@ km_status rebuild(km_engine* e, bool drain) {
       if (j->mem) {
         ENG_TRY(e, hipFreeAsync(j->mem, e->q), "hipFreeAsync");
         j->mem = nullptr;
-        e->used -= (int64_t)j->bytes;
+        e->used -= (int64_t)j->footprint;
       }
       if (j->taken) free_job(j);
     }
@@ -415,7 +416,7 @@ km_status rebuild(km_engine* e, bool drain) {
   std::vector<Job*> admitted;
   while (!e->queued.empty() && e->active.size() + admitted.size() < kDoneCap) {
     Job* j = e->queued.front();
-    if (e->budget > 0 && e->used + (int64_t)j->bytes > e->budget) break;
+    if (e->budget > 0 && e->used + (int64_t)j->footprint > e->budget) break;
     e->queued.pop_front();
     hipError_t he = hipMallocAsync(&j->mem, j->bytes, e->q);
     if (he != hipSuccess) {
@@ -426,7 +427,7 @@ km_status rebuild(km_engine* e, bool drain) {
       break;
     }
     ENG_TRY(e, hipMemsetAsync(j->mem, 0, j->bytes, e->q), "hipMemsetAsync");
-    e->used += (int64_t)j->bytes;
+    e->used += (int64_t)j->footprint;
     ws_layout(j->shape, (char*)j->mem, &j->w);
     j->state = kActive;
     admitted.push_back(j);
@@ -625,10 +626,10 @@ km_status harvest(km_engine* e, std::pair<int, int> it) {
   // a queued job that fits only once finished jobs are freed needs a drain
   bool admit_after_free = false;
   if (!e->queued.empty() && e->budget > 0 &&
-      e->used + (int64_t)e->queued.front()->bytes > e->budget) {
+      e->used + (int64_t)e->queued.front()->footprint > e->budget) {
     int64_t freed = 0;
-    for (Job* j : e->active) if (j->done_dev) freed += (int64_t)j->bytes;
-    admit_after_free = e->used - freed + (int64_t)e->queued.front()->bytes <= e->budget;
+    for (Job* j : e->active) if (j->done_dev) freed += (int64_t)j->footprint;
+    admit_after_free = e->used - freed + (int64_t)e->queued.front()->footprint <= e->budget;
   }
   if (live == 0 || admit_after_free || (done_in_tables > 0 && done_in_tables * 4 >= e->n_it) ||
       (!e->queued.empty() && (size_t)e->n_it >= kDoneCap))
@@ -639,7 +640,7 @@ km_status harvest(km_engine* e, std::pair<int, int> it) {
 // A queued job can join without a drain.
 bool can_append(const km_engine* e) {
   if (e->queued.empty() || (size_t)e->active.size() >= kDoneCap) return false;
-  return e->budget <= 0 || e->used + (int64_t)e->queued.front()->bytes <= e->budget;
+  return e->budget <= 0 || e->used + (int64_t)e->queued.front()->footprint <= e->budget;
 }
 
 void collect(km_engine* e) {
@@ -660,7 +661,8 @@ void collect(km_engine* e) {
     o.rejected = r.rejected;
     o.assign_passes = r.assign_passes;
     o.m_final = r.m;
-    o.flagged_rows = (int64_t)r.flagged_total;
+    o.recheck_rows = (int64_t)r.flagged_total;
+    o.near_tie_rows = (int64_t)r.near_total;
     o.latency_ms = now_ms() - j->t_submit;
     j->state = kReady;
     e->ready.push_back(j);
@@ -687,7 +689,7 @@ km_status km_engine_create(km_ctx* c, int32_t m_max, double tol, const km_opts* 
   if (opt.max_iter < 1 || opt.m_init < 0) return fail(c, KM_EINVAL, "max_iter must be >= 1 and m_init >= 0");
   if (!(opt.ridge >= 0.0) || !isfinite(opt.ridge) || !isfinite(opt.eps1) || !isfinite(opt.eps2))
     return fail(c, KM_EINVAL, "eps1, eps2 and ridge must be finite (ridge >= 0)");
-  if (opt.trace_C || opt.trace_rec) return fail(c, KM_EINVAL, "the engine does not trace");
+  if (opt.trace_C || opt.trace_rec || opt.m_traj) return fail(c, KM_EINVAL, "the engine does not trace");
   if (hbm_budget < 0) return fail(c, KM_EINVAL, "hbm_budget must be >= 0");
   if (hipSetDevice(c->device) != hipSuccess) return hip_fail(c, hipGetLastError(), "hipSetDevice");
   km_engine* e = new km_engine();
@@ -764,9 +766,11 @@ km_status km_engine_submit(km_engine* e, const km_job* job, int64_t* ticket) {
   j->xbf = job->xt == KM_X_BF16;
   j->shape = job_shape(*job, e->m_max, gbf);
   j->bytes = ws_layout(j->shape, nullptr, nullptr);
-  if (e->budget > 0 && (int64_t)j->bytes > e->budget) {
+  j->footprint = j->bytes + xbytes + 2 * cbytes + (size_t)job->N * 4;
+  if (e->budget > 0 && (int64_t)j->footprint > e->budget) {
     delete j;
-    return fail(c, KM_ENOMEM, "the job's workspace alone exceeds the HBM budget");
+    return fail(c, KM_ENOMEM, "the job's device memory (workspace, X, centroids, labels) alone exceeds the HBM "
+                              "budget");
   }
   AssignArgs probe{};
   probe.N = job->N; probe.d = job->d; probe.K = job->K; probe.xbf16 = j->xbf; probe.gemm_bf16 = gbf;

@@ -28,7 +28,19 @@ struct AssignArgs {
   int gemm_bf16;          // distance GEMM in bfloat16
   int role;               // Role of the launch (set by launch_assign / the batch tables)
   int shape;              // tile shape id (0 = default)
+  // Row bounds (Hamerly-style, float32 GEMM with LDS-resident centroids only;
+  // null / 0 elsewhere).  lb: lower bounds of the distance from each row to
+  // every centroid other than its own, 3 x N (one slice per label buffer;
+  // the plain role writes slice 0).  C_ref: the centroids the bounds of the
+  // previous labels refer to.  bounds = 1: candidate and fall-back passes
+  // skip the rows whose bound proves the previous label.
+  float* lb;
+  const float* C_ref;
+  int bounds;
 };
+// 1 if launches for a's shape can keep row bounds (float32 GEMM, centroids
+// resident in LDS); the solver enables them only then.
+int assign_bounds_ok(const AssignArgs& a);
 int assign_grid(const AssignArgs& a);   // workgroups of one launch (persistent grid)
 // ev0 / ev1 (nullable): events that take the start and end time of this
 // launch's own dispatch (no separate event record on the stream).
@@ -128,6 +140,8 @@ struct FinalizeArgs {
   const unsigned long long* fxpart;
   const unsigned* xbound;
   int64_t N;
+  float* C_ref;           // nullable: receives the accepted centroids (kFinInit: C_in), the
+                          // reference of the next pass's row bounds
 };
 // workgroups of the finalisation (and rows of Gram partials it writes)
 int finalize_grid(int64_t KD);                // counting-sort path

@@ -728,6 +728,7 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs& f, int bx, int
       continue;
     }
     const double cin = (f.mode == kFinInit) ? (double)f.C_in[e] : (double)Cacc[e];
+    if (f.C_ref) f.C_ref[e] = (float)cin;   // exact: cin is a float32 value
     const double gv = n > 0 ? sum / (double)n : cin;
     const double fv = gv - cin;
     if (f.mode == kFinIter && cap > 0) {
@@ -871,6 +872,7 @@ __device__ __forceinline__ void fxfinal_body(const FinalizeArgs& f, int bx) {
       f.C_out[e] = (float)(n > 0 ? sum / (double)n : cin);
       return;
     }
+    if (f.C_ref) f.C_ref[e] = (float)cin;   // exact: cin is a float32 value
     const double gv = n > 0 ? sum / (double)n : cin;
     fv = gv - cin;
     if (f.mode == kFinIter && cap > 0) {

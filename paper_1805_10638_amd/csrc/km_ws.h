@@ -16,8 +16,10 @@ inline size_t ws_up(size_t v) { return (v + kWsAlign - 1) & ~(kWsAlign - 1); }
 struct Shape {
   int64_t N = 0;
   int d = 0, K = 0, cap = 0, bf = 0;
+  int it = 0;   // entries of the m trajectory (max_iter + 1 when requested)
+  int bnd = 0;  // row bounds kept (3 x N lower bounds and the reference centroids)
   bool fits(const Shape& o) const {
-    return N >= o.N && d >= o.d && K >= o.K && cap >= o.cap && bf >= o.bf &&
+    return N >= o.N && d >= o.d && K >= o.K && cap >= o.cap && bf >= o.bf && it >= o.it && bnd >= o.bnd &&
            (int64_t)K * d >= (int64_t)o.K * o.d;
   }
 };
@@ -56,6 +58,9 @@ struct Ws {
   float* del_cand = nullptr;
   float* del_fb = nullptr;
   float* del_tmp = nullptr;
+  int* m_traj = nullptr;        // it ints (m after the dynamic-m rule per iteration)
+  float* lb = nullptr;          // 3 x N row bounds (bnd only)
+  float* C_ref = nullptr;       // K x d reference centroids of the row bounds (bnd only)
   int max_items = 0, nblk = 0, fin_grid = 0;
 };
 
@@ -102,6 +107,9 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const size_t o_dc = take(s.bf ? s.K * 4 : 0);
   const size_t o_df = take(s.bf ? s.K * 4 : 0);
   const size_t o_dtmp = take(s.bf ? s.K * 4 : 0);
+  const size_t o_mt = take((size_t)s.it * 4);
+  const size_t o_lb = take(s.bnd ? (size_t)3 * N * 4 : 0);
+  const size_t o_cr = take(s.bnd ? (size_t)KD * 4 : 0);
   if (base && w) {
     char* b = base;
     w->ctl = (Ctl*)(b + o_ctl);
@@ -137,6 +145,9 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
     w->del_cand = s.bf ? (float*)(b + o_dc) : nullptr;
     w->del_fb = s.bf ? (float*)(b + o_df) : nullptr;
     w->del_tmp = s.bf ? (float*)(b + o_dtmp) : nullptr;
+    w->m_traj = s.it ? (int*)(b + o_mt) : nullptr;
+    w->lb = s.bnd ? (float*)(b + o_lb) : nullptr;
+    w->C_ref = s.bnd ? (float*)(b + o_cr) : nullptr;
     w->max_items = max_items;
     w->nblk = nblk;
     w->fin_grid = fin_grid;
@@ -145,3 +156,4 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
 }
 
 }  // namespace km
+

@@ -187,13 +187,14 @@ def test_engine_served_against_oracle():
 
 
 def test_engine_budget_admission():
-    """With a budget of about two workspaces, jobs wait for room; the device
-    never holds more than the budget."""
+    """With a budget of about two jobs' device memory, jobs wait for room;
+    the device never holds more than the budget."""
     km = _lib()
     probs = _problems([(6000, 16, 40)] * 5, seed0=300)
     ts = [(x_tensor(x), dev(c)) for x, c in probs]
     probe = km.Engine(m_max=10, tol=1e-6)
-    ws = probe.workspace_bytes(ts[0][0], 40)
+    # the budget counts each job's workspace plus its X, C0, C_out and labels
+    ws = probe.workspace_bytes(ts[0][0], 40) + 6000 * 16 * 4 + 2 * 40 * 16 * 4 + 6000 * 4
     probe.close()
     budget = int(2.5 * ws)
     eng = km.Engine(m_max=10, tol=1e-6, hbm_budget=budget, graphs=True)

@@ -39,7 +39,7 @@ def test_g_parity_f32(N, d, K):
     C = synth.init_centroids(X, K, seed=K) + np.float32(0.25)
     rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C))
     r = check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
-    assert st.flagged_rows >= 0
+    assert st.recheck_rows >= 0
     assert r["max_c_err"] <= 1e-5
 
 
@@ -74,7 +74,8 @@ def test_g_exact_ties_lowest_index():
     rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C))
     a = ko.assign(X.astype(np.float64), C.astype(np.float64))
     assert np.array_equal(rho.cpu().numpy(), a.rho)
-    assert st.flagged_rows > 0
+    assert st.recheck_rows > 0
+    assert st.near_tie_rows == int(a.near_tie.sum()) == 120
 
 
 def test_g_cancellation_heavy_offsets():
@@ -86,8 +87,31 @@ def test_g_cancellation_heavy_offsets():
     C = X[rng.choice(4000, 50, replace=False)].copy()
     rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C))
     r = check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
-    assert st.flagged_rows > 0
+    assert st.recheck_rows > 0
     assert r["mismatch"] <= r["near_ties"]
+    assert st.near_tie_rows == r["near_ties"]
+
+
+@pytest.mark.parametrize("N,d,K,prec,xbf", [(3000, 16, 20, "f32", False), (2500, 5, 12, "f32", False),
+                                            (4000, 64, 300, "f32", False), (3000, 128, 40, "bf16", True),
+                                            (2000, 32, 600, "bf16", False), (5000, 2, 9, "f32", False)])
+def test_g_near_tie_count_matches_oracle(N, d, K, prec, xbf):
+    """Duplicated centroids make every sample nearest to them an exact tie;
+    the GPU's near-tie count equals the oracle's (every near tie is among
+    the re-checked rows, whatever the GEMM precision or width)."""
+    km = _lib()
+    if xbf:
+        X, _ = synth.precision(rep=3, n=N, d=d, k=max(2, K // 2))
+    else:
+        X = _mixture(N, d, K, seed=N + K)
+    C = synth.init_centroids(X, K, seed=4)
+    C[K - 1] = C[0]
+    C[K - 2] = C[1]
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C), prec=prec)
+    r = check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
+    assert r["near_ties"] > 0
+    assert st.near_tie_rows == r["near_ties"]
+    assert st.recheck_rows >= st.near_tie_rows
 
 
 def test_g_k1_and_k_equals_n():
@@ -224,7 +248,7 @@ def test_g_many_flags_streamed_centroids(prec):
     C = synth.init_centroids(X, 300, seed=3)
     rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C), prec=prec)
     r = check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
-    assert st.flagged_rows > 1000
+    assert st.recheck_rows > 1000
     assert r["mismatch"] <= r["near_ties"]
 
 

@@ -39,7 +39,7 @@ def _labels_match(rho_gpu, X64, C64):
 def lockstep(X, C0, m_max, tol, max_iter=500, **kw):
     km = _km()
     C, rho, E, iters, st, tr = km.kmeans_solve(x_tensor(X), dev(C0), m_max=m_max, tol=tol,
-                                               max_iter=max_iter, trace=True, **kw)
+                                               max_iter=max_iter, trace=True, m_traj=True, **kw)
     Ctr = tr["C"].cpu().numpy().astype(np.float64)
     rec = tr["rec"].cpu().numpy()
     X64 = x_values(X)
@@ -54,6 +54,9 @@ def lockstep(X, C0, m_max, tol, max_iter=500, **kw):
                    replay=lambda t: Ctr[t] if t <= iters else None,
                    stored=lambda G: G.astype(np.float32), **oracle_kw)
     assert res.iters == iters, (res.iters, iters)
+    # m trajectory returned by the solver: initial m, then m after the rule of every iteration
+    assert len(st.m_traj) == iters + 1
+    assert st.m_traj[0] == min(kw.get("m_init", 2), m_max)
     near_decisions = 0
     for r in res.trace:
         t = r["t"]
@@ -61,6 +64,9 @@ def lockstep(X, C0, m_max, tol, max_iter=500, **kw):
         assert g[0] == t
         assert g[1] == pytest.approx(r["E_cand"], rel=1e-9)
         assert int(g[2]) == r["changed_cand"]
+        # near ties of the candidate pass: the GPU counts them among its re-checked rows
+        assert int(g[12]) == r["cand_near_ties"], (t, g[12], r["cand_near_ties"])
+        assert st.m_traj[t] == r["m"], (t, st.m_traj[t], r["m"])
         if r["decision"] == "converged":
             assert int(g[4]) == 3
             continue
