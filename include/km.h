@@ -140,6 +140,30 @@ km_status kmeans_g(km_ctx *ctx, const void *X, km_xtype xt, int64_t N, int32_t d
                    const float *C, km_prec prec, const int32_t *rho_prev,
                    int32_t *rho, float *C_out, double *E, km_g_stats *st);
 
+/*
+ * kmeans_g_noalloc -- kmeans_g for callers that cannot allocate device memory
+ * (code being recorded into a HIP graph, tight serving loops, hosts that
+ * forbid allocation after start-up).  Same arguments, checks, kernels and
+ * results as kmeans_g (labels, C_out and E bitwise equal for the same
+ * inputs and tile shape), but the call allocates nothing: every buffer
+ * beyond the caller's inputs and outputs comes from one fixed device array
+ * of KM_NOALLOC_SCRATCH_BYTES per device, which the library holds from
+ * km_create until the process ends.
+ *   Limit: a shape whose scratch (control block, prepared centroids, energy
+ *   partials, N flagged-row slots and the update's buffers; roughly
+ *   4 N + 8 (K d + K) * 256 bytes on the fixed-point path, 12 N + 8 d (N/512
+ *   + K) on the sorting path) exceeds the array returns KM_EUNSUPPORTED with
+ *   the bytes it would need in km_last_error.
+ *   Every call on a device shares that device's array, and the array keeps
+ *   the last call's contents: calls that overlap in time on one device (two
+ *   host threads, or two contexts on different streams) race and must be
+ *   serialised by the caller.
+ */
+#define KM_NOALLOC_SCRATCH_BYTES (64u << 20)
+km_status kmeans_g_noalloc(km_ctx *ctx, const void *X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                           const float *C, km_prec prec, const int32_t *rho_prev,
+                           int32_t *rho, float *C_out, double *E, km_g_stats *st);
+
 typedef struct {
   double eps1;          /* dynamic-m shrink threshold (Sec. 3 default 0.02) */
   double eps2;          /* dynamic-m grow threshold (Sec. 3 default 0.5) */

@@ -8,9 +8,9 @@ if the library has not been built.
 
 import importlib
 
-__all__ = ["kmeans_g", "kmeans_solve", "kmeans_solve_batch", "Engine", "Context", "KMError", "synth"]
+__all__ = ["kmeans_g", "kmeans_g_noalloc", "kmeans_solve", "kmeans_solve_batch", "Engine", "Context", "KMError", "synth"]
 
-_LIB_NAMES = ("kmeans_g", "kmeans_solve", "kmeans_solve_batch", "Engine", "Context", "KMError",
+_LIB_NAMES = ("kmeans_g", "kmeans_g_noalloc", "kmeans_solve", "kmeans_solve_batch", "Engine", "Context", "KMError",
               "SolveStats", "GStats", "JobResult", "load_library")
 
 

@@ -164,6 +164,8 @@ def load_library(path: str | None = None):
     lib.kmeans_g.argtypes = [vp, vp, ct.c_int, i64, i32, i32, vp, ct.c_int, vp, vp, vp,
                              ct.POINTER(dbl), ct.POINTER(_GStats)]
     lib.kmeans_g.restype = ct.c_int
+    lib.kmeans_g_noalloc.argtypes = lib.kmeans_g.argtypes
+    lib.kmeans_g_noalloc.restype = ct.c_int
     lib.kmeans_solve.argtypes = [vp, vp, ct.c_int, i64, i32, i32, vp, i32, dbl,
                                  ct.POINTER(_Opts), vp, vp, ct.POINTER(dbl), ct.POINTER(i32),
                                  ct.POINTER(_SolveStats)]
@@ -273,6 +275,14 @@ def kmeans_g(X: torch.Tensor, C: torch.Tensor, prec="f32", rho_prev: torch.Tenso
     Returns (rho int32 [N], C_out float32 [K,d], E float (energy of C), GStats).
     ``out`` = (rho, C_out) writes into caller-owned tensors."""
     return _g_call("kmeans_g", X, C, prec, rho_prev, ctx, out)
+
+
+def kmeans_g_noalloc(X: torch.Tensor, C: torch.Tensor, out: tuple, prec="f32",
+                     rho_prev: torch.Tensor | None = None, ctx: Context | None = None):
+    """kmeans_g whose scratch is the library's fixed device array (no device
+    allocation in the call); ``out`` = (rho int32 [N], C_out float32 [K,d]) is
+    required.  Returns (rho, C_out, E, GStats)."""
+    return _g_call("kmeans_g_noalloc", X, C, prec, rho_prev, ctx, out)
 
 
 def _g_call(name, X, C, prec, rho_prev, ctx, out):

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,39 @@ static km_status ensure_ws(km_ctx* c, const Shape& want) {
   return KM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free G (kmeans_g_noalloc)
+// ---------------------------------------------------------------------------
+// Every buffer of a kmeans_g_noalloc call beyond its inputs and outputs lives
+// in this array; each device that runs the library holds its own copy until
+// the process ends.  In host code the name is only a stand-in for the symbol:
+// km_create looks up the array's address on the device (once per device,
+// with that device current) and every host use goes through that address.
+static __device__ __align__(256) unsigned char scratch[KM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+// Address of device `device`'s copy of the scratch array (device current).
+static hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_dev[device] = ptr;
+  return hipSuccess;
+}
+
+static void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 // Clears n 32-bit words (a kernel rather than a memset node, so that the
 // launch sequence can be recorded into a graph).
 __global__ __launch_bounds__(256) void k_clear_words(unsigned* p, int n) {
@@ -57,7 +91,7 @@ static hipError_t launch_clear(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Argument checks of one G application.
+// Argument checks of one G application (kmeans_g and kmeans_g_noalloc).
 static km_status g_check(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
                          const float* C, km_prec prec, const int32_t* rho_prev, int32_t* rho, float* C_out,
                          double* E) {
@@ -169,6 +203,10 @@ km_status km_create(int device, void* stream, km_ctx** out) {
     return KM_EINVAL;
   }
   if (hipSetDevice(device) != hipSuccess) return KM_EDEVICE;
+  if (scratch_setup(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return KM_EDEVICE;
+  }
   km_ctx* c = new km_ctx();
   c->device = device;
   c->stream = (hipStream_t)stream;
@@ -261,6 +299,28 @@ km_status kmeans_g(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, 
   s = ensure_ws(c, want);
   if (s != KM_OK) return s;
   return g_run(c, c->w, X, xt, N, d, K, C, prec, rho_prev, rho, C_out, E, st);
+}
+
+km_status kmeans_g_noalloc(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,
+                           const float* C, km_prec prec, const int32_t* rho_prev, int32_t* rho,
+                           float* C_out, double* E, km_g_stats* st) {
+  km_status s = g_check(c, X, xt, N, d, K, C, prec, rho_prev, rho, C_out, E);
+  if (s != KM_OK) return s;
+  char* base = (char*)scratch_ptr(c->device);
+  if (!base) return fail(c, KM_EDEVICE, "the scratch array of this device was not set up by km_create");
+  AssignArgs a{};
+  a.N = N; a.d = d; a.K = K; a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = prec == KM_GEMM_BF16;
+  a.shape = shape_for(c, a.gemm_bf16, a.xbf16, d, K);
+  const int grid = assign_grid(a);
+  if (grid <= 0) return fail(c, KM_EUNSUPPORTED, "no assignment kernel for this shape");
+  const size_t need = ws_layout_g(N, d, K, a.gemm_bf16, grid, nullptr, nullptr);
+  if (need > (size_t)KM_NOALLOC_SCRATCH_BYTES)
+    return fail(c, KM_EUNSUPPORTED, "kmeans_g_noalloc needs " + std::to_string(need) +
+                                        " bytes of scratch for this shape; the fixed array holds " +
+                                        std::to_string((size_t)KM_NOALLOC_SCRATCH_BYTES));
+  Ws w;
+  ws_layout_g(N, d, K, a.gemm_bf16, grid, base, &w);
+  return g_run(c, w, X, xt, N, d, K, C, prec, rho_prev, rho, C_out, E, st);
 }
 
 km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t d, int32_t K,

@@ -157,3 +157,59 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
 
 }  // namespace km
 
+namespace km {
+
+// Buffers of one stand-alone G application (kmeans_g): the control block,
+// the prepared centroids, the energy partials of `grid` workgroups, the
+// flagged-row lists and the update's scratch for the path (K, d) takes.  No
+// solver state.  Bytes for the shape; with base != null also fills the G
+// fields of w (the rest stay null).
+inline size_t ws_layout_g(int64_t N, int d, int K, int bf, int grid, char* base, Ws* w) {
+  const int64_t KD = (int64_t)K * d;
+  const bool fx = fx_ok(K, d);
+  const int max_items = fx ? 0 : update_max_items(N, K);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += ws_up(bytes); return o; };
+  const size_t o_ctl = take(sizeof(Ctl));
+  const size_t o_nc = take((size_t)K * 4);
+  const size_t o_cb = take(bf ? (size_t)KD * 4 : 0);
+  const size_t o_del = take(bf ? (size_t)K * 4 : 0);
+  const size_t o_ep = take((size_t)grid * 8);
+  const size_t o_eo = take(8);
+  const size_t o_flags = take((size_t)N * 4);
+  const size_t o_xb = take(fx ? (size_t)(kXBoundSlots + 1) * 4 : 0);
+  const size_t o_fx = take(fx ? (size_t)fx_part_entries(N, K, d) * 8 : 0);
+  const size_t o_lr = take(fx ? 0 : (size_t)N * 4);
+  const size_t o_perm = take(fx ? 0 : (size_t)N * 4);
+  const size_t o_bc = take(fx ? 0 : update_blockcount_ints(N, K) * 4);
+  const size_t o_cnt = take(fx ? 0 : (size_t)K * 4);
+  const size_t o_ss = take(fx ? 0 : (size_t)(K + 1) * 4);
+  const size_t o_is = take(fx ? 0 : (size_t)(K + 1) * 4);
+  const size_t o_ic = take((size_t)max_items * 4);
+  const size_t o_pa = take((size_t)max_items * d * 8);
+  if (base && w) {
+    char* b = base;
+    *w = Ws();
+    w->ctl = (Ctl*)(b + o_ctl);
+    w->nc_tmp = (float*)(b + o_nc);
+    w->Cb_tmp = bf ? (uint16_t*)(b + o_cb) : nullptr;
+    w->del_tmp = bf ? (float*)(b + o_del) : nullptr;
+    w->e_part = (double*)(b + o_ep);
+    w->e_out = (double*)(b + o_eo);
+    w->flags = (int*)(b + o_flags);
+    w->xbound = fx ? (unsigned*)(b + o_xb) : nullptr;
+    w->fxpart = fx ? (unsigned long long*)(b + o_fx) : nullptr;
+    w->lrank = fx ? nullptr : (int*)(b + o_lr);
+    w->perm = fx ? nullptr : (int*)(b + o_perm);
+    w->blockcount = fx ? nullptr : (int*)(b + o_bc);
+    w->counts = fx ? nullptr : (int*)(b + o_cnt);
+    w->seg_start = fx ? nullptr : (int*)(b + o_ss);
+    w->item_start = fx ? nullptr : (int*)(b + o_is);
+    w->item_cluster = fx ? nullptr : (int*)(b + o_ic);
+    w->partial = fx ? nullptr : (double*)(b + o_pa);
+    w->max_items = max_items;
+  }
+  return off;
+}
+
+}  // namespace km
