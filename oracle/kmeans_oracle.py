@@ -329,7 +329,7 @@ class SolveResult:
 def solve(X, C0, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
           eps1: float = EPS1, eps2: float = EPS2, m_init: int = M_INIT,
           fixed_m: bool = False, literal_return: bool = False,
-          replay=None, stored=None, lam: float = RIDGE) -> SolveResult:
+          replay=None, stored=None, lam: float = RIDGE, stored_cand=None) -> SolveResult:
     """Anderson-accelerated Lloyd iteration with dynamic m (Algorithm 1).
 
     ``replay(t)`` may return a centroid array that replaces the candidate
@@ -337,7 +337,12 @@ def solve(X, C0, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
     iterates step by step); returning None keeps the oracle's own candidate.
     ``stored(C)`` maps the fall-back iterate to the values another
     implementation stores for it (e.g. float32 rounding) when replaying;
-    by default the fall-back is the float64 G^{t-1} itself.
+    by default the fall-back is the float64 G^{t-1} itself.  ``stored_cand(C)``
+    does the same for every candidate C^t (C^1 = G^0 and each accelerated
+    iterate), so that an implementation which stores its iterates in float32
+    can be followed end to end without replaying its candidates; by default
+    candidates stay float64.  Neither hook changes any arithmetic of the
+    method, only the values an iterate is stored as.
     """
     X = _f64(X)
     C0 = _f64(C0)
@@ -350,7 +355,7 @@ def solve(X, C0, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
     G_prev, _ = update(X, P_prev, C0)
     hist = History(m_max + 1)
     hist.push(G_prev, G_prev - C0)
-    C = G_prev.copy()
+    C = G_prev.copy() if stored_cand is None else _f64(stored_cand(G_prev)).reshape(k, d)
     C_is_lloyd = True
     E1 = math.inf        # E^{t-1}
     E2 = math.inf        # E^{t-2}
@@ -428,7 +433,7 @@ def solve(X, C0, m_max: int = 10, tol: float = 1e-6, max_iter: int = 500,
 
         E2, E1 = E1, E
         P_prev, G_prev, C_acc = P, G, C
-        C = x_next.reshape(k, d)
+        C = x_next.reshape(k, d) if stored_cand is None else _f64(stored_cand(x_next.reshape(k, d))).reshape(k, d)
         C_is_lloyd = used == 0
 
     return finish(P_prev, C_acc, E1, max_iter, STATUS_NOT_CONVERGED)

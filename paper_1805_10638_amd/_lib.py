@@ -22,7 +22,7 @@ KM_OK, KM_NOT_CONVERGED = 0, 1
 KM_EINVAL, KM_ENOMEM, KM_EDEVICE, KM_EUNSUPPORTED, KM_ENONFINITE = -1, -2, -3, -4, -5
 KM_X_F32, KM_X_BF16 = 0, 1
 KM_GEMM_F32, KM_GEMM_BF16 = 0, 1
-KM_FLAG_FIXED_M, KM_FLAG_LITERAL_RETURN = 1, 2
+KM_FLAG_FIXED_M, KM_FLAG_LITERAL_RETURN, KM_FLAG_BOUNDS = 1, 2, 4
 KM_TRACE_REC = 80
 
 
@@ -48,7 +48,8 @@ class _SolveStats(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("accepted", ct.c_int32), ("rejected", ct.c_int32),
                 ("assign_passes", ct.c_int32), ("m_final", ct.c_int32),
                 ("assign_launches", ct.c_int32), ("recheck_rows", ct.c_int64),
-                ("near_tie_rows", ct.c_int64), ("device_ms", ct.c_double), ("assign_ms", ct.c_double)]
+                ("near_tie_rows", ct.c_int64), ("gemm_rows", ct.c_int64), ("bounds", ct.c_int32),
+                ("device_ms", ct.c_double), ("assign_ms", ct.c_double)]
 
 
 class _Job(ct.Structure):
@@ -103,6 +104,8 @@ class SolveStats:
     m_final: int
     recheck_rows: int
     near_tie_rows: int
+    gemm_rows: int          # rows through the distance GEMM, all passes (N per pass without bounds)
+    bounds: int             # 1 if row bounds were in use
     device_ms: float
     assign_ms: float
     assign_launches: int
@@ -328,7 +331,7 @@ def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float 
                  max_iter: int = 500, eps1: float = 0.02, eps2: float = 0.5, m_init: int = 2,
                  prec="f32", fixed_m: bool = False, literal_return: bool = False,
                  ridge: float = 1e-10, trace: bool = False, ctx: Context | None = None,
-                 out: tuple | None = None, m_traj: bool = False):
+                 out: tuple | None = None, m_traj: bool = False, bounds: bool = False):
     """Anderson-accelerated Lloyd K-Means (Algorithm 1).
 
     Returns (C float32 [K,d], rho int32 [N], E, iters, SolveStats) and, with
@@ -350,7 +353,8 @@ def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float 
     ctx.lib.km_opts_default(ct.byref(o))
     o.eps1, o.eps2, o.ridge = eps1, eps2, ridge
     o.m_init, o.max_iter, o.prec = m_init, max_iter, _prec(prec)
-    o.flags = (KM_FLAG_FIXED_M if fixed_m else 0) | (KM_FLAG_LITERAL_RETURN if literal_return else 0)
+    o.flags = (KM_FLAG_FIXED_M if fixed_m else 0) | (KM_FLAG_LITERAL_RETURN if literal_return else 0) | \
+        (KM_FLAG_BOUNDS if bounds else 0)
     tr = None
     if trace:
         tr = {"C": torch.zeros((max_iter + 1, K, d), dtype=torch.float32, device=X.device),
@@ -371,7 +375,8 @@ def kmeans_solve(X: torch.Tensor, C0: torch.Tensor, m_max: int = 10, tol: float 
                               ct.byref(E), ct.byref(it), ct.byref(ss))
     ctx._check(st, "kmeans_solve", allow=(KM_OK, KM_NOT_CONVERGED))
     stats = SolveStats(ss.iters, ss.accepted, ss.rejected, ss.assign_passes, ss.m_final,
-                       ss.recheck_rows, ss.near_tie_rows, ss.device_ms, ss.assign_ms, ss.assign_launches, st,
+                       ss.recheck_rows, ss.near_tie_rows, ss.gemm_rows, ss.bounds, ss.device_ms, ss.assign_ms,
+                       ss.assign_launches, st,
                        list(mt[:it.value + 1]) if mt is not None else None)
     if trace:
         return C, rho, E.value, it.value, stats, tr
