@@ -22,8 +22,8 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libkmaa.so")
 
-SOURCES = ["km_assign_f32.hip", "km_assign_bf16.hip", "km_assign.hip", "km_update.hip", "km_anderson.hip",
-           "km_api.hip", "km_engine.hip"]
+SOURCES = ["km_assign_f32.hip", "km_assign_f32x.hip", "km_assign_bf16.hip", "km_assign.hip", "km_update.hip",
+           "km_anderson.hip", "km_api.hip", "km_engine.hip", "km_recheck.hip"]
 
 ARCH = "gfx950"
 # Packed-FP32 instructions are disabled for all device code.

@@ -130,6 +130,7 @@ static km_status g_run(km_ctx* c, const Ws& w, const void* X, km_xtype xt, int64
   a.lab = rho; a.lab_prev = rho_prev; a.e_part = w.e_part; a.flags = w.flags; a.ctl = w.ctl;
   a.xbf16 = xt == KM_X_BF16; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xt == KM_X_BF16, d, K);
+  a.fl_cnt = assign_list_mode(a) ? w.fl_cnt : nullptr;
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xt == KM_X_BF16;
   u.lab = rho; u.lab_from_ctl = 0; u.lrank = w.lrank; u.blockcount = w.blockcount;
@@ -141,10 +142,17 @@ static km_status g_run(km_ctx* c, const Ws& w, const void* X, km_xtype xt, int64
   // phase times (a solve computes it once)
   HIP_TRY(c, launch_xbound(u, st_), "bound of |x|");
   // with timing on, the events take the times of the kernels' own dispatches
-  HIP_TRY(c, launch_assign(a, kRolePlain, st_, c->timing ? c->ta[0] : nullptr, c->timing ? c->tb[0] : nullptr),
+  HIP_TRY(c, launch_assign(a, kRolePlain, st_, c->timing ? c->ta[0] : nullptr,
+                           (c->timing && !a.fl_cnt) ? c->tb[0] : nullptr),
           "assignment");
   const int grid = assign_grid(a);
-  HIP_TRY(c, launch_reduce_energy(w.e_part, grid, w.e_out, st_), "energy");
+  int n_part = grid;
+  if (a.fl_cnt) {   // the listed rows: one re-check launch over the whole pass
+    HIP_TRY(c, launch_recheck(recheck_args(a, w.e_part + grid), kRolePlain, st_, c->timing ? c->tb[0] : nullptr),
+            "re-check");
+    n_part = grid + kReGrid;
+  }
+  HIP_TRY(c, launch_reduce_energy(w.e_part, n_part, w.e_out, st_), "energy");
   HIP_TRY(c, launch_update_sums(u, st_, c->timing ? c->ta[1] : nullptr), "update");
   FinalizeArgs f{};
   f.d = d; f.K = K; f.cap = 0; f.partial = w.partial; f.item_start = w.item_start;
@@ -397,6 +405,9 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   a.xbf16 = xbf; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xbf, d, K);
   a.lb = bnd ? c->w.lb : nullptr; a.C_ref = bnd ? c->w.C_ref : nullptr; a.bounds = 0;
+  // undecided rows of a deferring kernel: one re-check launch per pass
+  a.fl_cnt = assign_list_mode(a) ? c->w.fl_cnt : nullptr;
+  const bool relist = a.fl_cnt != nullptr;
   UpdateArgs u{};
   u.X = X; u.N = N; u.d = d; u.K = K; u.xbf16 = xbf;
   u.lab = c->w.labels; u.lab_from_ctl = 1; u.lrank = c->w.lrank; u.blockcount = c->w.blockcount;
@@ -425,6 +436,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   HIP_TRY(c, launch_prep(c->w.C_tmp, K, d, c->w.nc_tmp, gbf ? c->w.Cb_tmp : nullptr,
                          gbf ? c->w.del_tmp : nullptr, q), "prep");
   HIP_TRY(c, launch_assign(a, kRolePlain, q), "assignment");
+  if (relist) HIP_TRY(c, launch_recheck(recheck_args(a, c->w.e_part), kRolePlain, q), "re-check");
   HIP_TRY(c, launch_xbound(u, q), "bound of |x|");
   HIP_TRY(c, launch_update_sums(u, q), "update");
   HIP_TRY(c, launch_finalize(f, q), "finalize");
@@ -435,12 +447,16 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   // ---- per-iteration launch sequence ----
   const int grid = assign_grid(a);
   if (grid <= 0) return fail(c, KM_EUNSUPPORTED, "no assignment kernel for this shape");
+  // energy partials of a pass: the assignment's workgroups, then the re-check's
+  const int n_part = grid + (relist ? kReGrid : 0);
   AssignArgs ac = a;
   ac.C = c->w.C_cand; ac.nc = c->w.nc_cand; ac.Cb = gbf ? c->w.Cb_cand : nullptr;
   ac.delta = gbf ? c->w.del_cand : nullptr; ac.e_part = c->w.e_part; ac.bounds = bnd ? 1 : 0;
   AssignArgs af = a;
   af.C = c->w.C_fb; af.nc = c->w.nc_fb; af.Cb = gbf ? c->w.Cb_fb : nullptr;
-  af.delta = gbf ? c->w.del_fb : nullptr; af.e_part = c->w.e_part + grid; af.bounds = bnd ? 1 : 0;
+  af.delta = gbf ? c->w.del_fb : nullptr; af.e_part = c->w.e_part + n_part; af.bounds = bnd ? 1 : 0;
+  const RecheckArgs rc = recheck_args(ac, c->w.e_part + grid);
+  const RecheckArgs rf = recheck_args(af, c->w.e_part + n_part + grid);
   FinalizeArgs fi = f;
   fi.mode = kFinIter; fi.C_in = nullptr;
   CombineArgs ci = cb;
@@ -452,12 +468,12 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   // launched back to back start without a gap while the host stays ahead).
   // The host keeps two iterations in flight.
   CtlArgs k1{};
-  k1.ctl = c->w.ctl; k1.e_part = c->w.e_part; k1.n_part = grid; k1.stage = 1;
+  k1.ctl = c->w.ctl; k1.e_part = c->w.e_part; k1.n_part = n_part; k1.stage = 1;
   k1.tr.trace_C = opt.trace_C; k1.tr.trace_rec = opt.trace_rec; k1.tr.C_cand = c->w.C_cand;
   k1.tr.K = K; k1.tr.d = d;
   k1.tr.m_traj = opt.m_traj ? c->w.m_traj : nullptr;
   CtlArgs k2 = k1;
-  k2.e_part = c->w.e_part + grid; k2.stage = 2; k2.tr.trace_C = nullptr;
+  k2.e_part = c->w.e_part + n_part; k2.stage = 2; k2.tr.trace_C = nullptr;
 
   // The combine kernel, last of the iteration, writes the done flag into
   // pinned slot p.  An event taken by a dispatch still idles the device for a
@@ -471,10 +487,14 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
     CombineArgs cp = ci;
     cp.done_out = done_dev + p;
     // with timing on, ta/tb take the candidate assignment's own start and end
-    HIP_TRY(c, launch_assign(ac, kRoleCand, q, c->timing ? c->ta[p] : nullptr, c->timing ? c->tb[p] : nullptr),
+    // (the end of its re-check in list mode)
+    HIP_TRY(c, launch_assign(ac, kRoleCand, q, c->timing ? c->ta[p] : nullptr,
+                             (c->timing && !relist) ? c->tb[p] : nullptr),
             "assignment");
+    if (relist) HIP_TRY(c, launch_recheck(rc, kRoleCand, q, c->timing ? c->tb[p] : nullptr), "re-check");
     HIP_TRY(c, launch_controller(k1, q), "controller");
     HIP_TRY(c, launch_assign(af, kRoleFallback, q), "assignment");
+    if (relist) HIP_TRY(c, launch_recheck(rf, kRoleFallback, q), "re-check");
     HIP_TRY(c, launch_controller(k2, q), "controller");
     HIP_TRY(c, launch_update_sums(u, q), "update");
     HIP_TRY(c, launch_finalize(fi, q), "finalize");

@@ -46,6 +46,28 @@ int assign_bounds_ok(const AssignArgs& a) {
   return (p.fn_bnd && p.resident) ? 1 : 0;
 }
 
+int assign_list_mode(const AssignArgs& a) {
+  const KernelPick p = assign_pick(a);
+  if (!p.fn) return 0;
+  const bool defer = a.gemm_bf16 || !p.resident;
+  const int grid = assign_grid(a);
+  return (defer && grid > 0 && grid <= kReMaxGrid) ? 1 : 0;
+}
+
+RecheckArgs recheck_args(const AssignArgs& a, double* e_part) {
+  const KernelPick p = assign_pick(a);
+  RecheckArgs r{};
+  r.X = a.X; r.N = a.N; r.d = a.d; r.K = a.K; r.xbf16 = a.xbf16; r.C = a.C;
+  r.lab = a.lab; r.lab_prev = a.lab_prev; r.flags = a.flags; r.fl_cnt = a.fl_cnt;
+  r.grid = assign_grid(a);
+  r.W = p.threads / 64;
+  r.group_rows = p.rows;
+  r.sb16 = p.rows / (p.threads / 64);
+  r.e_part = e_part;
+  r.ctl = a.ctl;
+  return r;
+}
+
 // Kernels whose LDS budget exceeds the default 64 KB must say so once.
 static hipError_t allow_lds(const KernelPick& p) {
   if (p.lds <= 64 * 1024) return hipSuccess;

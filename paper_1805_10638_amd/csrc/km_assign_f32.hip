@@ -5,8 +5,11 @@
 //   1  SB = 1, W = 4, 60 KB
 //   2  default SB, W = 8, 60 KB
 //   3  SB = 4, W = 4, 60 KB (up to 8 dims per lane group; else the default)
-// Two 16-sample blocks per wave measured best for d = 32 on MI355X (190 us
-// vs 213 us with four blocks at N = 1e6, K = 256).
+// The autotuner picks the shape per (width, K bucket) from measured times
+// (tiles_gfx950.json); at N = 1e6, d = 32, K = 256 it picks shape 3.
+// float32 rows are instantiated here, bfloat16-stored rows in
+// km_assign_f32x.hip (the same source with KM_F32_XBF), so that the two
+// halves compile in parallel.
 
 #include "km_assign_kernel.h"
 
@@ -43,8 +46,14 @@ static KernelPick f32_ks(int ks, int K, int shape) {
   return KernelPick();
 }
 
+#ifdef KM_F32_XBF
+// bfloat16-stored rows (compiled as km_assign_f32x.hip)
+KernelPick pick_f32_xbf(int ks, int K, int shape) { return f32_ks<true>(ks, K, shape); }
+#else
+KernelPick pick_f32_xbf(int ks, int K, int shape);
 KernelPick pick_f32(int ks, bool xbf, int K, int shape) {
-  return xbf ? f32_ks<true>(ks, K, shape) : f32_ks<false>(ks, K, shape);
+  return xbf ? pick_f32_xbf(ks, K, shape) : f32_ks<false>(ks, K, shape);
 }
+#endif
 
 }  // namespace km

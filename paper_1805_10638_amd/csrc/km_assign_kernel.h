@@ -131,6 +131,13 @@ __device__ __forceinline__ bool near_tie(double d1, double d2) {
   return (d2 - d1) < 1e-6 * d2 || d2 == 0.0;
 }
 
+// Smallest power of two at least n (at most cap).
+constexpr int pow2_at_least(int n, int cap) {
+  int p = 1;
+  while (p < n && p < cap) p <<= 1;
+  return p;
+}
+
 // Largest float32 not above v (v >= 0 or +inf).
 __device__ __forceinline__ float f32_down(double v) {
   float f = (float)v;
@@ -552,17 +559,49 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     if (use_in) {
       double m1 = 0.0, m2 = 0.0;
       int j1 = -1;
-      for (int j = tid; j < K; j += NT) {
-        const float* cr = Cs + j * LD;
-        const float* rr = a.C_ref + (int64_t)j * d;
+      // TPR lanes per centroid row (DP / 4 rounded up to a power of two, at
+      // most 64), each with 16-byte loads of its dimensions; every load of a
+      // round is issued before the first is used
+      constexpr int TPR = pow2_at_least(DP / 4, 64);
+      constexpr int V = (DP / 4 + TPR - 1) / TPR;   // 16-byte vectors per lane and row
+      const int sub = lane % TPR;
+      constexpr int RPR = NT / TPR;   // rows per round
+      const bool vrow = (d == DP);
+      for (int it = 0; it < (K + RPR - 1) / RPR; ++it) {   // the same trip count on every lane
+        const int j = tid / TPR + it * RPR;
         double s2 = 0.0;
-        for (int k = 0; k < d; ++k) {
-          const double df = (double)cr[k] - (double)rr[k];
-          s2 = fma(df, df, s2);
+        if (j < K) {
+          float4 cv[V], rv[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const int k = (sub + v * TPR) * 4;
+            cv[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rv[v] = cv[v];
+            if (k < DP) cv[v] = *(const float4*)(Cs + j * LD + k);
+            if (k + 3 < d && vrow) {
+              rv[v] = *(const float4*)(a.C_ref + (int64_t)j * d + k);
+            } else {
+              if (k < d) rv[v].x = a.C_ref[(int64_t)j * d + k];
+              if (k + 1 < d) rv[v].y = a.C_ref[(int64_t)j * d + k + 1];
+              if (k + 2 < d) rv[v].z = a.C_ref[(int64_t)j * d + k + 2];
+              if (k + 3 < d) rv[v].w = a.C_ref[(int64_t)j * d + k + 3];
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < V; ++v) {   // padding dimensions are zero in both
+            double df = (double)cv[v].x - (double)rv[v].x; s2 = fma(df, df, s2);
+            df = (double)cv[v].y - (double)rv[v].y; s2 = fma(df, df, s2);
+            df = (double)cv[v].z - (double)rv[v].z; s2 = fma(df, df, s2);
+            df = (double)cv[v].w - (double)rv[v].w; s2 = fma(df, df, s2);
+          }
         }
-        const double sh = sqrt(s2) * (1.0 + 1e-12);
-        if (sh > m1) { m2 = m1; m1 = sh; j1 = j; }
-        else if (sh > m2) m2 = sh;
+#pragma unroll
+        for (int off = 1; off < TPR; off <<= 1) s2 += __shfl_xor(s2, off, kWave);
+        if (j < K && sub == 0) {
+          const double sh = sqrt(s2) * (1.0 + 1e-12);
+          if (sh > m1) { m2 = m1; m1 = sh; j1 = j; }
+          else if (sh > m2) m2 = sh;
+        }
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
@@ -1149,7 +1188,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       // batches now, so that the re-check overlaps other workgroups' MFMA work
       // instead of piling up after the last row group (bf16 GEMM kernels; in
       // the float32 kernels the extra live registers of this call would spill).
-      if (kInterleave && defer && !resident) {
+      if (kInterleave && defer && !resident && !a.fl_cnt) {
         int* wc = wcnt + (nb & 1) * 16;   // two buffers: a slow wave may still read the previous one
         if (lane == 0) wc[wave] = nfl;
         __syncthreads();
@@ -1159,7 +1198,9 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
   }
 
-  if (defer) {   // the remaining listed rows
+  if (a.fl_cnt) {   // list mode: the rows stay listed for k_recheck
+    if (lane == 0) a.fl_cnt[bx * 16 + wave] = defer ? nfl : 0;
+  } else if (defer) {   // the remaining listed rows
     int* wc = wcnt + (nb & 1) * 16;
     if (lane == 0) wc[wave] = nfl;
     __syncthreads();

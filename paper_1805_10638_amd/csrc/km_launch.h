@@ -37,6 +37,10 @@ struct AssignArgs {
   float* lb;
   const float* C_ref;
   int bounds;
+  // List mode (single-instance launches): rows the GEMM bound cannot decide
+  // stay in the per-wave lists for k_recheck, whose list lengths go to
+  // fl_cnt[workgroup * 16 + wave]; null: the workgroups re-check their own.
+  int* fl_cnt;
 };
 // 1 if launches for a's shape can keep row bounds (float32 GEMM, centroids
 // resident in LDS); the solver enables them only then.
@@ -188,6 +192,31 @@ struct CombineArgs {
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s, hipEvent_t ev1 = nullptr);
 int combine_grid(int K);
 hipError_t launch_combine_batch(const CombineArgs* tab, const int* prefix, int n, int blocks, hipStream_t s);
+
+// ----- re-check of a pass's listed rows (list-mode assignment launches) -----
+constexpr int kReGrid = 256;       // workgroups (and energy partials) of a re-check launch
+constexpr int kReMaxGrid = 4096;   // largest assignment grid a re-check can follow
+struct RecheckArgs {
+  const void* X;
+  int64_t N;
+  int d, K, xbf16;
+  const float* C;         // float32 centroids of the pass
+  int* lab;               // as in AssignArgs
+  const int* lab_prev;
+  const int* flags;       // the pass's per-wave lists (slot layout of the assignment launch)
+  const int* fl_cnt;      // grid x 16 list lengths written by the assignment launch
+  int grid, W, sb16, group_rows;   // the assignment launch's workgroups, waves, 16 SB, rows per group
+  double* e_part;         // kReGrid energy partials
+  Ctl* ctl;
+  int role;
+};
+// 1 if the assignment launch for a leaves undecided rows in lists (its kernel
+// defers: bfloat16 GEMM or centroids streamed through LDS) and its grid fits a re-check.
+int assign_list_mode(const AssignArgs& a);
+// The re-check's arguments for the assignment launch a (role of the launch).
+RecheckArgs recheck_args(const AssignArgs& a, double* e_part);
+// ev1 (nullable): takes the end time of the re-check's own dispatch
+hipError_t launch_recheck(const RecheckArgs& r, Role role, hipStream_t s, hipEvent_t ev1 = nullptr);
 
 // Plain energy reduction for stand-alone G(C): sum of partials in fixed order.
 hipError_t launch_reduce_energy(const double* e_part, int n, double* out, hipStream_t s);

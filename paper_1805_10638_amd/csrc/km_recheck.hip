@@ -1,0 +1,242 @@
+// Re-check of the rows an assignment pass could not decide (Sec. 1, Eq. (3)
+// exactly): one launch over the whole pass's flagged rows.
+//
+// An assignment launch in list mode (AssignArgs::fl_cnt set) leaves the rows
+// whose two best GEMM scores lie within the rounding bound in its per-wave
+// lists (the p-th row wave w of workgroup b flags is stored in the slot of
+// the p-th row that wave owns) and writes the list lengths.  This kernel
+// numbers the listed rows in (workgroup, wave, position) order, takes them in
+// batches of kReRows, stages each batch's rows in LDS and streams the float32
+// centroids through LDS in chunks: every chunk serves the whole batch, so the
+// centroids are read once per kReRows rows instead of once per row.  For
+// every listed row: float64 direct differences to all K centroids, the
+// lowest index among the smallest distances, and the second smallest
+// distance (near ties by the float64 definition are counted).  The energy
+// terms of the rows are added in batch and row order into one partial per
+// workgroup, so the pass's energy does not depend on timing.
+
+#include "km_assign_kernel.h"
+
+namespace km {
+
+constexpr int kReThreads = 256;
+constexpr int kReRows = 64;                  // rows per batch
+constexpr int kReMR = kReRows / 4;           // rows per thread (4 waves, one row group each)
+constexpr int kReCRows = 64;                 // centroid rows per LDS chunk (one per lane)
+constexpr int kReBatch = 8;                  // 16-byte loads in flight per thread while staging
+
+// Four consecutive values of a row of X from element e (all inside the row),
+// as float32.
+__device__ __forceinline__ float4 ld_x4(const void* X, int64_t e, bool bf) {
+  if (bf) {
+    const uint2 v = *(const uint2*)((const uint16_t*)X + e);
+    return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u),
+                       __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xFFFF0000u));
+  }
+  return *(const float4*)((const float*)X + e);
+}
+
+// LDS bytes of k_recheck for width d and an assignment grid of `grid`.
+size_t recheck_lds(int d, int grid) {
+  const int dp = (d + 3) & ~3;
+  return (size_t)(grid + 1) * 4 + kReRows * 4 + (size_t)kReRows * 8 + (size_t)kReRows * dp * 4 +
+         (size_t)kReCRows * (dp + 4) * 4;
+}
+
+__global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
+  Ctl* ctl = r.ctl;
+  if (r.role != kRolePlain) {
+    if (ctl->done) return;
+    if (r.role == kRoleFallback && !ctl->reject) return;
+  }
+  int* rho;
+  const int* prev;
+  if (r.role == kRoleCand) {
+    rho = r.lab + (int64_t)ctl->lab_cand * r.N;
+    prev = r.lab + (int64_t)ctl->lab_prev * r.N;
+  } else if (r.role == kRoleFallback) {
+    rho = r.lab + (int64_t)ctl->lab_fb * r.N;
+    prev = r.lab + (int64_t)ctl->lab_prev * r.N;
+  } else {
+    rho = r.lab;
+    prev = r.lab_prev;
+  }
+  const int slot = (r.role == kRoleFallback) ? 1 : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int d = r.d, K = r.K, dp = (d + 3) & ~3, LDc = dp + 4;
+  const int grid = r.grid;
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* rowterm = (double*)smem_raw;                       // kReRows
+  int* rowidx = (int*)(rowterm + kReRows);                   // kReRows
+  float* xs = (float*)(rowidx + kReRows);                     // kReRows x dp
+  float* cc = xs + (size_t)kReRows * dp;                     // kReCRows x (dp + 4)
+  int* pre = (int*)(cc + (size_t)kReCRows * LDc);            // grid + 1
+
+  // flagged rows before workgroup b of the assignment launch: pre[b]
+  for (int b = tid; b < grid; b += kReThreads) {
+    int c = 0;
+    for (int w = 0; w < r.W; ++w) c += r.fl_cnt[b * 16 + w];
+    pre[b + 1] = c;
+  }
+  if (tid == 0) pre[0] = 0;
+  __syncthreads();
+  if (tid == 0)
+    for (int b = 1; b <= grid; ++b) pre[b] += pre[b - 1];
+  __syncthreads();
+  const int F = pre[grid];
+  const int nbatch = (F + kReRows - 1) / kReRows;
+
+  double e_sum = 0.0;
+  unsigned n_changed = 0, n_near = 0;
+  for (int bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+    const int rb = (F - bt * kReRows) < kReRows ? (F - bt * kReRows) : kReRows;
+    if (tid < rb) {   // listed row number f: its workgroup, wave, list position, slot
+      const int f = bt * kReRows + tid;
+      int lo = 0, hi = grid;   // largest b with pre[b] <= f
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= f) lo = mid; else hi = mid;
+      }
+      int q = f - pre[lo], w = 0;
+      while (w < r.W - 1 && q >= r.fl_cnt[lo * 16 + w]) { q -= r.fl_cnt[lo * 16 + w]; ++w; }
+      const int64_t own = ((int64_t)lo + (int64_t)(q / r.sb16) * grid) * r.group_rows + (int64_t)w * r.sb16 +
+                          q % r.sb16;
+      rowidx[tid] = r.flags[own];
+    }
+    __syncthreads();
+    // the batch's rows as float32 (exact for float32 and bfloat16 storage),
+    // zero beyond d and rb; 16-byte loads when d is a multiple of 4
+    const int q4 = dp / 4;
+    const bool xbf = r.xbf16 != 0;
+    if (d == dp) {
+      for (int e0 = tid; e0 < kReRows * q4; e0 += kReBatch * kReThreads) {
+        float4 v[kReBatch];
+#pragma unroll
+        for (int t = 0; t < kReBatch; ++t) {
+          const int e = e0 + t * kReThreads, u = e / q4, k = (e - u * q4) * 4;
+          v[t] = (e < kReRows * q4 && u < rb) ? ld_x4(r.X, (int64_t)rowidx[u] * d + k, xbf)
+                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < kReBatch; ++t) {
+          const int e = e0 + t * kReThreads;
+          if (e < kReRows * q4) *(float4*)(xs + (size_t)e * 4) = v[t];
+        }
+      }
+    } else {
+      for (int e = tid; e < kReRows * dp; e += kReThreads) {
+        const int u = e / dp, k = e - u * dp;
+        float v = 0.f;
+        if (u < rb && k < d) v = ld_x(r.X, (int64_t)rowidx[u] * d + k, xbf);
+        xs[e] = v;
+      }
+    }
+    // rows wave + 4 m of the batch; centroid slot lane of each chunk
+    double bd[kReMR];
+    float bd2[kReMR];
+    int bj[kReMR];
+#pragma unroll
+    for (int m = 0; m < kReMR; ++m) { bd[m] = __builtin_inf(); bd2[m] = __builtin_inff(); bj[m] = -1; }
+    for (int c0 = 0; c0 < K; c0 += kReCRows) {
+      const int rows = (K - c0) < kReCRows ? (K - c0) : kReCRows;
+      __syncthreads();
+      if (d == dp) {   // 16-byte loads, kReBatch in flight per thread
+        for (int e0 = tid; e0 < kReCRows * q4; e0 += kReBatch * kReThreads) {
+          float4 v[kReBatch];
+#pragma unroll
+          for (int t = 0; t < kReBatch; ++t) {
+            const int e = e0 + t * kReThreads, jj = e / q4, k = (e - jj * q4) * 4;
+            v[t] = (e < kReCRows * q4 && jj < rows) ? *(const float4*)(r.C + (int64_t)(c0 + jj) * d + k)
+                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int t = 0; t < kReBatch; ++t) {
+            const int e = e0 + t * kReThreads, jj = e / q4, k = (e - jj * q4) * 4;
+            if (e < kReCRows * q4) *(float4*)(cc + jj * LDc + k) = v[t];
+          }
+        }
+      } else {
+        for (int e = tid; e < kReCRows * dp; e += kReThreads) {
+          const int jj = e / dp, k = e - jj * dp;
+          cc[jj * LDc + k] = (jj < rows && k < d) ? r.C[(int64_t)(c0 + jj) * d + k] : 0.f;
+        }
+      }
+      __syncthreads();
+      if (lane < rows) {
+        const float* cr = cc + lane * LDc;
+        double acc[kReMR];
+#pragma unroll
+        for (int m = 0; m < kReMR; ++m) acc[m] = 0.0;
+        for (int k = 0; k < dp; k += 4) {
+          const float4 c4 = *(const float4*)(cr + k);
+          const double cx = c4.x, cy = c4.y, cz = c4.z, cw = c4.w;
+#pragma unroll
+          for (int m = 0; m < kReMR; ++m) {
+            const float4 x4 = *(const float4*)(xs + (wave + 4 * m) * dp + k);
+            double df = (double)x4.x - cx; acc[m] = fma(df, df, acc[m]);
+            df = (double)x4.y - cy; acc[m] = fma(df, df, acc[m]);
+            df = (double)x4.z - cz; acc[m] = fma(df, df, acc[m]);
+            df = (double)x4.w - cw; acc[m] = fma(df, df, acc[m]);
+          }
+        }
+        const int j = c0 + lane;
+#pragma unroll
+        for (int m = 0; m < kReMR; ++m) {
+          if (acc[m] < bd[m]) { bd2[m] = (float)bd[m]; bd[m] = acc[m]; bj[m] = j; }
+          else bd2[m] = fminf(bd2[m], (float)acc[m]);
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kReMR; ++m) {
+      const int u = wave + 4 * m;
+      double dist, dist2;
+      const int j = wave_argmin2(bd[m], (double)bd2[m], bj[m], &dist, &dist2);
+      if (u < rb) {
+        const bool nt = near_tie(dist, dist2);
+        if (lane == 0) {
+          const int i = rowidx[u];
+          const int jl = j >= 0 ? j : 0;
+          rho[i] = jl;
+          if (prev != nullptr && prev[i] != jl) ++n_changed;
+          if (nt) ++n_near;
+          rowterm[u] = dist;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int u = 0; u < rb; ++u) e_sum += rowterm[u];
+  }
+  if (lane == 0) {
+    if (n_changed) atomicAdd(&ctl->cnt_changed[slot], (unsigned long long)n_changed);
+    if (n_near) atomicAdd(&ctl->cnt_near[slot], (unsigned long long)n_near);
+  }
+  if (tid == 0) r.e_part[blockIdx.x] = e_sum;
+}
+
+hipError_t launch_recheck(const RecheckArgs& a, Role role, hipStream_t s, hipEvent_t ev1) {
+  if (a.d <= 0 || a.d > kMaxD || a.K <= 0 || a.grid <= 0 || a.grid > kReMaxGrid || a.W <= 0 || a.W > 16)
+    return hipErrorInvalidValue;
+  RecheckArgs arg = a;
+  arg.role = role;
+  const size_t lds = recheck_lds(a.d, a.grid);
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)&k_recheck, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  clear_pending_error();
+  if (ev1) {
+    void* params[] = {&arg};
+    return hipExtLaunchKernel((const void*)&k_recheck, dim3(kReGrid), dim3(kReThreads), params, lds, s, nullptr,
+                              ev1, 0);
+  }
+  hipLaunchKernelGGL(k_recheck, dim3(kReGrid), dim3(kReThreads), lds, s, arg);
+  return hipGetLastError();
+}
+
+}  // namespace km

@@ -35,7 +35,9 @@ struct Ws {
   int* seg_start = nullptr;     // K + 1
   int* item_start = nullptr;    // K + 1
   int* item_cluster = nullptr;  // max_items
-  double* e_part = nullptr;     // 2 x (N / 64 + 1): partials of the candidate and fall-back passes
+  double* e_part = nullptr;     // 2 x (N / 64 + 1 + kReGrid): partials of the candidate and fall-back
+                                //   passes (assignment workgroups, then the re-check's)
+  int* fl_cnt = nullptr;        // kReMaxGrid x 16 list lengths of a list-mode assignment launch
   double* partial = nullptr;    // max_items x d
   unsigned* xbound = nullptr;   // kXBoundSlots + 1 (fixed-point update: maxima, then e)
   unsigned long long* fxpart = nullptr;  // fx_part_entries(N, K, d)
@@ -84,7 +86,8 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const size_t o_ss = take((size_t)(s.K + 1) * 4);
   const size_t o_is = take((size_t)(s.K + 1) * 4);
   const size_t o_ic = take((size_t)max_items * 4);
-  const size_t o_ep = take((size_t)2 * grid * 8);
+  const size_t o_ep = take((size_t)2 * (grid + kReGrid) * 8);
+  const size_t o_fc = take((size_t)kReMaxGrid * 16 * 4);
   const size_t o_pa = take((size_t)max_items * s.d * 8);
   const size_t o_xb = take((size_t)(kXBoundSlots + 1) * 4);
   const size_t o_fx = take((size_t)fx_part_entries(N, s.K, s.d) * 8);
@@ -123,6 +126,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
     w->item_start = (int*)(b + o_is);
     w->item_cluster = (int*)(b + o_ic);
     w->e_part = (double*)(b + o_ep);
+    w->fl_cnt = (int*)(b + o_fc);
     w->partial = (double*)(b + o_pa);
     w->xbound = (unsigned*)(b + o_xb);
     w->fxpart = (unsigned long long*)(b + o_fx);
@@ -174,7 +178,8 @@ inline size_t ws_layout_g(int64_t N, int d, int K, int bf, int grid, char* base,
   const size_t o_nc = take((size_t)K * 4);
   const size_t o_cb = take(bf ? (size_t)KD * 4 : 0);
   const size_t o_del = take(bf ? (size_t)K * 4 : 0);
-  const size_t o_ep = take((size_t)grid * 8);
+  const size_t o_ep = take((size_t)(grid + kReGrid) * 8);
+  const size_t o_fc = take((size_t)kReMaxGrid * 16 * 4);
   const size_t o_eo = take(8);
   const size_t o_flags = take((size_t)N * 4);
   const size_t o_xb = take(fx ? (size_t)(kXBoundSlots + 1) * 4 : 0);
@@ -195,6 +200,7 @@ inline size_t ws_layout_g(int64_t N, int d, int K, int bf, int grid, char* base,
     w->Cb_tmp = bf ? (uint16_t*)(b + o_cb) : nullptr;
     w->del_tmp = bf ? (float*)(b + o_del) : nullptr;
     w->e_part = (double*)(b + o_ep);
+    w->fl_cnt = (int*)(b + o_fc);
     w->e_out = (double*)(b + o_eo);
     w->flags = (int*)(b + o_flags);
     w->xbound = fx ? (unsigned*)(b + o_xb) : nullptr;
