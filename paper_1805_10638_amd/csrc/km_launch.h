@@ -194,7 +194,7 @@ int combine_grid(int K);
 hipError_t launch_combine_batch(const CombineArgs* tab, const int* prefix, int n, int blocks, hipStream_t s);
 
 // ----- re-check of a pass's listed rows (list-mode assignment launches) -----
-constexpr int kReGrid = 256;       // workgroups (and energy partials) of a re-check launch
+constexpr int kReGrid = 512;       // workgroups (and energy partials) of a re-check launch
 constexpr int kReMaxGrid = 4096;   // largest assignment grid a re-check can follow
 struct RecheckArgs {
   const void* X;

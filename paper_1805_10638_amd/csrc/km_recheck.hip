@@ -5,23 +5,25 @@
 // whose two best GEMM scores lie within the rounding bound in its per-wave
 // lists (the p-th row wave w of workgroup b flags is stored in the slot of
 // the p-th row that wave owns) and writes the list lengths.  This kernel
-// numbers the listed rows in (workgroup, wave, position) order, takes them in
-// batches of kReRows, stages each batch's rows in LDS and streams the float32
-// centroids through LDS in chunks: every chunk serves the whole batch, so the
-// centroids are read once per kReRows rows instead of once per row.  For
-// every listed row: float64 direct differences to all K centroids, the
-// lowest index among the smallest distances, and the second smallest
-// distance (near ties by the float64 definition are counted).  The energy
-// terms of the rows are added in batch and row order into one partial per
-// workgroup, so the pass's energy does not depend on timing.
+// numbers the listed rows in (workgroup, wave, position) order and takes them
+// in batches of kReRows (kReMR per wave), so that a few thousand listed rows
+// still spread over every CU.  A batch's rows are staged in LDS as float64;
+// the float32 centroids stream through LDS in chunks of 64 (one per lane) and
+// every chunk serves the whole batch.  For every listed row: float64 direct
+// differences to all K centroids, the lowest index among the smallest
+// distances, and the second smallest distance (near ties by the float64
+// definition are counted).  The energy terms of the rows are added in batch
+// and row order into one partial per workgroup, so the pass's energy does not
+// depend on timing.
 
 #include "km_assign_kernel.h"
 
 namespace km {
 
 constexpr int kReThreads = 256;
-constexpr int kReRows = 64;                  // rows per batch
-constexpr int kReMR = kReRows / 4;           // rows per thread (4 waves, one row group each)
+constexpr int kReWaves = kReThreads / 64;
+constexpr int kReMR = 4;                     // rows per wave and batch
+constexpr int kReRows = kReWaves * kReMR;    // rows per batch
 constexpr int kReCRows = 64;                 // centroid rows per LDS chunk (one per lane)
 constexpr int kReBatch = 8;                  // 16-byte loads in flight per thread while staging
 
@@ -39,8 +41,8 @@ __device__ __forceinline__ float4 ld_x4(const void* X, int64_t e, bool bf) {
 // LDS bytes of k_recheck for width d and an assignment grid of `grid`.
 size_t recheck_lds(int d, int grid) {
   const int dp = (d + 3) & ~3;
-  return (size_t)(grid + 1) * 4 + kReRows * 4 + (size_t)kReRows * 8 + (size_t)kReRows * dp * 4 +
-         (size_t)kReCRows * (dp + 4) * 4;
+  return (size_t)kReRows * dp * 8 + (size_t)kReRows * 8 + (size_t)kReCRows * (dp + 4) * 4 +
+         (size_t)kReRows * 4 + (size_t)kReWaves * 4 + (size_t)(grid + 1) * 4;
 }
 
 __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
@@ -67,28 +69,49 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
   const int grid = r.grid;
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* rowterm = (double*)smem_raw;                       // kReRows
-  int* rowidx = (int*)(rowterm + kReRows);                   // kReRows
-  float* xs = (float*)(rowidx + kReRows);                     // kReRows x dp
-  float* cc = xs + (size_t)kReRows * dp;                     // kReCRows x (dp + 4)
-  int* pre = (int*)(cc + (size_t)kReCRows * LDc);            // grid + 1
+  double* xs = (double*)smem_raw;                            // kReRows x dp
+  double* rowterm = xs + (size_t)kReRows * dp;               // kReRows
+  float* cc = (float*)(rowterm + kReRows);                   // kReCRows x (dp + 4)
+  int* rowidx = (int*)(cc + (size_t)kReCRows * LDc);         // kReRows
+  int* wsum = rowidx + kReRows;                              // kReWaves
+  int* pre = wsum + kReWaves;                                // grid + 1
 
   // flagged rows before workgroup b of the assignment launch: pre[b]
-  for (int b = tid; b < grid; b += kReThreads) {
-    int c = 0;
-    for (int w = 0; w < r.W; ++w) c += r.fl_cnt[b * 16 + w];
-    pre[b + 1] = c;
+  // (each thread sums a run of workgroups, then one scan over the threads)
+  {
+    const int per = (grid + kReThreads - 1) / kReThreads;
+    const int b0 = tid * per, b1 = (b0 + per) < grid ? (b0 + per) : grid;
+    int s = 0;
+    for (int b = b0; b < b1; ++b) {
+      int c = 0;
+      for (int w = 0; w < r.W; ++w) c += r.fl_cnt[b * 16 + w];
+      pre[b + 1] = c;
+      s += c;
+    }
+    int incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int run = incl - s;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (int b = b0; b < b1; ++b) {
+      run += pre[b + 1];
+      pre[b + 1] = run;
+    }
+    if (tid == 0) pre[0] = 0;
+    __syncthreads();
   }
-  if (tid == 0) pre[0] = 0;
-  __syncthreads();
-  if (tid == 0)
-    for (int b = 1; b <= grid; ++b) pre[b] += pre[b - 1];
-  __syncthreads();
   const int F = pre[grid];
   const int nbatch = (F + kReRows - 1) / kReRows;
 
   double e_sum = 0.0;
   unsigned n_changed = 0, n_near = 0;
+  const int q4 = dp / 4;
+  const bool xbf = r.xbf16 != 0;
   for (int bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
     const int rb = (F - bt * kReRows) < kReRows ? (F - bt * kReRows) : kReRows;
     if (tid < rb) {   // listed row number f: its workgroup, wave, list position, slot
@@ -105,24 +128,15 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
       rowidx[tid] = r.flags[own];
     }
     __syncthreads();
-    // the batch's rows as float32 (exact for float32 and bfloat16 storage),
+    // the batch's rows as float64 (exact for float32 and bfloat16 storage),
     // zero beyond d and rb; 16-byte loads when d is a multiple of 4
-    const int q4 = dp / 4;
-    const bool xbf = r.xbf16 != 0;
     if (d == dp) {
-      for (int e0 = tid; e0 < kReRows * q4; e0 += kReBatch * kReThreads) {
-        float4 v[kReBatch];
-#pragma unroll
-        for (int t = 0; t < kReBatch; ++t) {
-          const int e = e0 + t * kReThreads, u = e / q4, k = (e - u * q4) * 4;
-          v[t] = (e < kReRows * q4 && u < rb) ? ld_x4(r.X, (int64_t)rowidx[u] * d + k, xbf)
-                                              : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int t = 0; t < kReBatch; ++t) {
-          const int e = e0 + t * kReThreads;
-          if (e < kReRows * q4) *(float4*)(xs + (size_t)e * 4) = v[t];
-        }
+      for (int e = tid; e < kReRows * q4; e += kReThreads) {
+        const int u = e / q4, k = (e - u * q4) * 4;
+        const float4 v = (u < rb) ? ld_x4(r.X, (int64_t)rowidx[u] * d + k, xbf) : make_float4(0.f, 0.f, 0.f, 0.f);
+        double2* dst = (double2*)(xs + (size_t)u * dp + k);
+        dst[0] = make_double2(v.x, v.y);
+        dst[1] = make_double2(v.z, v.w);
       }
     } else {
       for (int e = tid; e < kReRows * dp; e += kReThreads) {
@@ -132,12 +146,12 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
         xs[e] = v;
       }
     }
-    // rows wave + 4 m of the batch; centroid slot lane of each chunk
-    double bd[kReMR];
-    float bd2[kReMR];
+    // rows wave * kReMR + m of the batch; centroid slot lane of each chunk
+    double bd[kReMR], bd2[kReMR];
     int bj[kReMR];
 #pragma unroll
-    for (int m = 0; m < kReMR; ++m) { bd[m] = __builtin_inf(); bd2[m] = __builtin_inff(); bj[m] = -1; }
+    for (int m = 0; m < kReMR; ++m) { bd[m] = __builtin_inf(); bd2[m] = __builtin_inf(); bj[m] = -1; }
+    const double* xw = xs + (size_t)(wave * kReMR) * dp;
     for (int c0 = 0; c0 < K; c0 += kReCRows) {
       const int rows = (K - c0) < kReCRows ? (K - c0) : kReCRows;
       __syncthreads();
@@ -168,31 +182,33 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
         double acc[kReMR];
 #pragma unroll
         for (int m = 0; m < kReMR; ++m) acc[m] = 0.0;
+#pragma unroll 2
         for (int k = 0; k < dp; k += 4) {
           const float4 c4 = *(const float4*)(cr + k);
           const double cx = c4.x, cy = c4.y, cz = c4.z, cw = c4.w;
 #pragma unroll
           for (int m = 0; m < kReMR; ++m) {
-            const float4 x4 = *(const float4*)(xs + (wave + 4 * m) * dp + k);
-            double df = (double)x4.x - cx; acc[m] = fma(df, df, acc[m]);
-            df = (double)x4.y - cy; acc[m] = fma(df, df, acc[m]);
-            df = (double)x4.z - cz; acc[m] = fma(df, df, acc[m]);
-            df = (double)x4.w - cw; acc[m] = fma(df, df, acc[m]);
+            const double2 xa = *(const double2*)(xw + m * dp + k);
+            const double2 xb = *(const double2*)(xw + m * dp + k + 2);
+            double df = xa.x - cx; acc[m] = fma(df, df, acc[m]);
+            df = xa.y - cy; acc[m] = fma(df, df, acc[m]);
+            df = xb.x - cz; acc[m] = fma(df, df, acc[m]);
+            df = xb.y - cw; acc[m] = fma(df, df, acc[m]);
           }
         }
         const int j = c0 + lane;
 #pragma unroll
         for (int m = 0; m < kReMR; ++m) {
-          if (acc[m] < bd[m]) { bd2[m] = (float)bd[m]; bd[m] = acc[m]; bj[m] = j; }
-          else bd2[m] = fminf(bd2[m], (float)acc[m]);
+          if (acc[m] < bd[m]) { bd2[m] = bd[m]; bd[m] = acc[m]; bj[m] = j; }
+          else bd2[m] = fmin(bd2[m], acc[m]);
         }
       }
     }
 #pragma unroll
     for (int m = 0; m < kReMR; ++m) {
-      const int u = wave + 4 * m;
+      const int u = wave * kReMR + m;
       double dist, dist2;
-      const int j = wave_argmin2(bd[m], (double)bd2[m], bj[m], &dist, &dist2);
+      const int j = wave_argmin2(bd[m], bd2[m], bj[m], &dist, &dist2);
       if (u < rb) {
         const bool nt = near_tie(dist, dist2);
         if (lane == 0) {
