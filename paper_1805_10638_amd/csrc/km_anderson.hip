@@ -247,7 +247,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
   if (j >= a.K) return;
   const int d = a.d;
   const int64_t KD = (int64_t)a.K * d;
-  double n_c = 0.0, e_c = 0.0, n_f = 0.0, e_f = 0.0;
+  double n_c = 0.0, e_c = 0.0, n_f = 0.0, e_f = 0.0, s_c = 0.0, s_f = 0.0;
   for (int k = lane; k < d; k += kWave) {
     const int64_t e = (int64_t)j * d + k;
     const double g = a.G_last[e];
@@ -263,18 +263,31 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
       for (int q8 = 0; q8 < 8; ++q8)
         if (q0 + q8 < mt) v -= th[q0 + q8] * r[q8];
     }
-    put_centroid(a.C_cand, a.Cb_cand, KD, e, v, &n_c, &e_c);
-    put_centroid(a.C_fb, a.Cb_fb, KD, e, g, &n_f, &e_f);
+    const float fc = put_centroid(a.C_cand, a.Cb_cand, KD, e, v, &n_c, &e_c);
+    const float ff = put_centroid(a.C_fb, a.Cb_fb, KD, e, g, &n_f, &e_f);
+    if (a.C_ref) {   // shifts of the stored float32 values against the reference
+      const double r = a.C_ref[e];
+      s_c = fma((double)fc - r, (double)fc - r, s_c);
+      s_f = fma((double)ff - r, (double)ff - r, s_f);
+    }
   }
   n_c = wave_sum(n_c);
   e_c = wave_sum(e_c);
   n_f = wave_sum(n_f);
   e_f = wave_sum(e_f);
+  if (a.C_ref) {
+    s_c = wave_sum(s_c);
+    s_f = wave_sum(s_f);
+  }
   if (lane == 0) {
     a.nc_cand[j] = (float)n_c;
     a.nc_fb[j] = (float)n_f;
     if (a.Cb_cand) a.delta_cand[j] = (float)sqrt(e_c);
     if (a.Cb_fb) a.delta_fb[j] = (float)sqrt(e_f);
+    if (a.C_ref) {   // rounded up: upper bounds of the shifts
+      a.sh_cand[j] = sqrt(s_c) * (1.0 + 1e-12);
+      a.sh_fb[j] = sqrt(s_f) * (1.0 + 1e-12);
+    }
   }
 }
 

@@ -404,7 +404,7 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   a.lab = c->w.labels; a.lab_prev = nullptr; a.e_part = c->w.e_part; a.flags = c->w.flags; a.ctl = c->w.ctl;
   a.xbf16 = xbf; a.gemm_bf16 = gbf;
   a.shape = shape_for(c, gbf, xbf, d, K);
-  a.lb = bnd ? c->w.lb : nullptr; a.C_ref = bnd ? c->w.C_ref : nullptr; a.bounds = 0;
+  a.lb = bnd ? c->w.lb : nullptr; a.bounds = 0;
   // undecided rows of a deferring kernel: one re-check launch per pass
   a.fl_cnt = assign_list_mode(a) ? c->w.fl_cnt : nullptr;
   const bool relist = a.fl_cnt != nullptr;
@@ -430,6 +430,9 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   cb.delta_cand = gbf ? c->w.del_cand : nullptr;
   cb.C_fb = c->w.C_fb; cb.nc_fb = c->w.nc_fb; cb.Cb_fb = gbf ? c->w.Cb_fb : nullptr;
   cb.delta_fb = gbf ? c->w.del_fb : nullptr;
+  if (bnd) {   // shifts of the new centroids against the bounds' reference
+    cb.C_ref = c->w.C_ref; cb.sh_cand = c->w.shift; cb.sh_fb = c->w.shift + K;
+  }
 
   // ---- prologue: P^0 = Assign(C^0), G^0 = Update(P^0), F^0 = G^0 - C^0, C^1 = G^0 ----
   HIP_TRY(c, hipMemcpyAsync(c->w.C_tmp, C0, cbytes, hipMemcpyDeviceToDevice, q), "copy C0");
@@ -452,9 +455,11 @@ km_status kmeans_solve(km_ctx* c, const void* X, km_xtype xt, int64_t N, int32_t
   AssignArgs ac = a;
   ac.C = c->w.C_cand; ac.nc = c->w.nc_cand; ac.Cb = gbf ? c->w.Cb_cand : nullptr;
   ac.delta = gbf ? c->w.del_cand : nullptr; ac.e_part = c->w.e_part; ac.bounds = bnd ? 1 : 0;
+  ac.shift = bnd ? c->w.shift : nullptr;
   AssignArgs af = a;
   af.C = c->w.C_fb; af.nc = c->w.nc_fb; af.Cb = gbf ? c->w.Cb_fb : nullptr;
   af.delta = gbf ? c->w.del_fb : nullptr; af.e_part = c->w.e_part + n_part; af.bounds = bnd ? 1 : 0;
+  af.shift = bnd ? c->w.shift + K : nullptr;
   const RecheckArgs rc = recheck_args(ac, c->w.e_part + grid);
   const RecheckArgs rf = recheck_args(af, c->w.e_part + n_part + grid);
   FinalizeArgs fi = f;

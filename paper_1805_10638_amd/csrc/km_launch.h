@@ -31,12 +31,13 @@ struct AssignArgs {
   // Row bounds (Hamerly-style, float32 GEMM with LDS-resident centroids only;
   // null / 0 elsewhere).  lb: lower bounds of the distance from each row to
   // every centroid other than its own, 3 x N (one slice per label buffer;
-  // the plain role writes slice 0).  C_ref: the centroids the bounds of the
-  // previous labels refer to.  bounds = 1: candidate and fall-back passes
-  // skip the rows whose bound proves the previous label.
+  // the plain role writes slice 0).  bounds = 1: candidate and fall-back
+  // passes skip the rows whose bound proves the previous label; shift: K
+  // upper bounds of ||c_j - c_ref_j|| of this pass's centroids against the
+  // centroids the previous labels' bounds refer to.
   float* lb;
-  const float* C_ref;
   int bounds;
+  const double* shift;
   // List mode (single-instance launches): rows the GEMM bound cannot decide
   // stay in the per-wave lists for k_recheck, whose list lengths go to
   // fl_cnt[workgroup * 16 + wave]; null: the workgroups re-check their own.
@@ -186,6 +187,9 @@ struct CombineArgs {
   int K, d, cap;
   float* C_cand; float* nc_cand; uint16_t* Cb_cand; float* delta_cand;
   float* C_fb; float* nc_fb; uint16_t* Cb_fb; float* delta_fb;
+  // row bounds (nullable): upper bounds of ||c_j - C_ref_j|| of the new
+  // candidate and fall-back centroids (float64, K each)
+  const float* C_ref; double* sh_cand; double* sh_fb;
   int* done_out;          // nullable: pinned host slot that receives ctl->done (solver iterations)
 };
 // ev1 (nullable): takes the end time of the combine's dispatch

@@ -63,6 +63,7 @@ struct Ws {
   int* m_traj = nullptr;        // it ints (m after the dynamic-m rule per iteration)
   float* lb = nullptr;          // 3 x N row bounds (bnd only)
   float* C_ref = nullptr;       // K x d reference centroids of the row bounds (bnd only)
+  double* shift = nullptr;      // 2 x K centroid shifts against C_ref: candidate, fall-back (bnd only)
   int max_items = 0, nblk = 0, fin_grid = 0;
 };
 
@@ -113,6 +114,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
   const size_t o_mt = take((size_t)s.it * 4);
   const size_t o_lb = take(s.bnd ? (size_t)3 * N * 4 : 0);
   const size_t o_cr = take(s.bnd ? (size_t)KD * 4 : 0);
+  const size_t o_sh = take(s.bnd ? (size_t)2 * s.K * 8 : 0);
   if (base && w) {
     char* b = base;
     w->ctl = (Ctl*)(b + o_ctl);
@@ -152,6 +154,7 @@ inline size_t ws_layout(const Shape& s, char* base, Ws* w) {
     w->m_traj = s.it ? (int*)(b + o_mt) : nullptr;
     w->lb = s.bnd ? (float*)(b + o_lb) : nullptr;
     w->C_ref = s.bnd ? (float*)(b + o_cr) : nullptr;
+    w->shift = s.bnd ? (double*)(b + o_sh) : nullptr;
     w->max_items = max_items;
     w->nblk = nblk;
     w->fin_grid = fin_grid;
