@@ -68,16 +68,6 @@ RecheckArgs recheck_args(const AssignArgs& a, double* e_part) {
   return r;
 }
 
-// List-mode launches of bf16 kernels with streamed centroids run the
-// double-buffered variant when d fills the padded width (every 16-byte
-// vector of a row is real).  The variant has the same row groups and LDS
-// size, so the grid (from the base kernel) and the re-check's slot layout do
-// not change.
-static const void* launch_fn(const KernelPick& p, const AssignArgs& a) {
-  if (a.fl_cnt && p.fn_db && !p.resident && a.d == p.dp && p.db_rows > 0) return p.fn_db;
-  return p.fn;
-}
-
 // Kernels whose LDS budget exceeds the default 64 KB must say so once.
 static hipError_t allow_lds(const KernelPick& p) {
   if (p.lds <= 64 * 1024) return hipSuccess;
@@ -88,8 +78,6 @@ static hipError_t allow_lds(const KernelPick& p) {
   hipError_t e = hipFuncSetAttribute(p.fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e == hipSuccess && p.fn_batch && p.fn_batch != p.fn)
     e = hipFuncSetAttribute(p.fn_batch, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e == hipSuccess && p.fn_db)
-    e = hipFuncSetAttribute(p.fn_db, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
   if (n_done < 64) done[n_done++] = p.fn;
   return hipSuccess;
@@ -143,9 +131,8 @@ hipError_t launch_assign(const AssignArgs& a, Role role, hipStream_t s, hipEvent
   hipError_t e = allow_lds(p);
   if (e != hipSuccess) return e;
   clear_pending_error();
-  const void* fn = launch_fn(p, a);
-  if (ev0 || ev1) return hipExtLaunchKernel(fn, dim3(grid), dim3(p.threads), params, p.lds, s, ev0, ev1, 0);
-  return hipLaunchKernel(fn, dim3(grid), dim3(p.threads), params, p.lds, s);
+  if (ev0 || ev1) return hipExtLaunchKernel(p.fn, dim3(grid), dim3(p.threads), params, p.lds, s, ev0, ev1, 0);
+  return hipLaunchKernel(p.fn, dim3(grid), dim3(p.threads), params, p.lds, s);
 }
 
 // ---------------------------------------------------------------------------

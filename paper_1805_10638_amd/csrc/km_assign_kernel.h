@@ -50,8 +50,6 @@ namespace km {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short i16x8 __attribute__((ext_vector_type(8)));
-// LDS pointer type of the LDS-DMA loads (global_load_lds)
-typedef __attribute__((address_space(3))) void lds_void;
 
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
@@ -240,38 +238,13 @@ struct Tile {
     int c = ((LB - HEAD) / (ROW_BYTES + 4)) & ~15;
     return c < kpad ? c : kpad;
   }
-  // Double-buffered chunks (bf16 GEMM with streamed centroids): a buffer of
-  // kc rows holds the rows and their squared norms, each rounded up to whole
-  // LDS-DMA blocks (1 KB of 16-byte loads, 256 B of 4-byte loads per wave);
-  // db_rows(K) rows per buffer (0: none fits).
-  static __host__ __device__ size_t db_rows_bytes(int kc) {
-    return ((size_t)kc * ROW_BYTES + 1023) & ~(size_t)1023;
-  }
-  static __host__ __device__ size_t db_buf(int kc) {
-    return db_rows_bytes(kc) + (((size_t)kc * 4 + 255) & ~(size_t)255);
-  }
-  static __host__ __device__ int db_rows(int K) {
-    if (!GBF) return 0;
-    int c = ((LB - HEAD) / 2 / (ROW_BYTES + 4)) & ~15;
-    while (c >= 16 && 2 * db_buf(c) > (size_t)(LB - HEAD)) c -= 16;
-    return c >= 16 ? c : 0;
-  }
-  // the chunk (or the deferred re-check) area of the kernels that stage
-  // synchronously
-  static __host__ __device__ size_t chunk_area(int K) {
+  static __host__ __device__ size_t area_bytes(int K) {
     const size_t c = (size_t)chunk_rows(K) * (ROW_BYTES + 4);
     return c > (size_t)DEF_MIN ? c : (size_t)DEF_MIN;
   }
-  // LDS area of every variant: the double buffer may need a little more
-  static __host__ __device__ size_t area_bytes(int K) {
-    size_t c = chunk_area(K);
-    const int kpad = (K + 15) & ~15;
-    if (GBF && chunk_rows(K) < kpad && db_rows(K) > 0 && 2 * db_buf(db_rows(K)) > c) c = 2 * db_buf(db_rows(K));
-    return c;
-  }
   static __host__ __device__ size_t lds_bytes(int K) { return HEAD + area_bytes(K); }
   // float32 centroid rows per chunk of the deferred re-check (at least 16)
-  static __host__ __device__ int def_rows(int K) { return (int)((chunk_area(K) - DEF_FIXED) / (LD * 4)); }
+  static __host__ __device__ int def_rows(int K) { return (int)((area_bytes(K) - DEF_FIXED) / (LD * 4)); }
 };
 
 // A operand of one 16-centroid tile (rows [tt, tt+16) of the LDS chunk): this
@@ -286,18 +259,11 @@ struct AOp {
   float av[GBF ? 1 : KS];                     // float32 row
 };
 
-// raw: ncs holds ||c||^2 as loaded (double-buffered chunks): the start values
-// are formed here, -inf for the padding rows from centroid jb + 4 g on.
 template <int KS, bool GBF, int LB>
 __device__ __forceinline__ void load_aop(const float* Cs, const uint16_t* Cbs, const float* ncs, int tt,
-                                         int g, int r16, AOp<KS, GBF, LB>& o, bool raw = false, int jb = 0,
-                                         int K = 0) {
+                                         int g, int r16, AOp<KS, GBF, LB>& o) {
   using T = Tile<KS, GBF, LB>;
   o.n4 = *(const f32x4*)(ncs + tt + 4 * g);
-  if (raw) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o.n4[r] = (jb + 4 * g + r < K) ? -0.5f * o.n4[r] : -__builtin_inff();
-  }
   if constexpr (GBF) {
     const uint16_t* cr = Cbs + (tt + r16) * T::LDB + g * KS;
 #pragma unroll
@@ -394,7 +360,7 @@ constexpr int assign_wpe() {
 // per workgroup (they share one LDS copy of the centroids); LB: LDS bytes.
 // bx / gx: this workgroup's index and the number of workgroups working on
 // this instance.
-template <int KS, int SB, int W, bool XBF, bool GBF, int LB, bool BND = false, bool DB = false>
+template <int KS, int SB, int W, bool XBF, bool GBF, int LB, bool BND = false>
 __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx) {
   constexpr int NT = 64 * W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -570,50 +536,8 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       ncs[rr] = (j < K) ? -0.5f * a.nc[j] : -__builtin_inff();
     }
   };
-  if (!DB && resident) {
+  if (resident) {
     stage(0, Kpad);
-    __syncthreads();
-  }
-  // DB (streamed bf16 centroids, whole 16-byte vectors, list mode, so no
-  // re-check shares the chunk area; the host launches it only then): two
-  // buffers of kc2 rows.  While the tiles of
-  // the current chunk run, the next chunk (the first again when the
-  // workgroup has another row group) streams into the other buffer by
-  // LDS-DMA loads (global_load_lds: lane l of a wave writes the 16 bytes at
-  // base + 16 l), so a chunk costs one barrier and no exposed L2 latency.
-  // A row of the buffer is SPR 16-byte slots: hi, lo, one pad slot.
-  constexpr int SPR = T::ROW_BYTES / 16;
-  const int kc2 = DB ? T::db_rows(K) : 0;
-  const size_t dbb = DB ? T::db_buf(kc2) : 0;
-  int cbuf = 0;               // buffer of the current chunk
-  bool more_groups = false;   // the workgroup has another row group after this one
-  // Issue the loads of the chunk from centroid c0n into buffer buf: the rows,
-  // then their squared norms (raw: load_aop forms the start values).
-  auto dma_chunk = [&](int c0n, unsigned char* buf) {
-    const int rows = (Kpad - c0n) < kc2 ? (Kpad - c0n) : kc2;
-    const int S = rows * SPR;
-    const int64_t KD = (int64_t)K * d;
-    for (int q = wave; q * 64 < S; q += W) {
-      const int sl = q * 64 + lane, r = sl / SPR, p = sl - r * SPR, j = c0n + r;
-      // slots past the chunk, pad slots and rows past K load a valid dummy
-      const uint16_t* src = a.Cb;
-      if (sl < S && j < K && p < 2 * (DP / 8)) {
-        const int half = p >= DP / 8 ? 1 : 0;
-        src = a.Cb + half * KD + (int64_t)j * d + 8 * (p - half * (DP / 8));
-      }
-      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(buf + q * 1024), 16, 0, 0);
-    }
-    unsigned char* nb = buf + T::db_rows_bytes(kc2);
-    for (int q = wave; q * 64 < rows; q += W) {
-      const int j = c0n + q * 64 + lane;
-      __builtin_amdgcn_global_load_lds((const void*)(a.nc + (j < K ? j : 0)), (lds_void*)(nb + q * 256), 4, 0,
-                                       0);
-    }
-  };
-  auto db_ncs = [&](unsigned char* buf) { return (const float*)(buf + T::db_rows_bytes(kc2)); };
-  if constexpr (DB) {
-    dma_chunk(0, area);
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's loads have landed in LDS
     __syncthreads();
   }
   // Row bounds in use (candidate and fall-back passes, centroids resident):
@@ -899,23 +823,12 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
 #pragma unroll
     for (int s = 0; s < U; ++s) { best[s] = -__builtin_inff(); sec[s] = -__builtin_inff(); bidx[s] = 0; }
 
-    const int csz = DB ? kc2 : kchunk;
-    for (int c0 = 0; c0 < Kpad; c0 += csz) {
-      const int rows = (Kpad - c0) < csz ? (Kpad - c0) : csz;
-      const uint16_t* Cbc = Cbs;
-      const float* ncc = ncs;
-      if constexpr (DB) {
-        unsigned char* cur = area + cbuf * dbb;
-        Cbc = (const uint16_t*)cur;
-        ncc = db_ncs(cur);
-        const int cn = c0 + kc2 < Kpad ? c0 + kc2 : (more_groups ? 0 : -1);
-        if (cn >= 0) dma_chunk(cn, area + (cbuf ^ 1) * dbb);
-      } else {
-        if (!resident) {
-          __syncthreads();
-          stage(c0, rows);
-          __syncthreads();
-        }
+    for (int c0 = 0; c0 < Kpad; c0 += kchunk) {
+      const int rows = (Kpad - c0) < kchunk ? (Kpad - c0) : kchunk;
+      if (!resident) {
+        __syncthreads();
+        stage(c0, rows);
+        __syncthreads();
       }
       // Tiles in pairs with two operand buffers: the loads of tile t + 1 are
       // issued (and pinned there by a scheduling barrier) before the MFMAs of
@@ -944,28 +857,21 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       AO opa;
       if constexpr (kPairOps) {
         AO opb;
-        load_aop<KS, GBF, LB>(Cs, Cbc, ncc, 0, g, r16, opa, DB, c0, K);
+        load_aop<KS, GBF, LB>(Cs, Cbs, ncs, 0, g, r16, opa);
         for (int tt = 0; tt < rows; tt += 32) {
-          load_aop<KS, GBF, LB>(Cs, Cbc, ncc, tt + 16 < rows ? tt + 16 : tt, g, r16, opb, DB,
-                                c0 + (tt + 16 < rows ? tt + 16 : tt), K);
+          load_aop<KS, GBF, LB>(Cs, Cbs, ncs, tt + 16 < rows ? tt + 16 : tt, g, r16, opb);
           __builtin_amdgcn_sched_barrier(0);
           step(opa, tt);
           if (tt + 16 >= rows) break;
-          load_aop<KS, GBF, LB>(Cs, Cbc, ncc, tt + 32 < rows ? tt + 32 : tt + 16, g, r16, opa, DB,
-                                c0 + (tt + 32 < rows ? tt + 32 : tt + 16), K);
+          load_aop<KS, GBF, LB>(Cs, Cbs, ncs, tt + 32 < rows ? tt + 32 : tt + 16, g, r16, opa);
           __builtin_amdgcn_sched_barrier(0);
           step(opb, tt + 16);
         }
       } else {
         for (int tt = 0; tt < rows; tt += 16) {
-          load_aop<KS, GBF, LB>(Cs, Cbc, ncc, tt, g, r16, opa, DB, c0 + tt, K);
+          load_aop<KS, GBF, LB>(Cs, Cbs, ncs, tt, g, r16, opa);
           step(opa, tt);
         }
-      }
-      if constexpr (DB) {   // the next chunk is complete and visible after the barrier
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        __syncthreads();
-        cbuf ^= 1;
       }
     }
 
@@ -1232,13 +1138,12 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
   } else {
     for (int64_t grp = bx; grp < groups; grp += gx) {
-      if constexpr (DB) more_groups = grp + gx < groups;
       unit(std::integral_constant<int, SB>{}, grp * group_rows + (int64_t)wave * (16 * SB), nullptr, 0);
       // With streamed centroids the chunk area is free here: re-check full
       // batches now, so that the re-check overlaps other workgroups' MFMA work
       // instead of piling up after the last row group (bf16 GEMM kernels; in
       // the float32 kernels the extra live registers of this call would spill).
-      if (!DB && kInterleave && defer && !resident && !a.fl_cnt) {
+      if (kInterleave && defer && !resident && !a.fl_cnt) {
         int* wc = wcnt + (nb & 1) * 16;   // two buffers: a slow wave may still read the previous one
         if (lane == 0) wc[wave] = nfl;
         __syncthreads();
@@ -1250,7 +1155,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
 
   if (a.fl_cnt) {   // list mode: the rows stay listed for k_recheck
     if (lane == 0) a.fl_cnt[bx * 16 + wave] = defer ? nfl : 0;
-  } else if (!DB && defer) {   // the remaining listed rows
+  } else if (defer) {   // the remaining listed rows
     int* wc = wcnt + (nb & 1) * 16;
     if (lane == 0) wc[wave] = nfl;
     __syncthreads();
@@ -1287,14 +1192,6 @@ void k_assign_bnd(AssignArgs a) {
   assign_body<KS, SB, W, XBF, GBF, LB, true>(a, blockIdx.x, gridDim.x);
 }
 
-// Single instance in list mode with double-buffered LDS-DMA chunks (bf16
-// GEMM, streamed centroids, d equal to the padded width 4 KS).
-template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(assign_wpe<KS, SB, W, XBF, GBF>())))
-void k_assign_db(AssignArgs a) {
-  assign_body<KS, SB, W, XBF, GBF, LB, false, true>(a, blockIdx.x, gridDim.x);
-}
-
 // Batched launch: the grid is the concatenation of every instance's slice.
 template <int KS, int SB, int W, bool XBF, bool GBF, int LB>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(assign_wpe<KS, SB, W, XBF, GBF>())))
@@ -1309,9 +1206,6 @@ struct KernelPick {
   const void* fn = nullptr;        // k_assign
   const void* fn_batch = nullptr;  // k_assign_batch
   const void* fn_bnd = nullptr;    // k_assign_bnd (float32 GEMM only)
-  const void* fn_db = nullptr;     // k_assign_db (bf16 GEMM only)
-  int db_rows = 0;                 // its rows per chunk buffer for the K of the call (0: none)
-  int dp = 0;                      // padded width 4 KS: k_assign_db needs d == dp
   bool resident = false;           // the K centroids fit the LDS budget at once
   size_t lds_bnd = 0;              // LDS bytes of k_assign_bnd (lds + the row queues)
   int rows = 0;                    // samples per row group (16 * SB * W)
@@ -1330,13 +1224,9 @@ KernelPick make_pick(int K) {
   p.lb = LB;
   p.lds = Tile<KS, GBF, LB>::lds_bytes(K);
   p.resident = Tile<KS, GBF, LB>::chunk_rows(K) >= ((K + 15) & ~15);
-  p.dp = 4 * KS;
   if constexpr (!GBF) {
     p.fn_bnd = (const void*)&k_assign_bnd<KS, SB, W, XBF, GBF, LB>;
     p.lds_bnd = p.lds + (size_t)W * 32 * SB * 4;
-  } else {
-    p.fn_db = (const void*)&k_assign_db<KS, SB, W, XBF, GBF, LB>;
-    p.db_rows = Tile<KS, GBF, LB>::db_rows(K);
   }
   return p;
 }

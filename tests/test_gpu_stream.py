@@ -1,11 +1,9 @@
 """Streamed bfloat16 centroids: K exceeds what one LDS chunk holds, so the
-centroid pair streams through LDS.  List-mode launches (kmeans_g, the solver)
-then run the double-buffered variant, whose next chunk arrives by LDS-DMA
-loads while the current chunk's tiles run.  Checked against the FP64 oracle
-and against the float32 GEMM (an independent kernel) on every row, for each
-tile shape, with ragged final chunks (K not a multiple of the chunk), padding
-rows (K not a multiple of 16) and several row groups per workgroup (so the
-first chunk of the next row group is prefetched across the epilogue)."""
+centroid pair streams through LDS chunk by chunk and the undecided rows go
+to the pass-wide re-check.  Checked against the FP64 oracle and against the
+float32 GEMM (an independent kernel) on every row, for each tile shape, with
+ragged final chunks (K not a multiple of the chunk), padding rows (K not a
+multiple of 16) and several row groups per workgroup."""
 
 import numpy as np
 import pytest
