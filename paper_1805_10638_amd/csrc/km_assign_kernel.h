@@ -97,6 +97,49 @@ __device__ __forceinline__ void load_chunk(const void* X, int64_t i, int d, int 
   }
 }
 
+// load_chunk for U rows at once (ic: valid row indices; callers map rows
+// past N to row 0 and discard their results).  The choice between 16-byte
+// and per-column loads is made once for all rows, so every load of the U
+// rows is in flight before the first is used; a branch per row would make
+// the compiler wait for each row's loads before issuing the next row's.
+template <int U, int KS, bool XBF>
+__device__ __forceinline__ void load_rows(const void* X, const int64_t (&ic)[U], int d, int k0, bool vec,
+                                          float (&out)[U][KS]) {
+  if constexpr (KS % 4 == 0) {
+    if (vec) {
+#pragma unroll
+      for (int s = 0; s < U; ++s) {
+        if constexpr (XBF) {
+          const uint2* p = (const uint2*)((const uint16_t*)X + ic[s] * d + k0);
+#pragma unroll
+          for (int q = 0; q < KS / 4; ++q) {
+            const uint2 v = p[q];
+            out[s][4 * q + 0] = __uint_as_float(v.x << 16);
+            out[s][4 * q + 1] = __uint_as_float(v.x & 0xFFFF0000u);
+            out[s][4 * q + 2] = __uint_as_float(v.y << 16);
+            out[s][4 * q + 3] = __uint_as_float(v.y & 0xFFFF0000u);
+          }
+        } else {
+          const float4* p = (const float4*)((const float*)X + ic[s] * d + k0);
+#pragma unroll
+          for (int q = 0; q < KS / 4; ++q) {
+            const float4 v = p[q];
+            out[s][4 * q + 0] = v.x;
+            out[s][4 * q + 1] = v.y;
+            out[s][4 * q + 2] = v.z;
+            out[s][4 * q + 3] = v.w;
+          }
+        }
+      }
+      return;
+    }
+  }
+  // other widths: one row at a time, which keeps the registers of the
+  // loads in flight to one row's
+#pragma unroll
+  for (int s = 0; s < U; ++s) load_chunk<KS, XBF>(X, ic[s], d, k0, false, out[s]);
+}
+
 // Wave reduction of per-lane (smallest distance bd, its index bj, second
 // smallest distance bd2): lowest index on ties; the second smallest counts a
 // second centroid at the smallest distance (then it equals the smallest).
@@ -446,31 +489,37 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   const float cb = GBF ? cmax * 1.008f : cmax;
 
   // Stage centroid rows [c0, c0 + rows) into LDS (zero padding beyond d and K).
-  // When every vector of a row is real (d = dp), each thread issues
-  // kStageBatch 16-byte loads before it writes any of them, so a chunk costs
-  // a few L2 round trips instead of one per vector (2 where registers are
-  // short: float32 rows on the bf16 GEMM at 256 dims, 4-wave-per-SIMD tiles,
-  // and float32 tiles up to 64 dims, whose centroids are mostly resident and
-  // which would otherwise lose a wave per SIMD).  Other widths take one
-  // vector at a time with per-element bounds.
+  // When every vector of a row is real (d = dp), each thread issues several
+  // 16-byte loads before it writes any of them, so a chunk costs a few L2
+  // round trips instead of one per vector: 8, or for chunks staged inside
+  // the row-group loop 2 where registers are short there (float32 rows on
+  // the bf16 GEMM at 256 dims, 4-wave-per-SIMD tiles, and float32 tiles up to
+  // 64 dims, which would otherwise lose a wave per SIMD).  Other widths take
+  // one vector at a time with per-element bounds.
   constexpr int kWpe = assign_wpe<KS, SB, W, XBF, GBF>();
   constexpr bool kShortRegs = (GBF && !XBF && KS >= 64) || kWpe >= 4 || (!GBF && KS <= 16);
   constexpr int kStageBatch = kShortRegs ? 2 : 8;
-  // float32 rows [c0, c0 + rows) of C into dst (row stride LD, zero beyond d)
-  auto stage_f32 = [&](float* dst, int c0, int rows) {
+  // The one staging of resident centroids runs before any row is in
+  // registers, so it always keeps 8 loads in flight.
+  using StageAll = std::integral_constant<int, 8>;
+  using StageLoop = std::integral_constant<int, kStageBatch>;
+  // float32 rows [c0, c0 + rows) of C into dst (row stride LD, zero beyond d);
+  // bt: 16-byte loads in flight per thread
+  auto stage_f32 = [&](auto bt, float* dst, int c0, int rows) {
+    constexpr int SBt = decltype(bt)::value;
     const int total = rows * (DP / 4);
     if (d == DP) {
-      for (int e0 = tid; e0 < total; e0 += kStageBatch * NT) {
-        float4 v[kStageBatch];
+      for (int e0 = tid; e0 < total; e0 += SBt * NT) {
+        float4 v[SBt];
 #pragma unroll
-        for (int b = 0; b < kStageBatch; ++b) {
+        for (int b = 0; b < SBt; ++b) {
           const int e = e0 + b * NT;
           const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4, j = c0 + rr;
           v[b] = (e < total && j < K) ? *(const float4*)(a.C + (int64_t)j * d + c4)
                                       : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int b = 0; b < kStageBatch; ++b) {
+        for (int b = 0; b < SBt; ++b) {
           const int e = e0 + b * NT;
           if (e < total) {
             const int rr = e / (DP / 4), c4 = (e - rr * (DP / 4)) * 4;
@@ -491,16 +540,17 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       }
     }
   };
-  auto stage = [&](int c0, int rows) {
+  auto stage = [&](auto bt, int c0, int rows) {
+    constexpr int SBt = decltype(bt)::value;
     if constexpr (GBF) {
       const int64_t KD = (int64_t)K * d;
       constexpr int V = DP / 8;   // 8-element vectors per half row
       const int total = rows * 2 * V;
       if (d == DP) {
-        for (int e0 = tid; e0 < total; e0 += kStageBatch * NT) {
-          i16x8 v[kStageBatch];
+        for (int e0 = tid; e0 < total; e0 += SBt * NT) {
+          i16x8 v[SBt];
 #pragma unroll
-          for (int b = 0; b < kStageBatch; ++b) {
+          for (int b = 0; b < SBt; ++b) {
             const int e = e0 + b * NT;
             const int rr = e / (2 * V), rem = e - rr * (2 * V);
             const int half = rem >= V ? 1 : 0, c8 = (rem - half * V) * 8, j = c0 + rr;
@@ -508,7 +558,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
                                         : i16x8{0, 0, 0, 0, 0, 0, 0, 0};
           }
 #pragma unroll
-          for (int b = 0; b < kStageBatch; ++b) {
+          for (int b = 0; b < SBt; ++b) {
             const int e = e0 + b * NT;
             if (e < total) {
               const int rr = e / (2 * V), rem = e - rr * (2 * V);
@@ -529,7 +579,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
         }
       }
     } else {
-      stage_f32(Cs, c0, rows);
+      stage_f32(bt, Cs, c0, rows);
     }
     for (int rr = tid; rr < rows; rr += NT) {
       const int j = c0 + rr;
@@ -537,7 +587,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
   };
   if (resident) {
-    stage(0, Kpad);
+    stage(StageAll{}, 0, Kpad);
     __syncthreads();
   }
   // Row bounds in use (candidate and fall-back passes, centroids resident):
@@ -670,7 +720,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       for (int c0 = 0; c0 < K; c0 += crows) {
         const int rows = (K - c0) < crows ? (K - c0) : crows;
         __syncthreads();
-        stage_f32(cc, c0, rows);
+        stage_f32(StageLoop{}, cc, c0, rows);
         __syncthreads();
         for (int jj = cs; jj < rows; jj += S) {
           const float* cr = cc + jj * LD;
@@ -767,37 +817,40 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       if (qrows) ii[s] = (16 * s + r16 < qcnt) ? (int64_t)qrows[16 * s + r16] : a.N;
       else ii[s] = row0 + 16 * s + r16;
     }
-    // Sample rows of this wave, kept in registers.
+    // Sample rows of this wave, kept in registers.  Rows past N load row 0
+    // (their results are discarded), so no load waits behind a branch and
+    // the loads of all U blocks are in flight together.
+    int64_t ic[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) ic[s] = ii[s] < a.N ? ii[s] : 0;
     float xv[U][KF ? KS : 1];
     i16x8 xbv[U][NB];
     i16x8 xlv[U][XLO ? NB : 1];
     float xres[U];  // ||x - hi - lo||^2 lane partial (XLO)
 #pragma unroll
-    for (int s = 0; s < U; ++s) {
-      xres[s] = 0.f;
-      const int64_t i = ii[s];
-      if constexpr (GBF && XBF) {
-        const uint16_t* xr = (const uint16_t*)a.X + i * d + g * KS;
+    for (int s = 0; s < U; ++s) xres[s] = 0.f;
+    if constexpr (GBF && XBF) {
+#pragma unroll
+      for (int s = 0; s < U; ++s) {
+        const uint16_t* xr = (const uint16_t*)a.X + ic[s] * d + g * KS;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-          if (i < a.N && vec) {
+          if (vec) {
             xbv[s][q] = *(const i16x8*)(xr + 8 * q);
           } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
               const int k = g * KS + 8 * q + e;
-              xbv[s][q][e] = (i < a.N && k < d) ? (short)xr[8 * q + e] : (short)0;
+              xbv[s][q][e] = (k < d) ? (short)xr[8 * q + e] : (short)0;
             }
           }
         }
-      } else if constexpr (XLO) {
-        float t[KS];
-        if (i < a.N) {
-          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, t);
-        } else {
+      }
+    } else if constexpr (XLO) {
 #pragma unroll
-          for (int q = 0; q < KS; ++q) t[q] = 0.f;
-        }
+      for (int s = 0; s < U; ++s) {
+        float t[KS];
+        load_chunk<KS, XBF>(a.X, ic[s], d, g * KS, vec, t);
 #pragma unroll
         for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -808,14 +861,9 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
             xlv[s][q][e] = (short)l;
             xres[s] = fmaf(r, r, xres[s]);
           }
-      } else {
-        if (i < a.N) {
-          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xv[s]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < KS; ++q) xv[s][q] = 0.f;
-        }
       }
+    } else {
+      load_rows<U, KS, XBF>(a.X, ic, d, g * KS, vec, xv);
     }
 
     float best[U], sec[U];
@@ -827,7 +875,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       const int rows = (Kpad - c0) < kchunk ? (Kpad - c0) : kchunk;
       if (!resident) {
         __syncthreads();
-        stage(c0, rows);
+        stage(StageLoop{}, c0, rows);
         __syncthreads();
       }
       // Tiles in pairs with two operand buffers: the loads of tile t + 1 are
@@ -876,6 +924,11 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
 
     // Epilogue: combine the 4 lane groups, flag near ties, exact energy terms.
+    // The previous labels (changed-row count) of all U blocks are loaded
+    // first, together, and used at the end.
+    int pv[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) pv[s] = prev != nullptr ? prev[ii[s] < a.N ? ii[s] : 0] : -1;
     int bi_s[U];
     bool fl_s[U];
     double term_s[U];
@@ -907,12 +960,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
 #pragma unroll
         for (int q = 0; q < KS; ++q) xe[q] = bf_elem(xbv[s][q >> 3], q & 7);
       } else {
-        if (valid) {
-          load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xe);
-        } else {
-#pragma unroll
-          for (int q = 0; q < KS; ++q) xe[q] = 0.f;
-        }
+        load_chunk<KS, XBF>(a.X, i < a.N ? i : 0, d, g * KS, vec, xe);
       }
       float xs = 0.f;
 #pragma unroll
@@ -1015,7 +1063,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       bool ch = false;
       if (mine) {
         rho[i] = bi_s[s];
-        ch = (prev != nullptr) && (prev[i] != bi_s[s]);
+        ch = (prev != nullptr) && (pv[s] != bi_s[s]);
         if constexpr (BND) {
           if (lbo) lbo[i] = sqrt_down(l2_s[s]);
         }
@@ -1060,23 +1108,23 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
         nq = rest;
       };
       for (; b < b1; b += SB) {
+        // rows past the range load row 0 (not used): no load behind a branch
         float xr[SB][KS];
         int ar[SB];
         float lr[SB];
-        int64_t ir[SB];
+        int64_t ir[SB], ic[SB];
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
           const int64_t i = (b + s) * 16 + r16;
           const bool valid = b + s < b1 && i < a.N;
           ir[s] = valid ? i : a.N;
-          if (valid) {
-            load_chunk<KS, XBF>(a.X, i, d, g * KS, vec, xr[s]);
-          } else {
+          ic[s] = valid ? i : 0;
+        }
+        load_rows<SB, KS, XBF>(a.X, ic, d, g * KS, vec, xr);
 #pragma unroll
-            for (int q2 = 0; q2 < KS; ++q2) xr[s][q2] = 0.f;
-          }
-          ar[s] = valid ? prev[i] : 0;
-          lr[s] = valid ? lbi[i] : 0.f;
+        for (int s = 0; s < SB; ++s) {
+          ar[s] = prev[ic[s]];
+          lr[s] = lbi[ic[s]];
         }
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
