@@ -174,6 +174,26 @@ def main():
         assign_n += st.assign_launches
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    # With row bounds the candidate launches mostly filter rows; beside them,
+    # outside the timed region, a few solves without bounds give the dense
+    # pass (all N rows through the MFMA GEMM) its own roofline.
+    dense = None
+    if args.bounds:
+        d_ms, d_n = 0.0, 0
+        for s in range(args.warmup, args.warmup + min(3, args.steps)):
+            st = km.kmeans_solve(Xd, inits[s], m_max=w["m_max"], tol=w["tol"], max_iter=w["max_iter"],
+                                 ctx=ctx, out=(Cout, rho), bounds=False)[4]
+            d_ms += st.assign_ms
+            d_n += st.assign_launches
+        torch.cuda.synchronize()
+        d_s = (d_ms / 1e3) / max(d_n, 1)
+        d_flops = 2.0 * w["N"] * w["K"] * w["d"]
+        dense = {"kernel": "assignment without bounds (all rows through the GEMM, candidate role)",
+                 "bound": "mfma", "achieved": d_flops / d_s / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS,
+                 "unit": "TFLOP/s", "frac": d_flops / d_s / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+                 "traffic": TRAFFIC_BYTES_PER_LAUNCH, "avg_launch_us": d_s * 1e6, "launches": d_n,
+                 "flop_per_launch": d_flops}
     ctx.set_timing(False)
 
     N, d, K = w["N"], w["d"], w["K"]
@@ -219,7 +239,8 @@ def main():
         "rejected_mean": statistics.mean(rej),
         "recheck_rows_per_pass": sum(flagged) / max(sum(passes), 1),
         "roofline": {
-            "kernel": "assignment (k_assign, candidate role)",
+            "kernel": ("assignment with row bounds (k_assign_bnd, candidate role; GEMM rows only count)"
+                       if args.bounds else "assignment (k_assign, candidate role)"),
             "bound": "mfma",
             "achieved": achieved,
             "peak": FP32_MFMA_PEAK_TFLOPS,
@@ -232,6 +253,8 @@ def main():
             "gemm_rows_per_pass": rows_per_pass,
         },
     }
+    if dense is not None:
+        out["roofline_dense"] = dense
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, synth.init_centroids(X, K, 0),
                                            statistics.mean(passes), args.cpu_seconds)
@@ -560,6 +583,7 @@ def served_workload(args, km, synth, torch):
     backlog_at_end = None
     t_start = time.perf_counter()
     i = done = 0
+    next_note = 10.0
     while done < n:
         now = time.perf_counter() - t_start
         while i < n and arrivals[i] <= now:
@@ -584,9 +608,13 @@ def served_workload(args, km, synth, torch):
                 done += 1
         if backlog_at_end is None and i == n:
             backlog_at_end = n - done
+        if now >= next_note:
+            print(f"served: t={now:.0f} s, {i} arrived, {done} done", file=sys.stderr, flush=True)
+            next_note += 10.0
         if busy == 0 and i < n:
             time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t_start))))
     t_served = time.perf_counter() - t_start
+    print(f"served: {n} jobs in {t_served:.1f} s", file=sys.stderr, flush=True)
     for e in engines:
         e.close()
     # served results against the float64 oracle (a few small jobs; their data
@@ -605,7 +633,11 @@ def served_workload(args, km, synth, torch):
     fin = 0.0
     base_lat = []
     busy = 0.0
+    print(f"served: {len(keep)} results checked against the oracle, {o_mism} mismatched; "
+          "FIFO baseline next", file=sys.stderr, flush=True)
     for j in range(n):
+        if j % 2000 == 0:
+            print(f"FIFO baseline: job {j} of {n}", file=sys.stderr, flush=True)
         X, C0 = make(j)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
