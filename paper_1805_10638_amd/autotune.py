@@ -13,7 +13,9 @@ Buckets: K rounds up to a power of two (at least 16) and d to the padded
 width of the kernel, exactly as km_set_tile_shape keys them.  The default
 bucket list covers the benchmark configurations: the batched mix (d in
 {3, 16, 64}, K from 8 to 512), d = 32 / K = 256 float32, d = 128 /
-K = 1024 and d = 96 / K = 2048 on bfloat16 rows.
+K = 1024 and d = 96 / K = 2048 on bfloat16 rows.  The d = 128 / K = 1024
+buckets are timed on the precision workload's own data (4M bfloat16 rows of
+512 Gaussian clusters with 5 % outliers), the others on Gaussian mixtures.
 """
 
 from __future__ import annotations
@@ -29,12 +31,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tiles_gfx950.json")
 SHAPES = 4
 
-# (prec, xtype, d, K, rows)
+# (prec, xtype, d, K, rows, data): data "mixture" or "precision"
 DEFAULT_BUCKETS = (
-    [("f32", "f32", d, k, 200_000) for d in (3, 16, 64) for k in (16, 32, 64, 128, 256, 512)]
-    + [("f32", "f32", 32, 256, 1_000_000),
-       ("bf16", "bf16", 128, 1024, 1_000_000), ("f32", "bf16", 128, 1024, 1_000_000),
-       ("bf16", "bf16", 96, 2048, 500_000)]
+    [("f32", "f32", d, k, 200_000, "mixture") for d in (3, 16, 64) for k in (16, 32, 64, 128, 256, 512)]
+    + [("f32", "f32", 32, 256, 1_000_000, "mixture"),
+       ("bf16", "bf16", 128, 1024, 4_000_000, "precision"), ("f32", "bf16", 128, 1024, 4_000_000, "precision"),
+       ("bf16", "bf16", 96, 2048, 500_000, "mixture")]
 )
 
 
@@ -54,8 +56,13 @@ def apply_table(ctx, entries) -> int:
     return n
 
 
-def _data(rows, d, k, xtype, seed):
+def _data(rows, d, k, xtype, seed, kind="mixture"):
     from . import synth
+    if kind == "precision":   # bfloat16 rows by construction
+        x, _ = synth.precision(rep=1, n=rows, d=d, k=max(2, k // 2))
+        if xtype == "f32":
+            x = synth.bf16_bits_to_f32(x)
+        return x, synth.init_centroids(x, k, seed)
     x, _ = synth.plain_large(rep=seed, n=rows, d=d, k=max(2, k // 2), cfg=200)
     if xtype == "bf16":
         x = synth.to_bf16_bits(x)
@@ -68,9 +75,9 @@ def tune(buckets=DEFAULT_BUCKETS, reps=5, rows=None, log=print):
     ctx = _lib.Context(0, tuned=False)
     ctx.set_timing(True)
     out = []
-    for prec, xtype, d, k, n in buckets:
+    for prec, xtype, d, k, n, kind in buckets:
         n = rows or n
-        x, c0 = _data(n, d, k, xtype, seed=d * 1000 + k)
+        x, c0 = _data(n, d, k, xtype, seed=d * 1000 + k, kind=kind)
         X = torch.from_numpy(x.view(np.int16) if xtype == "bf16" else x).to("cuda")
         C = torch.from_numpy(c0).to("cuda")
         times, whole = [], []
@@ -89,7 +96,7 @@ def tune(buckets=DEFAULT_BUCKETS, reps=5, rows=None, log=print):
             whole.append(a.elapsed_time(b) * 1e3 / reps)
         best = int(np.argmin(times))
         ctx.set_tile_shape(prec, xtype, d, k, 0)
-        out.append({"prec": prec, "xtype": xtype, "d": d, "K": k, "rows": n, "shape": best,
+        out.append({"prec": prec, "xtype": xtype, "d": d, "K": k, "rows": n, "data": kind, "shape": best,
                     "assign_us": [round(t, 1) for t in times], "us_per_g": [round(t, 1) for t in whole]})
         log(json.dumps(out[-1]), flush=True)
         del X, C

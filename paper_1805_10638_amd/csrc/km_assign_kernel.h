@@ -542,6 +542,9 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   };
   auto stage = [&](auto bt, int c0, int rows) {
     constexpr int SBt = decltype(bt)::value;
+    // the first NT rows' -||c||^2/2, loaded before the row vectors so that
+    // its latency overlaps theirs
+    const float nc0 = tid < rows ? (c0 + tid < K ? -0.5f * a.nc[c0 + tid] : -__builtin_inff()) : 0.f;
     if constexpr (GBF) {
       const int64_t KD = (int64_t)K * d;
       constexpr int V = DP / 8;   // 8-element vectors per half row
@@ -581,7 +584,8 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     } else {
       stage_f32(bt, Cs, c0, rows);
     }
-    for (int rr = tid; rr < rows; rr += NT) {
+    if (tid < rows) ncs[tid] = nc0;
+    for (int rr = tid + NT; rr < rows; rr += NT) {
       const int j = c0 + rr;
       ncs[rr] = (j < K) ? -0.5f * a.nc[j] : -__builtin_inff();
     }
