@@ -135,9 +135,13 @@ __device__ __forceinline__ void load_rows(const void* X, const int64_t (&ic)[U],
     }
   }
   // other widths: one row at a time, which keeps the registers of the
-  // loads in flight to one row's
+  // loads in flight to one row's.  The wait at the end keeps these loads
+  // from being pending where the two paths join: the compiler would
+  // otherwise wait for every outstanding memory operation (the previous
+  // unit's label stores included) before the 16-byte path's first load.
 #pragma unroll
   for (int s = 0; s < U; ++s) load_chunk<KS, XBF>(X, ic[s], d, k0, false, out[s]);
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
 }
 
 // Wave reduction of per-lane (smallest distance bd, its index bj, second
@@ -542,9 +546,18 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
   };
   auto stage = [&](auto bt, int c0, int rows) {
     constexpr int SBt = decltype(bt)::value;
-    // the first NT rows' -||c||^2/2, loaded before the row vectors so that
-    // its latency overlaps theirs
-    const float nc0 = tid < rows ? (c0 + tid < K ? -0.5f * a.nc[c0 + tid] : -__builtin_inff()) : 0.f;
+    // bfloat16 pair chunks of bfloat16 rows from 64 dims (streamed per row
+    // group): the first NT rows' -||c||^2/2 are loaded before the row vectors
+    // so that its latency overlaps theirs (an unconditional load at a clamped
+    // index: a load inside a branch would be waited for before going on).
+    // Elsewhere the extra register would cost an occupancy step.
+    constexpr bool kNcEarly = GBF && XBF && KS >= 16;
+    const int jn = c0 + tid;
+    float nc0 = 0.f;
+    if constexpr (kNcEarly) {
+      const float ncv = a.nc[jn < K ? jn : K - 1];
+      nc0 = jn < K ? -0.5f * ncv : -__builtin_inff();
+    }
     if constexpr (GBF) {
       const int64_t KD = (int64_t)K * d;
       constexpr int V = DP / 8;   // 8-element vectors per half row
@@ -584,8 +597,10 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     } else {
       stage_f32(bt, Cs, c0, rows);
     }
-    if (tid < rows) ncs[tid] = nc0;
-    for (int rr = tid + NT; rr < rows; rr += NT) {
+    if constexpr (kNcEarly) {
+      if (tid < rows) ncs[tid] = nc0;
+    }
+    for (int rr = kNcEarly ? tid + NT : tid; rr < rows; rr += NT) {
       const int j = c0 + rr;
       ncs[rr] = (j < K) ? -0.5f * a.nc[j] : -__builtin_inff();
     }
@@ -870,6 +885,20 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       load_rows<U, KS, XBF>(a.X, ic, d, g * KS, vec, xv);
     }
 
+    // Previous labels (changed-row count): for units of 4 or more blocks of
+    // float32 rows they are loaded here, with the rows, so that the tile loop
+    // hides their latency (4 registers; smaller units would lose an occupancy
+    // step); otherwise at the start of the epilogue.
+    // Without previous labels this pass's own label buffer is read instead
+    // (the values are not used): no branch around the loads, which would
+    // make the compiler wait for them before going on.
+    constexpr bool kEarlyPrev = U >= 4 && !GBF;
+    int pv[U];
+    if constexpr (kEarlyPrev) {
+      const int* pvsrc = prev != nullptr ? prev : rho;
+#pragma unroll
+      for (int s = 0; s < U; ++s) pv[s] = pvsrc[ic[s]];
+    }
     float best[U], sec[U];
     int bidx[U];
 #pragma unroll
@@ -928,11 +957,10 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
     }
 
     // Epilogue: combine the 4 lane groups, flag near ties, exact energy terms.
-    // The previous labels (changed-row count) of all U blocks are loaded
-    // first, together, and used at the end.
-    int pv[U];
+    if constexpr (!kEarlyPrev) {   // all U blocks' previous labels together, used at the end
 #pragma unroll
-    for (int s = 0; s < U; ++s) pv[s] = prev != nullptr ? prev[ii[s] < a.N ? ii[s] : 0] : -1;
+      for (int s = 0; s < U; ++s) pv[s] = prev != nullptr ? prev[ic[s]] : -1;
+    }
     int bi_s[U];
     bool fl_s[U];
     double term_s[U];
