@@ -1086,16 +1086,22 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       if constexpr (BND) l2_s[s] = listed ? 0.0 : l2;
     }
 
+    // Changed labels of all blocks are counted before the first label
+    // store: a previous label compared after a store inside a branch makes
+    // the compiler wait for the outstanding stores (it cannot count them).
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+      const bool mine = ii[s] < a.N && g == 0 && !fl_s[s];
+      n_changed += (unsigned)__popcll(__ballot(mine && prev != nullptr && pv[s] != bi_s[s]));
+    }
     double e_lane = 0.0;
 #pragma unroll
     for (int s = 0; s < U; ++s) {
       const int64_t i = ii[s];
       const bool valid = i < a.N;
       const bool mine = valid && g == 0 && !fl_s[s];   // deferred rows are written later
-      bool ch = false;
       if (mine) {
         rho[i] = bi_s[s];
-        ch = (prev != nullptr) && (pv[s] != bi_s[s]);
         if constexpr (BND) {
           if (lbo) lbo[i] = sqrt_down(l2_s[s]);
         }
@@ -1103,7 +1109,6 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, int bx, int gx)
       if constexpr (BND) {   // listed rows get no bound (they are re-checked later)
         if (lbo && valid && g == 0 && fl_s[s]) lbo[i] = 0.f;
       }
-      n_changed += (unsigned)__popcll(__ballot(ch));
       n_gemm += (unsigned)__popcll(__ballot(valid && g == 0));
       e_lane += mine ? term_s[s] : 0.0;
     }
