@@ -32,7 +32,7 @@ WORKLOAD = dict(N=1_000_000, d=32, K=256, m_max=10, tol=1e-6, max_iter=500)
 # WRITE_SIZE, each scaled by its reading for a plain copy of known size
 # (profiles/assign_f32_N1M_d32_K256_traffic.md).  Set to None when the kernel
 # changes until it is measured again.
-TRAFFIC_BYTES_PER_LAUNCH = 137109169
+TRAFFIC_BYTES_PER_LAUNCH = 137474245
 
 
 def parse():
