@@ -57,7 +57,7 @@ int assign_list_mode(const AssignArgs& a) {
 RecheckArgs recheck_args(const AssignArgs& a, double* e_part) {
   const KernelPick p = assign_pick(a);
   RecheckArgs r{};
-  r.X = a.X; r.N = a.N; r.d = a.d; r.K = a.K; r.xbf16 = a.xbf16; r.C = a.C;
+  r.X = a.X; r.N = a.N; r.d = a.d; r.K = a.K; r.xbf16 = a.xbf16; r.C = a.C; r.nc = a.nc;
   r.lab = a.lab; r.lab_prev = a.lab_prev; r.flags = a.flags; r.fl_cnt = a.fl_cnt;
   r.grid = assign_grid(a);
   r.W = p.threads / 64;

@@ -205,6 +205,7 @@ struct RecheckArgs {
   int64_t N;
   int d, K, xbf16;
   const float* C;         // float32 centroids of the pass
+  const float* nc;        // their squared norms (float32, as in AssignArgs)
   int* lab;               // as in AssignArgs
   const int* lab_prev;
   const int* flags;       // the pass's per-wave lists (slot layout of the assignment launch)

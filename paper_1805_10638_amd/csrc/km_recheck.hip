@@ -7,14 +7,26 @@
 // the p-th row that wave owns) and writes the list lengths.  This kernel
 // numbers the listed rows in (workgroup, wave, position) order and takes them
 // in batches of kReRows (kReMR per wave), so that a few thousand listed rows
-// still spread over every CU.  A batch's rows are staged in LDS as float64;
-// the float32 centroids stream through LDS in chunks of 64 (one per lane) and
-// every chunk serves the whole batch.  For every listed row: float64 direct
-// differences to all K centroids, the lowest index among the smallest
-// distances, and the second smallest distance (near ties by the float64
-// definition are counted).  The energy terms of the rows are added in batch
-// and row order into one partial per workgroup, so the pass's energy does not
-// depend on timing.
+// still spread over every CU.  A batch's rows are staged in LDS as float64
+// and float32; the float32 centroids stream through LDS in chunks of 64 (one
+// per lane) and every chunk serves the whole batch.
+//
+// For every listed row the result is that of float64 direct differences to
+// all K centroids: the lowest index among the smallest distances, and the
+// second smallest distance (near ties by the float64 definition are counted).
+// The float64 distance is computed only for candidates: each lane first
+// scores its centroid in float32, s_j = x.c_j - ||c_j||^2 / 2 (dimensions in
+// order, one rounding per step), whose error is at most
+// B = gamma_{dp+2} (||x|| + max ||c||)^2 (plus an absolute term for
+// underflow); the squared distance is ||x||^2 - 2 s_j.  With M the largest
+// float32 score seen so far, every centroid scored below
+// M - 2B - 0.51e-6 (||x|| + max ||c||)^2 is farther than the best by more
+// than the near-tie margin, so it is neither the argmin nor a near tie and
+// its distance is not needed; the others get float64 distances (lanes split
+// the dimensions, then a fixed-order wave sum), taken in index order.
+// Non-finite scores or bounds make every centroid a candidate.  The energy
+// terms of the rows are added in batch and row order into one partial per
+// workgroup, so the pass's energy does not depend on timing.
 
 #include "km_assign_kernel.h"
 
@@ -41,8 +53,8 @@ __device__ __forceinline__ float4 ld_x4(const void* X, int64_t e, bool bf) {
 // LDS bytes of k_recheck for width d and an assignment grid of `grid`.
 size_t recheck_lds(int d, int grid) {
   const int dp = (d + 3) & ~3;
-  return (size_t)kReRows * dp * 8 + (size_t)kReRows * 8 + (size_t)kReCRows * (dp + 4) * 4 +
-         (size_t)kReRows * 4 + (size_t)kReWaves * 4 + (size_t)(grid + 1) * 4;
+  return (size_t)kReRows * dp * 8 + (size_t)kReRows * 8 + (size_t)kReRows * dp * 4 +
+         (size_t)kReCRows * (dp + 4) * 4 + (size_t)kReRows * 4 + (size_t)kReWaves * 4 + (size_t)(grid + 1) * 4;
 }
 
 __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
@@ -71,7 +83,8 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* xs = (double*)smem_raw;                            // kReRows x dp
   double* rowterm = xs + (size_t)kReRows * dp;               // kReRows
-  float* cc = (float*)(rowterm + kReRows);                   // kReCRows x (dp + 4)
+  float* xsf = (float*)(rowterm + kReRows);                  // kReRows x dp (float32 copies)
+  float* cc = xsf + (size_t)kReRows * dp;                    // kReCRows x (dp + 4)
   int* rowidx = (int*)(cc + (size_t)kReCRows * LDc);         // kReRows
   int* wsum = rowidx + kReRows;                              // kReWaves
   int* pre = wsum + kReWaves;                                // grid + 1
@@ -107,6 +120,26 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
   }
   const int F = pre[grid];
   const int nbatch = (F + kReRows - 1) / kReRows;
+  if (blockIdx.x >= nbatch) {   // no rows for this workgroup
+    if (tid == 0) r.e_part[blockIdx.x] = 0.0;
+    return;
+  }
+  // largest centroid norm (from the float32 squared norms, rounded up)
+  double cmax;
+  {
+    float mx = 0.f;
+    for (int j = tid; j < K; j += kReThreads) mx = fmaxf(mx, r.nc[j]);
+    mx = wave_max(mx);
+    __syncthreads();
+    if (lane == 0) wsum[wave] = __float_as_int(mx);
+    __syncthreads();
+    for (int w = 0; w < kReWaves; ++w) mx = fmaxf(mx, __int_as_float(wsum[w]));
+    cmax = sqrt((double)mx) * (1.0 + 1e-6);
+    __syncthreads();
+  }
+  // error bound factor of a float32 score of dp terms (two more roundings:
+  // the norm term and its float32 value)
+  const double gam = (double)(dp + 2) * 0x1p-24 / (1.0 - (double)(dp + 2) * 0x1p-24);
 
   double e_sum = 0.0;
   unsigned n_changed = 0, n_near = 0;
@@ -137,6 +170,7 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
         double2* dst = (double2*)(xs + (size_t)u * dp + k);
         dst[0] = make_double2(v.x, v.y);
         dst[1] = make_double2(v.z, v.w);
+        *(float4*)(xsf + (size_t)u * dp + k) = v;
       }
     } else {
       for (int e = tid; e < kReRows * dp; e += kReThreads) {
@@ -144,14 +178,30 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
         float v = 0.f;
         if (u < rb && k < d) v = ld_x(r.X, (int64_t)rowidx[u] * d + k, xbf);
         xs[e] = v;
+        xsf[e] = v;
       }
     }
     // rows wave * kReMR + m of the batch; centroid slot lane of each chunk
-    double bd[kReMR], bd2[kReMR];
+    const double* xw = xs + (size_t)(wave * kReMR) * dp;
+    const float* xwf = xsf + (size_t)(wave * kReMR) * dp;
+    __syncthreads();   // rows staged
+    // per row: the margin 2B + 0.51e-6 (||x|| + max||c||)^2 of the float32
+    // score test, the largest float32 score so far, and the float64 result
+    // (smallest distance, its index, second smallest; the same on all lanes)
+    double marg[kReMR], bd[kReMR], bd2[kReMR];
+    float smax[kReMR];
     int bj[kReMR];
 #pragma unroll
-    for (int m = 0; m < kReMR; ++m) { bd[m] = __builtin_inf(); bd2[m] = __builtin_inf(); bj[m] = -1; }
-    const double* xw = xs + (size_t)(wave * kReMR) * dp;
+    for (int m = 0; m < kReMR; ++m) {
+      double q = 0.0;
+      for (int k = lane; k < dp; k += kWave) q = fma(xw[m * dp + k], xw[m * dp + k], q);
+      const double nb = sqrt(wave_sum(q)) * (1.0 + 1e-12) + cmax;
+      marg[m] = 2.0 * (1.01 * gam * nb * nb + (double)(dp + 2) * 0x1p-125) + 0.51e-6 * nb * nb;
+      smax[m] = -__builtin_inff();
+      bd[m] = __builtin_inf();
+      bd2[m] = __builtin_inf();
+      bj[m] = -1;
+    }
     for (int c0 = 0; c0 < K; c0 += kReCRows) {
       const int rows = (K - c0) < kReCRows ? (K - c0) : kReCRows;
       __syncthreads();
@@ -176,44 +226,57 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
           cc[jj * LDc + k] = (jj < rows && k < d) ? r.C[(int64_t)(c0 + jj) * d + k] : 0.f;
         }
       }
+      const float ncj = lane < rows ? r.nc[c0 + lane] : 0.f;
       __syncthreads();
+      // float32 scores of this lane's centroid against the wave's rows
+      float sc[kReMR];
+#pragma unroll
+      for (int m = 0; m < kReMR; ++m) sc[m] = 0.f;
       if (lane < rows) {
         const float* cr = cc + lane * LDc;
-        double acc[kReMR];
-#pragma unroll
-        for (int m = 0; m < kReMR; ++m) acc[m] = 0.0;
-#pragma unroll 2
         for (int k = 0; k < dp; k += 4) {
           const float4 c4 = *(const float4*)(cr + k);
-          const double cx = c4.x, cy = c4.y, cz = c4.z, cw = c4.w;
 #pragma unroll
           for (int m = 0; m < kReMR; ++m) {
-            const double2 xa = *(const double2*)(xw + m * dp + k);
-            const double2 xb = *(const double2*)(xw + m * dp + k + 2);
-            double df = xa.x - cx; acc[m] = fma(df, df, acc[m]);
-            df = xa.y - cy; acc[m] = fma(df, df, acc[m]);
-            df = xb.x - cz; acc[m] = fma(df, df, acc[m]);
-            df = xb.y - cw; acc[m] = fma(df, df, acc[m]);
+            const float4 x4 = *(const float4*)(xwf + m * dp + k);
+            sc[m] = fmaf(x4.x, c4.x, sc[m]);
+            sc[m] = fmaf(x4.y, c4.y, sc[m]);
+            sc[m] = fmaf(x4.z, c4.z, sc[m]);
+            sc[m] = fmaf(x4.w, c4.w, sc[m]);
           }
         }
-        const int j = c0 + lane;
+      }
 #pragma unroll
-        for (int m = 0; m < kReMR; ++m) {
-          if (acc[m] < bd[m]) { bd2[m] = bd[m]; bd[m] = acc[m]; bj[m] = j; }
-          else bd2[m] = fmin(bd2[m], acc[m]);
+      for (int m = 0; m < kReMR; ++m) {
+        const float t = lane < rows ? fmaf(-0.5f, ncj, sc[m]) : -__builtin_inff();
+        smax[m] = fmaxf(smax[m], wave_max(t));
+        const double thr = (isfinite(smax[m]) && isfinite(marg[m])) ? (double)smax[m] - marg[m] : -__builtin_inf();
+        unsigned long long cand = __ballot(lane < rows && !((double)t < thr));
+        // candidates in index order: float64 distance, lanes split the dimensions
+        while (cand) {
+          const int jj = __ffsll((long long)cand) - 1;
+          cand &= cand - 1;
+          const float* cr = cc + jj * LDc;
+          double p = 0.0;
+          for (int k = lane; k < dp; k += kWave) {
+            const double df = xw[m * dp + k] - (double)cr[k];
+            p = fma(df, df, p);
+          }
+          const double dist = wave_sum(p);
+          if (dist < bd[m]) { bd2[m] = bd[m]; bd[m] = dist; bj[m] = c0 + jj; }
+          else bd2[m] = fmin(bd2[m], dist);
         }
       }
     }
 #pragma unroll
     for (int m = 0; m < kReMR; ++m) {
       const int u = wave * kReMR + m;
-      double dist, dist2;
-      const int j = wave_argmin2(bd[m], bd2[m], bj[m], &dist, &dist2);
       if (u < rb) {
+        const double dist = bd[m], dist2 = bd2[m];
         const bool nt = near_tie(dist, dist2);
         if (lane == 0) {
           const int i = rowidx[u];
-          const int jl = j >= 0 ? j : 0;
+          const int jl = bj[m] >= 0 ? bj[m] : 0;
           rho[i] = jl;
           if (prev != nullptr && prev[i] != jl) ++n_changed;
           if (nt) ++n_near;
