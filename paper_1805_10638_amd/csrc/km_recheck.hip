@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
       for (int m = 0; m < kReMR; ++m) sc[m] = 0.f;
       if (lane < rows) {
         const float* cr = cc + lane * LDc;
-        for (int k = 0; k < dp; k += 4) {
+#pragma unroll 4
+        for (int k = 0; k < dp; k += 4) {   // unrolled: the LDS loads of 4 steps in flight
           const float4 c4 = *(const float4*)(cr + k);
 #pragma unroll
           for (int m = 0; m < kReMR; ++m) {
