@@ -95,3 +95,26 @@ def test_stream_bf16_solve_matches_f32():
     assert a[3] == b[3]
     assert b[2] == pytest.approx(a[2], rel=1e-9)
     assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+
+
+@pytest.mark.parametrize("prec,K,scale,offset", [("bf16", 300, 1.0, 1000.0), ("f32", 1500, 1.0, 1000.0),
+                                                 ("bf16", 300, 1e-20, 0.0)])
+def test_recheck_filter_extremes(prec, K, scale, offset):
+    """The pass-wide re-check scores every centroid in float32 and computes
+    float64 distances only for those within its rigorous bound of the best;
+    every row must still get the float64 argmin and the float64 near-tie
+    count.  A large common offset makes the scores cancel (wide bound, many
+    candidates); values of 1e-20 make float32 products underflow (every
+    centroid stays a candidate).  A duplicated centroid adds exact ties.
+    f32 at K = 1500 streams the centroids, so its rows are listed too."""
+    km = _lib()
+    rng = np.random.default_rng(K)
+    N, d = 6000, 64
+    X = (offset + scale * rng.normal(size=(N, d))).astype(np.float32)
+    C = X[rng.choice(N, K, replace=False)].copy()
+    C[K - 1] = C[0]
+    rho, Cn, E, st = km.kmeans_g(x_tensor(X), dev(C), prec=prec)
+    r = check_g(X, C, rho.cpu().numpy(), Cn.cpu().numpy(), E)
+    assert st.recheck_rows > 0
+    assert r["mismatch"] <= r["near_ties"]
+    assert st.near_tie_rows == r["near_ties"]
