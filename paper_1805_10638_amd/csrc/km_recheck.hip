@@ -14,16 +14,19 @@
 // For every listed row the result is that of float64 direct differences to
 // all K centroids: the lowest index among the smallest distances, and the
 // second smallest distance (near ties by the float64 definition are counted).
-// The float64 distance is computed only for candidates: each lane first
-// scores its centroid in float32, s_j = x.c_j - ||c_j||^2 / 2 (dimensions in
-// order, one rounding per step), whose error is at most
-// B = gamma_{dp+2} (||x|| + max ||c||)^2 (plus an absolute term for
-// underflow); the squared distance is ||x||^2 - 2 s_j.  With M the largest
+// The float64 distance is computed only for candidates: each wave first
+// scores a 16-centroid tile of the chunk against the batch's 16 rows with
+// float32 MFMA, s_j = x.c_j - ||c_j||^2 / 2 (the assignment kernel's float32
+// tile product), whose error is at most B = gamma_{dp+3} (||x|| + max ||c||)^2
+// (plus an absolute term for underflow); the squared distance is
+// ||x||^2 - 2 s_j.  With M the largest
 // float32 score seen so far, every centroid scored below
 // M - 2B - 0.51e-6 (||x|| + max ||c||)^2 is farther than the best by more
 // than the near-tie margin, so it is neither the argmin nor a near tie and
 // its distance is not needed; the others get float64 distances (lanes split
-// the dimensions, then a fixed-order wave sum), taken in index order.
+// the dimensions, then a fixed-order wave sum).  The smallest distance with
+// the lowest index and the second smallest are kept per wave and row, then
+// merged over the waves.
 // Non-finite scores or bounds make every centroid a candidate.  The energy
 // terms of the rows are added in batch and row order into one partial per
 // workgroup, so the pass's energy does not depend on timing.
@@ -52,9 +55,11 @@ __device__ __forceinline__ float4 ld_x4(const void* X, int64_t e, bool bf) {
 
 // LDS bytes of k_recheck for width d and an assignment grid of `grid`.
 size_t recheck_lds(int d, int grid) {
-  const int dp = (d + 3) & ~3;
-  return (size_t)kReRows * dp * 8 + (size_t)kReRows * 8 + (size_t)kReRows * dp * 4 +
-         (size_t)kReCRows * (dp + 4) * 4 + (size_t)kReRows * 4 + (size_t)kReWaves * 4 + (size_t)(grid + 1) * 4;
+  const int dp = (d + 15) & ~15;
+  return (size_t)kReRows * dp * 8 + (size_t)kReRows * 8 + (size_t)kReRows * (dp + 4) * 4 +
+         (size_t)kReCRows * (dp + 4) * 4 + (size_t)kReCRows * 4 + (size_t)kReRows * 8 +
+         (size_t)kReWaves * kReRows * (8 + 8 + 4 + 4) + (size_t)kReRows * 4 + (size_t)kReWaves * 4 +
+         (size_t)(grid + 1) * 4;
 }
 
 __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
@@ -77,15 +82,23 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
   }
   const int slot = (r.role == kRoleFallback) ? 1 : 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int d = r.d, K = r.K, dp = (d + 3) & ~3, LDc = dp + 4;
+  // rows padded with zeros to dp (a multiple of 16: the MFMA tile takes dp / 4
+  // dimensions per lane group, four at a time); LDS row stride dp + 4
+  const int d = r.d, K = r.K, dp = (d + 15) & ~15, LDc = dp + 4;
   const int grid = r.grid;
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* xs = (double*)smem_raw;                            // kReRows x dp
   double* rowterm = xs + (size_t)kReRows * dp;               // kReRows
-  float* xsf = (float*)(rowterm + kReRows);                  // kReRows x dp (float32 copies)
-  float* cc = xsf + (size_t)kReRows * dp;                    // kReCRows x (dp + 4)
-  int* rowidx = (int*)(cc + (size_t)kReCRows * LDc);         // kReRows
+  float* xsf = (float*)(rowterm + kReRows);                  // kReRows x (dp + 4) (float32 copies)
+  float* cc = xsf + (size_t)kReRows * LDc;                   // kReCRows x (dp + 4)
+  float* ncc = cc + (size_t)kReCRows * LDc;                  // kReCRows: -||c||^2 / 2 of the chunk
+  double* margs = (double*)(ncc + kReCRows);                 // kReRows: margin of the score test
+  double* st_bd = margs + kReRows;                           // kReWaves x kReRows: smallest distance
+  double* st_bd2 = st_bd + kReWaves * kReRows;               //   second smallest
+  int* st_bj = (int*)(st_bd2 + kReWaves * kReRows);          //   index of the smallest
+  float* smx = (float*)(st_bj + kReWaves * kReRows);         // kReWaves x kReRows: tile maxima
+  int* rowidx = (int*)(smx + kReWaves * kReRows);            // kReRows
   int* wsum = rowidx + kReRows;                              // kReWaves
   int* pre = wsum + kReWaves;                                // grid + 1
 
@@ -137,9 +150,8 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
     cmax = sqrt((double)mx) * (1.0 + 1e-6);
     __syncthreads();
   }
-  // error bound factor of a float32 score of dp terms (two more roundings:
-  // the norm term and its float32 value)
-  const double gam = (double)(dp + 2) * 0x1p-24 / (1.0 - (double)(dp + 2) * 0x1p-24);
+  // error bound factor of a float32 MFMA score of dp terms and the start value
+  const double gam = (double)(dp + 3) * 0x1p-24 / (1.0 - (double)(dp + 3) * 0x1p-24);
 
   double e_sum = 0.0;
   unsigned n_changed = 0, n_near = 0;
@@ -161,16 +173,17 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
       rowidx[tid] = r.flags[own];
     }
     __syncthreads();
-    // the batch's rows as float64 (exact for float32 and bfloat16 storage),
-    // zero beyond d and rb; 16-byte loads when d is a multiple of 4
-    if (d == dp) {
+    // the batch's rows as float64 (exact for float32 and bfloat16 storage)
+    // and float32, zero beyond d and rb; 16-byte loads when d is a multiple of 4
+    if ((d & 3) == 0) {
       for (int e = tid; e < kReRows * q4; e += kReThreads) {
         const int u = e / q4, k = (e - u * q4) * 4;
-        const float4 v = (u < rb) ? ld_x4(r.X, (int64_t)rowidx[u] * d + k, xbf) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 v = (u < rb && k < d) ? ld_x4(r.X, (int64_t)rowidx[u] * d + k, xbf)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
         double2* dst = (double2*)(xs + (size_t)u * dp + k);
         dst[0] = make_double2(v.x, v.y);
         dst[1] = make_double2(v.z, v.w);
-        *(float4*)(xsf + (size_t)u * dp + k) = v;
+        *(float4*)(xsf + (size_t)u * LDc + k) = v;
       }
     } else {
       for (int e = tid; e < kReRows * dp; e += kReThreads) {
@@ -178,41 +191,41 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
         float v = 0.f;
         if (u < rb && k < d) v = ld_x(r.X, (int64_t)rowidx[u] * d + k, xbf);
         xs[e] = v;
-        xsf[e] = v;
+        xsf[(size_t)u * LDc + k] = v;
       }
     }
-    // rows wave * kReMR + m of the batch; centroid slot lane of each chunk
-    const double* xw = xs + (size_t)(wave * kReMR) * dp;
-    const float* xwf = xsf + (size_t)(wave * kReMR) * dp;
     __syncthreads();   // rows staged
-    // per row: the margin 2B + 0.51e-6 (||x|| + max||c||)^2 of the float32
-    // score test, the largest float32 score so far, and the float64 result
-    // (smallest distance, its index, second smallest; the same on all lanes)
-    double marg[kReMR], bd[kReMR], bd2[kReMR];
-    float smax[kReMR];
-    int bj[kReMR];
-#pragma unroll
-    for (int m = 0; m < kReMR; ++m) {
+    // per row: the margin 2B + 0.51e-6 (||x|| + max||c||)^2 of the score
+    // test; per wave and row: the float64 result so far
+    if (tid < kReRows) {
       double q = 0.0;
-      for (int k = lane; k < dp; k += kWave) q = fma(xw[m * dp + k], xw[m * dp + k], q);
-      const double nb = sqrt(wave_sum(q)) * (1.0 + 1e-12) + cmax;
-      marg[m] = 2.0 * (1.01 * gam * nb * nb + (double)(dp + 2) * 0x1p-125) + 0.51e-6 * nb * nb;
-      smax[m] = -__builtin_inff();
-      bd[m] = __builtin_inf();
-      bd2[m] = __builtin_inf();
-      bj[m] = -1;
+      for (int k = 0; k < dp; ++k) q = fma(xs[tid * dp + k], xs[tid * dp + k], q);
+      const double nb = sqrt(q) * (1.0 + 1e-12) + cmax;
+      margs[tid] = 2.0 * (1.01 * gam * nb * nb + (double)(dp + 3) * 0x1p-125) + 0.51e-6 * nb * nb;
     }
+    if (tid < kReWaves * kReRows) {
+      st_bd[tid] = __builtin_inf();
+      st_bd2[tid] = __builtin_inf();
+      st_bj[tid] = -1;
+    }
+    __syncthreads();
+    // this lane's tile position: centroid row 16 * wave + r16 (A operand),
+    // row r16 of the batch (B operand), dimensions g * KS ... g * KS + KS - 1
+    const int g = lane >> 4, r16 = lane & 15, KS = dp >> 2;
+    const float* brow = xsf + (size_t)r16 * LDc + g * KS;
+    const double marg = margs[r16];
+    float smax = -__builtin_inff();   // largest score of row r16 so far
     for (int c0 = 0; c0 < K; c0 += kReCRows) {
       const int rows = (K - c0) < kReCRows ? (K - c0) : kReCRows;
       __syncthreads();
-      if (d == dp) {   // 16-byte loads, kReBatch in flight per thread
+      if ((d & 3) == 0) {   // 16-byte loads, kReBatch in flight per thread
         for (int e0 = tid; e0 < kReCRows * q4; e0 += kReBatch * kReThreads) {
           float4 v[kReBatch];
 #pragma unroll
           for (int t = 0; t < kReBatch; ++t) {
             const int e = e0 + t * kReThreads, jj = e / q4, k = (e - jj * q4) * 4;
-            v[t] = (e < kReCRows * q4 && jj < rows) ? *(const float4*)(r.C + (int64_t)(c0 + jj) * d + k)
-                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+            v[t] = (e < kReCRows * q4 && jj < rows && k < d) ? *(const float4*)(r.C + (int64_t)(c0 + jj) * d + k)
+                                                             : make_float4(0.f, 0.f, 0.f, 0.f);
           }
 #pragma unroll
           for (int t = 0; t < kReBatch; ++t) {
@@ -226,64 +239,88 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
           cc[jj * LDc + k] = (jj < rows && k < d) ? r.C[(int64_t)(c0 + jj) * d + k] : 0.f;
         }
       }
-      const float ncj = lane < rows ? r.nc[c0 + lane] : 0.f;
+      if (tid < kReCRows) ncc[tid] = tid < rows ? -0.5f * r.nc[c0 + tid] : -__builtin_inff();
       __syncthreads();
-      // float32 scores of this lane's centroid against the wave's rows
-      float sc[kReMR];
-#pragma unroll
-      for (int m = 0; m < kReMR; ++m) sc[m] = 0.f;
-      if (lane < rows) {
-        const float* cr = cc + lane * LDc;
-#pragma unroll 4
-        for (int k = 0; k < dp; k += 4) {   // unrolled: the LDS loads of 4 steps in flight
-          const float4 c4 = *(const float4*)(cr + k);
-#pragma unroll
-          for (int m = 0; m < kReMR; ++m) {
-            const float4 x4 = *(const float4*)(xwf + m * dp + k);
-            sc[m] = fmaf(x4.x, c4.x, sc[m]);
-            sc[m] = fmaf(x4.y, c4.y, sc[m]);
-            sc[m] = fmaf(x4.z, c4.z, sc[m]);
-            sc[m] = fmaf(x4.w, c4.w, sc[m]);
-          }
-        }
+      // float32 scores of centroids 16 * wave + 4 g + i (i < 4) for row r16
+      const int jt = 16 * wave + 4 * g;
+      f32x4 acc = *(const f32x4*)(ncc + jt);
+      const float* arow = cc + (size_t)(16 * wave + r16) * LDc + g * KS;
+      for (int q = 0; q < KS; q += 4) {
+        const float4 a4 = *(const float4*)(arow + q);
+        const float4 b4 = *(const float4*)(brow + q);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc, 0, 0, 0);
       }
+      float t[4];
 #pragma unroll
-      for (int m = 0; m < kReMR; ++m) {
-        const float t = lane < rows ? fmaf(-0.5f, ncj, sc[m]) : -__builtin_inff();
-        smax[m] = fmaxf(smax[m], wave_max(t));
-        const double thr = (isfinite(smax[m]) && isfinite(marg[m])) ? (double)smax[m] - marg[m] : -__builtin_inf();
-        unsigned long long cand = __ballot(lane < rows && !((double)t < thr));
-        // candidates in index order: float64 distance, lanes split the dimensions
+      for (int i = 0; i < 4; ++i) t[i] = (jt + i < rows) ? acc[i] : -__builtin_inff();
+      // largest score of each row over the chunk: lane, lane groups, waves
+      float m = fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3]));
+      m = fmaxf(m, __shfl_xor(m, 16, kWave));
+      m = fmaxf(m, __shfl_xor(m, 32, kWave));
+      if (g == 0) smx[wave * kReRows + r16] = m;
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < kReWaves; ++w) smax = fmaxf(smax, smx[w * kReRows + r16]);
+      const double thr = (isfinite(smax) && isfinite(marg)) ? (double)smax - marg : -__builtin_inf();
+      // candidates: float64 distance, lanes split the dimensions; the wave's
+      // result for the row is updated by lane 0 (the same on every lane)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        unsigned long long cand = __ballot(r16 < rb && jt + i < rows && !((double)t[i] < thr));
         while (cand) {
-          const int jj = __ffsll((long long)cand) - 1;
+          const int l = __ffsll((long long)cand) - 1;
           cand &= cand - 1;
-          const float* cr = cc + jj * LDc;
+          const int u = l & 15, jj = 16 * wave + 4 * (l >> 4) + i;
+          const float* cr = cc + (size_t)jj * LDc;
           double p = 0.0;
           for (int k = lane; k < dp; k += kWave) {
-            const double df = xw[m * dp + k] - (double)cr[k];
+            const double df = xs[u * dp + k] - (double)cr[k];
             p = fma(df, df, p);
           }
           const double dist = wave_sum(p);
-          if (dist < bd[m]) { bd2[m] = bd[m]; bd[m] = dist; bj[m] = c0 + jj; }
-          else bd2[m] = fmin(bd2[m], dist);
+          if (lane == 0) {
+            const int o = wave * kReRows + u, j = c0 + jj;
+            const double b = st_bd[o];
+            if (dist < b || (dist == b && j < st_bj[o])) {
+              st_bd2[o] = fmin(st_bd2[o], b);
+              st_bd[o] = dist;
+              st_bj[o] = j;
+            } else {
+              st_bd2[o] = fmin(st_bd2[o], dist);
+            }
+          }
         }
       }
     }
-#pragma unroll
-    for (int m = 0; m < kReMR; ++m) {
-      const int u = wave * kReMR + m;
-      if (u < rb) {
-        const double dist = bd[m], dist2 = bd2[m];
-        const bool nt = near_tie(dist, dist2);
-        if (lane == 0) {
-          const int i = rowidx[u];
-          const int jl = bj[m] >= 0 ? bj[m] : 0;
-          rho[i] = jl;
-          if (prev != nullptr && prev[i] != jl) ++n_changed;
-          if (nt) ++n_near;
-          rowterm[u] = dist;
-        }
+    __syncthreads();
+    // merge the waves' results per row: lowest index among the smallest
+    // distances, second smallest distance
+    bool ch = false, nt = false;
+    if (tid < rb) {
+      double bd = st_bd[tid], bd2 = st_bd2[tid];
+      int bj = st_bj[tid];
+      for (int w = 1; w < kReWaves; ++w) {
+        const double ob = st_bd[w * kReRows + tid], ob2 = st_bd2[w * kReRows + tid];
+        const int oj = st_bj[w * kReRows + tid];
+        const bool take = (ob < bd) || (ob == bd && (unsigned)oj < (unsigned)bj);
+        const double hi = bd < ob ? ob : bd, lo2 = bd2 < ob2 ? bd2 : ob2;
+        bd2 = hi < lo2 ? hi : lo2;
+        bd = take ? ob : bd;
+        bj = take ? oj : bj;
       }
+      const int i = rowidx[tid];
+      const int jl = bj >= 0 ? bj : 0;
+      rho[i] = jl;
+      ch = (prev != nullptr) && (prev[i] != jl);
+      nt = near_tie(bd, bd2);
+      rowterm[tid] = bd;
+    }
+    if (wave == 0) {
+      n_changed += (unsigned)__popcll(__ballot(ch));
+      n_near += (unsigned)__popcll(__ballot(nt));
     }
     __syncthreads();
     if (tid == 0)
