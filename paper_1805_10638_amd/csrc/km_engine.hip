@@ -111,6 +111,9 @@ struct km_engine {
     size_t lds = 0;
   };
   std::vector<Bucket> it_buckets;
+  // pass-wide re-checks of the jobs whose assignment leaves listed rows
+  size_t o_rc = 0, o_rf = 0, o_rpre = 0, rl_lds = 0;
+  int n_rl = 0, rl_blocks = 0;
   size_t o_k1 = 0, o_k2 = 0, o_u = 0, o_upre[kUpdateKinds] = {}, o_fi = 0, o_fpre = 0, o_fxpre = 0, o_cb = 0, o_cpre = 0, o_ctls = 0;
   int ublocks[kUpdateKinds] = {}, fblocks = 0, fxblocks = 0, cblocks = 0, n_it = 0;
 
@@ -219,6 +222,8 @@ void init_ctl(km_engine* e, Job* j) {
 
 struct JobArgs {
   AssignArgs plain, cand, fb;
+  bool relist = false;    // candidate and fall-back rows the GEMM cannot decide go to a re-check launch
+  RecheckArgs rc, rf;
   UpdateArgs u;
   FinalizeArgs f_init, f_iter;
   CombineArgs c0, c1;
@@ -243,6 +248,30 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   r.fb = a;
   r.fb.C = w.C_fb; r.fb.nc = w.nc_fb; r.fb.Cb = gbf ? w.Cb_fb : nullptr;
   r.fb.delta = gbf ? w.del_fb : nullptr; r.fb.e_part = w.e_part + j->assign_blocks; r.fb.role = kRoleFallback;
+  // Kernels that defer undecided rows (bfloat16 GEMM, centroids streamed
+  // through LDS) leave them listed for one batched re-check per pass, as in
+  // kmeans_solve, instead of re-checking them inside the assignment: the
+  // re-check's float32 MFMA filter computes float64 distances for few
+  // centroids.  The energy partials of a pass are then the assignment's
+  // G and the re-check's kReGrid.
+  const int G = j->assign_blocks;
+  int n_part = G;
+  r.relist = (gbf || !j->pick.resident) && G <= kReMaxGrid;
+  if (r.relist) {
+    n_part = G + kReGrid;
+    r.cand.fl_cnt = w.fl_cnt;
+    r.fb.fl_cnt = w.fl_cnt;
+    r.fb.e_part = w.e_part + n_part;
+    RecheckArgs rr{};
+    rr.X = s.X; rr.N = s.N; rr.d = s.d; rr.K = s.K; rr.xbf16 = j->xbf;
+    rr.lab = w.labels; rr.lab_prev = nullptr; rr.flags = w.flags; rr.fl_cnt = w.fl_cnt;
+    rr.grid = G; rr.W = j->pick.threads / 64; rr.group_rows = j->pick.rows; rr.sb16 = j->pick.rows / rr.W;
+    rr.ctl = w.ctl;
+    r.rc = rr;
+    r.rc.C = w.C_cand; r.rc.nc = w.nc_cand; r.rc.e_part = w.e_part + G; r.rc.role = kRoleCand;
+    r.rf = rr;
+    r.rf.C = w.C_fb; r.rf.nc = w.nc_fb; r.rf.e_part = w.e_part + n_part + G; r.rf.role = kRoleFallback;
+  }
 
   UpdateArgs u{};
   u.X = s.X; u.N = s.N; u.d = s.d; u.K = s.K; u.xbf16 = j->xbf;
@@ -277,11 +306,11 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   r.c1.trace_rec = nullptr;
 
   CtlArgs k{};
-  k.ctl = w.ctl; k.e_part = w.e_part; k.n_part = j->assign_blocks; k.stage = 1;
+  k.ctl = w.ctl; k.e_part = w.e_part; k.n_part = n_part; k.stage = 1;
   k.tr.trace_C = nullptr; k.tr.trace_rec = nullptr; k.tr.C_cand = w.C_cand; k.tr.K = s.K; k.tr.d = s.d;
   r.k1 = k;
   r.k2 = k;
-  r.k2.e_part = w.e_part + j->assign_blocks; r.k2.stage = 2;
+  r.k2.e_part = w.e_part + n_part; r.k2.stage = 2;
 
   r.prep = PrepArgs{w.C_tmp, s.K, s.d, w.nc_tmp, gbf ? w.Cb_tmp : nullptr, gbf ? w.del_tmp : nullptr};
   return r;
@@ -346,10 +375,16 @@ km_status enqueue_iteration(km_engine* e, int p) {
   for (const auto& b : e->it_buckets)
     ENG_TRY(e, launch_assign_batch(b.pick, dptr<AssignArgs>(e, b.o_cand), dptr<int>(e, b.o_pre), b.n, b.blocks,
                                    b.lds, q), "batched assignment");
+  if (e->n_rl > 0)
+    ENG_TRY(e, launch_recheck_batch(dptr<RecheckArgs>(e, e->o_rc), dptr<int>(e, e->o_rpre), e->n_rl, e->rl_blocks,
+                                    e->rl_lds, q), "batched re-check");
   ENG_TRY(e, launch_controller_batch(dptr<CtlArgs>(e, e->o_k1), e->n_it, q), "batched controller");
   for (const auto& b : e->it_buckets)
     ENG_TRY(e, launch_assign_batch(b.pick, dptr<AssignArgs>(e, b.o_fb), dptr<int>(e, b.o_pre), b.n, b.blocks,
                                    b.lds, q), "batched assignment");
+  if (e->n_rl > 0)
+    ENG_TRY(e, launch_recheck_batch(dptr<RecheckArgs>(e, e->o_rf), dptr<int>(e, e->o_rpre), e->n_rl, e->rl_blocks,
+                                    e->rl_lds, q), "batched re-check");
   ENG_TRY(e, launch_controller_batch(dptr<CtlArgs>(e, e->o_k2), e->n_it, q), "batched controller");
   UpdateBatch ub;
   ub.tab = dptr<UpdateArgs>(e, e->o_u);
@@ -490,9 +525,18 @@ km_status rebuild(km_engine* e, bool drain) {
   std::vector<CombineArgs> ci;
   std::vector<int> cisz;
   std::vector<Ctl*> ctls;
+  std::vector<RecheckArgs> rcs, rfs;
+  std::vector<int> rlsz;
+  size_t rl_lds = 0;
   for (Job* j : all) {
     const JobArgs r = job_args(e, j);
     add_bucket(ib, j->pick, r.cand, &r.fb, j->assign_blocks);
+    if (r.relist) {
+      rcs.push_back(r.rc);
+      rfs.push_back(r.rf);
+      rlsz.push_back(kReGrid);
+      rl_lds = std::max(rl_lds, recheck_lds(j->spec.d, j->assign_blocks));
+    }
     k1.push_back(r.k1);
     k2.push_back(r.k2);
     iu.push_back(r.u);
@@ -514,6 +558,13 @@ km_status rebuild(km_engine* e, bool drain) {
     eb.n = (int)b.a.size();
     eb.lds = b.lds;
     e->it_buckets.push_back(eb);
+  }
+  e->n_rl = (int)rcs.size();
+  e->rl_lds = rl_lds;
+  if (e->n_rl > 0) {
+    e->o_rc = pk.add(rcs);
+    e->o_rf = pk.add(rfs);
+    e->o_rpre = pk.add(prefix_of(rlsz, &e->rl_blocks));
   }
   e->o_k1 = pk.add(k1);
   e->o_k2 = pk.add(k2);

@@ -222,6 +222,13 @@ int assign_list_mode(const AssignArgs& a);
 RecheckArgs recheck_args(const AssignArgs& a, double* e_part);
 // ev1 (nullable): takes the end time of the re-check's own dispatch
 hipError_t launch_recheck(const RecheckArgs& r, Role role, hipStream_t s, hipEvent_t ev1 = nullptr);
+// LDS bytes of a re-check launch for width d after an assignment grid of `grid`
+size_t recheck_lds(int d, int grid);
+// Batched re-check: tab (device) one RecheckArgs per instance (role set in
+// the entry), prefix (device, n + 1 entries) kReGrid workgroups each; lds =
+// the largest recheck_lds of the instances.
+hipError_t launch_recheck_batch(const RecheckArgs* tab, const int* prefix, int n, int blocks, size_t lds,
+                                hipStream_t s);
 
 // Plain energy reduction for stand-alone G(C): sum of partials in fixed order.
 hipError_t launch_reduce_energy(const double* e_part, int n, double* out, hipStream_t s);

@@ -62,7 +62,8 @@ size_t recheck_lds(int d, int grid) {
          (size_t)(grid + 1) * 4;
 }
 
-__global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
+// bx / gx: this workgroup's index and the workgroups of this instance
+__device__ __forceinline__ void recheck_body(const RecheckArgs& r, int bx, int gx) {
   Ctl* ctl = r.ctl;
   if (r.role != kRolePlain) {
     if (ctl->done) return;
@@ -133,8 +134,8 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
   }
   const int F = pre[grid];
   const int nbatch = (F + kReRows - 1) / kReRows;
-  if (blockIdx.x >= nbatch) {   // no rows for this workgroup
-    if (tid == 0) r.e_part[blockIdx.x] = 0.0;
+  if (bx >= nbatch) {   // no rows for this workgroup
+    if (tid == 0) r.e_part[bx] = 0.0;
     return;
   }
   // largest centroid norm (from the float32 squared norms, rounded up)
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
   unsigned n_changed = 0, n_near = 0;
   const int q4 = dp / 4;
   const bool xbf = r.xbf16 != 0;
-  for (int bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+  for (int bt = bx; bt < nbatch; bt += gx) {
     const int rb = (F - bt * kReRows) < kReRows ? (F - bt * kReRows) : kReRows;
     if (tid < rb) {   // listed row number f: its workgroup, wave, list position, slot
       const int f = bt * kReRows + tid;
@@ -330,7 +331,31 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) {
     if (n_changed) atomicAdd(&ctl->cnt_changed[slot], (unsigned long long)n_changed);
     if (n_near) atomicAdd(&ctl->cnt_near[slot], (unsigned long long)n_near);
   }
-  if (tid == 0) r.e_part[blockIdx.x] = e_sum;
+  if (tid == 0) r.e_part[bx] = e_sum;
+}
+
+__global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) { recheck_body(r, blockIdx.x, gridDim.x); }
+
+// Batched: every instance of the table gets kReGrid workgroups (prefix).
+__global__ __launch_bounds__(kReThreads) void k_recheck_batch(BatchRef<RecheckArgs> t) {
+  const int b = batch_find(t.prefix, t.n, blockIdx.x);
+  recheck_body(t.tab[b], blockIdx.x - t.prefix[b], t.prefix[b + 1] - t.prefix[b]);
+}
+
+hipError_t launch_recheck_batch(const RecheckArgs* tab, const int* prefix, int n, int blocks, size_t lds,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)&k_recheck_batch,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  clear_pending_error();
+  hipLaunchKernelGGL(k_recheck_batch, dim3(blocks), dim3(kReThreads), lds, s,
+                     BatchRef<RecheckArgs>{tab, prefix, n});
+  return hipGetLastError();
 }
 
 hipError_t launch_recheck(const RecheckArgs& a, Role role, hipStream_t s, hipEvent_t ev1) {
