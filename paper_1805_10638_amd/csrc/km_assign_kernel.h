@@ -1283,7 +1283,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(assign_w
 void k_assign_batch(BatchRef<AssignArgs> t) {
   const int b = batch_find(t.prefix, t.n, blockIdx.x);
   const int b0 = t.prefix[b];
-  assign_body<KS, SB, W, XBF, GBF, LB>(t.tab[b], blockIdx.x - b0, t.prefix[b + 1] - b0);
+  if constexpr (GBF && XBF && KS >= 16) {
+    // a copy of the instance's arguments: read through the table pointer,
+    // fields are loaded again after stores to global memory (the stores
+    // could alias the table); the other kernels keep the reference, where
+    // the copy's registers would cost an occupancy step or spill
+    const AssignArgs a = t.tab[b];
+    assign_body<KS, SB, W, XBF, GBF, LB>(a, blockIdx.x - b0, t.prefix[b + 1] - b0);
+  } else {
+    assign_body<KS, SB, W, XBF, GBF, LB>(t.tab[b], blockIdx.x - b0, t.prefix[b + 1] - b0);
+  }
 }
 
 // Host view of one kernel instantiation.

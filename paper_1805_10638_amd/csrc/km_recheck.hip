@@ -339,7 +339,8 @@ __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) { recheck
 // Batched: every instance of the table gets kReGrid workgroups (prefix).
 __global__ __launch_bounds__(kReThreads) void k_recheck_batch(BatchRef<RecheckArgs> t) {
   const int b = batch_find(t.prefix, t.n, blockIdx.x);
-  recheck_body(t.tab[b], blockIdx.x - t.prefix[b], t.prefix[b + 1] - t.prefix[b]);
+  const RecheckArgs r = t.tab[b];   // a copy: no reloads after stores that could alias the table
+  recheck_body(r, blockIdx.x - t.prefix[b], t.prefix[b + 1] - t.prefix[b]);
 }
 
 hipError_t launch_recheck_batch(const RecheckArgs* tab, const int* prefix, int n, int blocks, size_t lds,
