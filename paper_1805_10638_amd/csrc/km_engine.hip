@@ -223,6 +223,7 @@ void init_ctl(km_engine* e, Job* j) {
 struct JobArgs {
   AssignArgs plain, cand, fb;
   bool relist = false;    // candidate and fall-back rows the GEMM cannot decide go to a re-check launch
+  int rgrid = 0;          // workgroups of its re-check (and energy partials it adds)
   RecheckArgs rc, rf;
   UpdateArgs u;
   FinalizeArgs f_init, f_iter;
@@ -252,13 +253,15 @@ JobArgs job_args(const km_engine* e, const Job* j) {
   // through LDS) leave them listed for one batched re-check per pass, as in
   // kmeans_solve, instead of re-checking them inside the assignment: the
   // re-check's float32 MFMA filter computes float64 distances for few
-  // centroids.  The energy partials of a pass are then the assignment's
-  // G and the re-check's kReGrid.
+  // centroids.  The re-check gets a workgroup per 4096 rows (8 to kReGrid),
+  // and the energy partials of a pass are the assignment's G and its rgrid.
   const int G = j->assign_blocks;
   int n_part = G;
   r.relist = (gbf || !j->pick.resident) && G <= kReMaxGrid;
   if (r.relist) {
-    n_part = G + kReGrid;
+    const int64_t rg = s.N / 4096;
+    r.rgrid = rg < 8 ? 8 : (rg > kReGrid ? kReGrid : (int)rg);
+    n_part = G + r.rgrid;
     r.cand.fl_cnt = w.fl_cnt;
     r.fb.fl_cnt = w.fl_cnt;
     r.fb.e_part = w.e_part + n_part;
@@ -534,7 +537,7 @@ km_status rebuild(km_engine* e, bool drain) {
     if (r.relist) {
       rcs.push_back(r.rc);
       rfs.push_back(r.rf);
-      rlsz.push_back(kReGrid);
+      rlsz.push_back(r.rgrid);
       rl_lds = std::max(rl_lds, recheck_lds(j->spec.d, j->assign_blocks));
     }
     k1.push_back(r.k1);

@@ -225,8 +225,9 @@ hipError_t launch_recheck(const RecheckArgs& r, Role role, hipStream_t s, hipEve
 // LDS bytes of a re-check launch for width d after an assignment grid of `grid`
 size_t recheck_lds(int d, int grid);
 // Batched re-check: tab (device) one RecheckArgs per instance (role set in
-// the entry), prefix (device, n + 1 entries) kReGrid workgroups each; lds =
-// the largest recheck_lds of the instances.
+// the entry), prefix (device, n + 1 entries) its workgroups (at most
+// kReGrid; e_part of an instance holds that many partials); lds = the
+// largest recheck_lds of the instances.
 hipError_t launch_recheck_batch(const RecheckArgs* tab, const int* prefix, int n, int blocks, size_t lds,
                                 hipStream_t s);
 

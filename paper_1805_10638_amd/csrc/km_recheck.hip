@@ -336,7 +336,7 @@ __device__ __forceinline__ void recheck_body(const RecheckArgs& r, int bx, int g
 
 __global__ __launch_bounds__(kReThreads) void k_recheck(RecheckArgs r) { recheck_body(r, blockIdx.x, gridDim.x); }
 
-// Batched: every instance of the table gets kReGrid workgroups (prefix).
+// Batched: instance b gets prefix[b + 1] - prefix[b] workgroups.
 __global__ __launch_bounds__(kReThreads) void k_recheck_batch(BatchRef<RecheckArgs> t) {
   const int b = batch_find(t.prefix, t.n, blockIdx.x);
   const RecheckArgs r = t.tab[b];   // a copy: no reloads after stores that could alias the table
