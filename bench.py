@@ -9,7 +9,7 @@ assigns every row through the distance GEMM).  X stays resident in HBM; the
 timed region holds K steps between two device synchronisations.  Prints one
 JSON line.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline] [--bounds 0|1]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-cpu-baseline] [--bounds 0|1]
 """
 
 from __future__ import annotations
@@ -38,7 +38,8 @@ TRAFFIC_BYTES_PER_LAUNCH = 137474245
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="solves timed (default workload: one seed each, seed = step index)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bounds", type=int, choices=[0, 1], default=1,
