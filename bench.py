@@ -28,11 +28,13 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOAD = dict(N=1_000_000, d=32, K=256, m_max=10, tol=1e-6, max_iter=500)
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# HBM bytes per launch of the assignment kernels from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by its reading for a plain copy of known size
-# (profiles/assign_f32_N1M_d32_K256_traffic.md).  Set to None when the kernel
-# changes until it is measured again.
+# (profiles/assign_f32_N1M_d32_K256_traffic.md): the dense pass (every row
+# through the GEMM) and the mean over the candidate launches of a solve with
+# row bounds.  Set to None when the kernel changes until it is measured again.
 TRAFFIC_BYTES_PER_LAUNCH = 137474245
+TRAFFIC_BYTES_PER_LAUNCH_BND = 181306566
 
 
 def parse():
@@ -247,7 +249,7 @@ def main():
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-            "traffic": TRAFFIC_BYTES_PER_LAUNCH if not args.bounds else None,
+            "traffic": TRAFFIC_BYTES_PER_LAUNCH_BND if args.bounds else TRAFFIC_BYTES_PER_LAUNCH,
             "avg_launch_us": avg_assign_s * 1e6,
             "launches": assign_n,
             "flop_per_launch": flops,
