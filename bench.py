@@ -9,7 +9,7 @@ assigns every row through the distance GEMM).  X stays resident in HBM; the
 timed region holds K steps between two device synchronisations.  Prints one
 JSON line.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-cpu-baseline] [--bounds 0|1]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-cpu-baseline | --cpu-full-solve] [--bounds 0|1]
 """
 
 from __future__ import annotations
@@ -44,6 +44,10 @@ def parse():
                     help="solves timed (default workload: one seed each, seed = step index)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full-solve", nargs="?", const="f64", choices=["f64", "f32"], default=None,
+                    help="default workload: the CPU baseline is one complete oracle solve from the first "
+                         "timed seed's starting centroids (minutes) instead of one timed oracle pass; f32: "
+                         "the oracle stores its iterates in float32 as the GPU does")
     ap.add_argument("--bounds", type=int, choices=[0, 1], default=1,
                     help="default workload: keep row bounds (Hamerly's lower bound, the assignment method of "
                          "the paper's experiments; KM_FLAG_BOUNDS) and skip the distance GEMM for rows they "
@@ -102,6 +106,42 @@ def cpu_baseline(X, C0, passes_per_solve, budget_s):
                    f"about {pass_s * passes_per_solve / 60:.0f} min); single-threaded NumPy on a host with "
                    f"{threads} visible cores"),
         "dist_evals_per_s": rows * C0.shape[0] / dt,
+    }
+
+
+def cpu_full_solve(X, C0, w, seed, gpu_iters, gpu_passes, gpu_E, stored32=False):
+    """Time one complete solve of the FP64 oracle (Algorithm 1) from the
+    starting centroids of one timed GPU solve; one progress line per
+    iteration on stderr.  stored32: the oracle keeps its iterates (the
+    fall-back G and every candidate) as float32 values, as the GPU stores
+    them; its arithmetic stays float64."""
+    from oracle import kmeans_oracle as ko
+    t0 = time.perf_counter()
+
+    def progress(t):   # called at the start of each iteration; keeps the oracle's own iterate
+        print(f"oracle solve, seed {seed}: iteration {t} at {time.perf_counter() - t0:.0f} s",
+              file=sys.stderr, flush=True)
+        return None
+
+    f32 = (lambda A: A.astype(np.float32).astype(np.float64)) if stored32 else None
+    r = ko.solve(X.astype(np.float64), C0.astype(np.float64), m_max=w["m_max"], tol=w["tol"],
+                 max_iter=w["max_iter"], replay=progress, stored=f32, stored_cand=f32)
+    dt = time.perf_counter() - t0
+    return {
+        "value": 1.0 / dt,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one complete oracle solve (float64 direct differences, single-threaded NumPy"
+                   f"{', iterates stored as float32' if stored32 else ''}) from the "
+                   f"starting centroids of seed {seed}: {r.iters} iterations, {r.assign_passes} assignment "
+                   f"passes in {dt:.1f} s; the GPU's solve of the same seed: {gpu_iters} iterations, "
+                   f"{gpu_passes} passes"),
+        "oracle_iters": r.iters,
+        "oracle_passes": r.assign_passes,
+        "gpu_iters": gpu_iters,
+        "gpu_passes": gpu_passes,
+        "energy_rel_diff": abs(gpu_E - r.E) / abs(r.E) if r.E else None,
     }
 
 
@@ -167,6 +207,8 @@ def main():
         ts = time.perf_counter()
         _, _, E, it, st = solve(inits[s])
         lat.append(time.perf_counter() - ts)
+        if s == args.warmup:
+            first = (it, st.assign_passes, E)
         iters.append(it)
         passes.append(st.assign_passes)
         acc.append(st.accepted)
@@ -258,7 +300,10 @@ def main():
     }
     if dense is not None:
         out["roofline_dense"] = dense
-    if not args.no_cpu_baseline:
+    if args.cpu_full_solve:
+        out["cpu_baseline"] = cpu_full_solve(X, synth.init_centroids(X, K, args.warmup), w, args.warmup, *first,
+                                             stored32=args.cpu_full_solve == "f32")
+    elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, synth.init_centroids(X, K, 0),
                                            statistics.mean(passes), args.cpu_seconds)
     print(json.dumps(out), flush=True)
